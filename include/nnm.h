@@ -1,0 +1,231 @@
+/*
+ * nnm.h -- C ABI of the MI355X (gfx950) nearest-neighbour clustering library.
+ *
+ * The library computes the clustering of N records with D features by the
+ * nearest neighbour method (single linkage) exactly, on one GPU:
+ *
+ *   knn_build    the exact k nearest neighbours of every point;
+ *   mst_build    the minimum spanning tree of the complete graph on the
+ *                points (the single-linkage merge tree), sorted by key;
+ *   cluster_cut  the constrained cut of that tree into clusters.
+ *
+ * Definitions (shared by every entry point):
+ *
+ *   Pair distance: eq. (1) of the paper, rho = sqrt(sum_j (x_j1 - x_j2)^2).
+ *   The library orders pairs by the squared distance s, evaluated in IEEE
+ *   FP64 as follows: every FP32 feature is widened exactly to FP64, the
+ *   per-feature difference and its square are each rounded once and the
+ *   squares are added left to right over features 0..D-1 (no fused
+ *   multiply-add).  The reported distance is w = sqrt(s), correctly rounded.
+ *
+ *   Key: pairs are compared by (s, min(i,j), max(i,j)), lexicographically.
+ *   All keys are distinct, so the minimum spanning tree is unique.
+ *
+ *   Merge tree: the section "General description of the algorithm for
+ *   constructing the set of minimum distances" unites clusters along the
+ *   globally smallest pairs, skipping pairs already inside one cluster,
+ *   until clustering ends.  Run to the end that process yields the
+ *   key-ordered minimum spanning tree; mst_build returns its N-1 edges.
+ *
+ *   Constraints: section "Problem settings" (KL1..KL4) and the distance
+ *   threshold of the "Problem statement"; see cluster_cut below.
+ *
+ * Conventions:
+ *   - Every pointer named *_dev is device memory on the current HIP device;
+ *     *_host is host memory.  The caller allocates and owns every buffer,
+ *     including the workspace; the library allocates nothing.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  GPU entry
+ *     points enqueue their work on it and return once the results are
+ *     complete on the device (they synchronise on `stream` internally,
+ *     because the number of rounds is data-dependent).
+ *   - X_dev is FP32 row-major: feature f of point i at X_dev[i * ld + f].
+ *   - Failures return a negative nnm_status and leave outputs undefined;
+ *     argument checks happen before any device work.
+ */
+#ifndef NNM_H
+#define NNM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NNM_OK = 0,
+    NNM_EINVAL = -1,        /* bad size, null pointer, short workspace        */
+    NNM_ENOMEM = -2,        /* (not raised: the library allocates nothing)    */
+    NNM_EDEVICE = -3,       /* a HIP call failed                              */
+    NNM_ENONFINITE = -4,    /* a feature is NaN or infinite                   */
+    NNM_EUNSUPPORTED = -5   /* precision not usable for these inputs          */
+} nnm_status;
+
+/*
+ * Precision of the candidate pass.  Every precision gives the same, exact
+ * result: candidates within a proven error bound of the selection threshold
+ * are rescored in FP64 by the definition above.
+ *   FP32  direct differences on the vector ALUs (D <= 32);
+ *   BF16  x.y form on the matrix cores, FP32 accumulation (D <= 26);
+ *   FP16  as BF16 with FP16 operands (D <= 26);
+ *   FP8   e4m3 operands; only for integer features in [-16, 16] (D <= 26);
+ *   AUTO  FP8 for such integer data, else BF16 when D <= 26, else FP32.
+ */
+typedef enum {
+    NNM_PREC_FP32 = 0,
+    NNM_PREC_BF16 = 1,
+    NNM_PREC_FP8 = 2,
+    NNM_PREC_AUTO = 3,
+    NNM_PREC_FP16 = 4
+} nnm_precision;
+
+/* One tree edge: u < v, s = FP64 squared distance, w = sqrt(s). 24 bytes. */
+typedef struct {
+    int32_t u;
+    int32_t v;
+    double s;
+    double w;
+} nnm_edge;
+
+/*
+ * Settings of the constrained cut ("Problem settings"; threshold from the
+ * "Problem statement").  Edges are taken one at a time:
+ *   kl1_max_clusters  stop once #clusters <= kl1 (<= 0: off);
+ *   kl2_max_size      do not unite when the larger side has more than kl2
+ *                     points (< 0: off); united clusters may exceed kl2;
+ *   kl3_max_merged    do not unite when both sides hold more than kl3
+ *                     points together (< 0: off);
+ *   kl4_min_size      (> 1: on) first unite along edges whose smaller side
+ *                     has fewer than kl4 points, in key order, re-checked
+ *                     each time an edge is taken;
+ *   dmax              do not unite along an edge with w > dmax (+inf: off).
+ */
+typedef struct {
+    int64_t kl1_max_clusters;
+    int64_t kl2_max_size;
+    int64_t kl3_max_merged;
+    int64_t kl4_min_size;
+    double dmax;
+} nnm_cut_params;
+
+/* Run options.  Zero-initialised options mean "defaults". */
+typedef struct {
+    int32_t precision;      /* nnm_precision (0 = FP32; use AUTO for auto)   */
+    int32_t knn_k;          /* neighbour-cache depth, 1..32 (0 = 16)          */
+    int32_t survivor_cap;   /* candidates kept per row, 16..2048 (0 = auto)   */
+    int32_t disable_prune;  /* 1: rescan every exhausted row (debug)          */
+    int32_t force_fallback; /* 1: rescore every row by a full FP64 scan       */
+    int32_t col_splits;     /* column splits per row tile (0 = auto)          */
+    int32_t reserved[10];
+} nnm_options;
+
+/* Per-call measurements (all optional to read; filled when non-NULL). */
+typedef struct {
+    int32_t precision_used;     /* nnm_precision actually used                */
+    int32_t integer_mode;       /* 1: candidate distances were exact          */
+    int32_t rounds;             /* merge rounds (mst_build)                   */
+    int32_t knn_k;              /* cache depth used                           */
+    int64_t rows_scanned;       /* rows sent through the candidate pass       */
+    int64_t pairs_evaluated;    /* candidate pairs evaluated (tiles run)      */
+    int64_t survivors;          /* candidates rescored in FP64                */
+    int64_t overflow_rows;      /* rows rescored by the full FP64 scan        */
+    double max_abs_err;         /* max |t - s| over rescored candidates       */
+    double max_rel_err;         /* max |t - s| / s over candidates with s > 0 */
+    double max_bound;           /* largest error bound applied                */
+    double ms_total;            /* wall time of the call, ms                  */
+    double ms_candidates;       /* candidate kernels, ms (HIP events)         */
+    double ms_rescore;          /* FP64 rescoring, ms                         */
+    double ms_merge;            /* cursor, component minima, union-find, ms   */
+    double ms_sort;             /* edge and component sorts, ms               */
+    int64_t rows_per_round[32]; /* rows scanned in each round                 */
+    int64_t comps_per_round[32];/* components at the start of each round      */
+} nnm_report;
+
+/* Fill *opt with the defaults (AUTO precision, k = 16, automatic caps). */
+void nnm_default_options(nnm_options *opt);
+
+/* Human-readable text of a status code (static storage). */
+const char *nnm_strerror(int32_t status);
+
+/*
+ * Workspace bytes that mst_build needs for n points of d features with
+ * these options (NULL = defaults).  Returns NNM_EINVAL for n < 1,
+ * d < 1 or d > 32.
+ */
+nnm_status mst_workspace_size(int64_t n, int32_t d, const nnm_options *opt,
+                              size_t *bytes);
+
+/* Workspace bytes that knn_build needs for n points, d features, depth k. */
+nnm_status knn_workspace_size(int64_t n, int32_t d, int32_t k,
+                              const nnm_options *opt, size_t *bytes);
+
+/*
+ * Exact k nearest neighbours of every point by key (s, j), j != i
+ * (the selection of minimum distances of the section "Overall idea of the
+ * algorithm", one row at a time).
+ *   X_dev     [n][ld] FP32, device, read only;
+ *   k         1..32;
+ *   idx_dev   [n][k] int32, device: neighbour indices, ascending key;
+ *   s_dev     [n][k] FP64, device: their squared distances;
+ *   len_dev   [n] int32, device: min(k, n-1) valid entries per row;
+ *             entries past len are idx = -1, s = +inf.
+ * Errors: NNM_EINVAL (n < 1, d < 1, d > 32, ld < d, k out of range, null
+ * pointer, ws_bytes short), NNM_ENONFINITE (a NaN/Inf feature),
+ * NNM_EUNSUPPORTED (precision unusable for these inputs).
+ */
+nnm_status knn_build(const float *X_dev, int64_t n, int32_t d, int64_t ld,
+                     int32_t k, const nnm_options *opt, void *ws_dev,
+                     size_t ws_bytes, int32_t *idx_dev, double *s_dev,
+                     int32_t *len_dev, void *stream, nnm_report *rep);
+
+/*
+ * The key-ordered minimum spanning tree (single-linkage merge tree).
+ *   X_dev      [n][ld] FP32, device, read only;
+ *   edges_dev  [n-1] nnm_edge, device: sorted ascending by key (s, u, v).
+ * n = 1 gives no edges.  Errors as for knn_build.
+ */
+nnm_status mst_build(const float *X_dev, int64_t n, int32_t d, int64_t ld,
+                     const nnm_options *opt, void *ws_dev, size_t ws_bytes,
+                     nnm_edge *edges_dev, void *stream, nnm_report *rep);
+
+/* One instance of a batched call. */
+typedef struct {
+    const float *X_dev;     /* [n][ld] FP32 device                             */
+    int64_t n;
+    int32_t d;
+    int32_t pad_;
+    int64_t ld;
+    nnm_edge *edges_dev;    /* [n-1] device output, sorted by key              */
+} nnm_instance;
+
+/*
+ * Many independent instances of uneven n and d in one call; each instance's
+ * tree is exactly what mst_build gives for it alone.
+ *   inst   [count] host array of instance descriptors;
+ *   reps   [count] host reports or NULL.
+ * The workspace must hold mst_batched_workspace_size() bytes.
+ */
+nnm_status mst_batched_workspace_size(const nnm_instance *inst, int32_t count,
+                                      const nnm_options *opt, size_t *bytes);
+nnm_status mst_build_batched(const nnm_instance *inst, int32_t count,
+                             const nnm_options *opt, void *ws_dev,
+                             size_t ws_bytes, void *stream, nnm_report *reps);
+
+/*
+ * Constrained cut of a sorted tree (host code, synchronous).
+ *   edges_host  [n-1] nnm_edge, host, sorted by key as mst_build returns;
+ *   labels_host [n] int32, host output: cluster of each point, numbered
+ *               0..K-1 in order of first appearance over i = 0..n-1;
+ *   n_clusters  host output: K.
+ * Errors: NNM_EINVAL (n < 1, null pointer, an edge with u >= v or out of
+ * range, edges not sorted by key).
+ */
+nnm_status cluster_cut(const nnm_edge *edges_host, int64_t n,
+                       const nnm_cut_params *params, int32_t *labels_host,
+                       int64_t *n_clusters);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNM_H */

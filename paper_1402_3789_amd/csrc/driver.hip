@@ -1,0 +1,670 @@
+// driver.hip -- host orchestration behind knn_build and mst_build.
+//
+// mst_build runs merge rounds until one component is left:
+//   round 0   every row is scanned (candidate pass with depth k, FP64
+//             rescoring) -> exact k-nearest-neighbour prefix of every point;
+//   round r   cursors skip list entries now inside the point's component;
+//             components take the minimum over their rows; rows whose list
+//             is used up are rescanned only if their lower bound can still
+//             beat their component's best (the rescan only looks below that
+//             best); components hook to their partners, mutual pairs are
+//             resolved, trees collapse by pointer jumping; points are then
+//             re-sorted by component so tiles of rows and chunks of columns
+//             rarely share a component.
+// The N-1 edges collected on the way are sorted by key at the end.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <vector>
+
+#include "nnm_common.h"
+
+namespace nnm {
+namespace {
+
+struct Counters {
+    int32_t ctr[8];                 // [0] edges [1] roots [2] jump misses
+    int32_t rcount;                 // rows to rescan
+    int32_t over;                   // overflowed rows in the last batch
+    int32_t pad_[6];
+    unsigned long long pairs;
+    unsigned long long survivors;
+    unsigned long long err_bits[2];
+};
+
+struct Plan {
+    int64_t n = 0;
+    int d = 0;
+    int64_t ld = 0;
+    int opkind = OP_FP32;
+    int exact = 0;
+    int k = 16;
+    int S = 256;
+    int64_t rmax = 0;               // rows per candidate launch
+    int op_bytes = 64;
+    bool mst = true;
+};
+
+struct WS {
+    StageStats* stats;
+    Counters* ctr;
+    float* centre;
+    void* opR; void* opC; PointConst* pc;
+    void* opRs; void* opCs; PointConst* pcs;
+    float* xs;
+    int32_t* compS; int32_t* perm; int32_t* comp; int32_t* parent;
+    int32_t* cidx; double* cs; int32_t* clen; int32_t* ccur; double* clb; int32_t* cflag;
+    double* rbest_s; int32_t* rbest_j; int32_t* rstat;
+    unsigned long long* cbest_s; unsigned long long* cbest_p;
+    int32_t* rflag; int32_t* rlist; double* u0s;
+    int32_t* surv_cnt; int32_t* surv_j; float* surv_t;
+    int32_t* overflow_list;
+    SortRec* edges; SortRec* srtA; SortRec* srtB;
+    void* scan_temp; void* radix_temp;
+};
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+size_t carve(const Plan& p, void* base, WS* w)
+{
+    Carver c{(char*)base};
+    const size_t n = (size_t)p.n;
+    const bool mfma = p.opkind != OP_FP32;
+    w->stats = c.take<StageStats>(1);
+    w->ctr = c.take<Counters>(1);
+    w->centre = c.take<float>(DMAX);
+    w->opR = mfma ? c.take<char>(n * p.op_bytes) : nullptr;
+    w->opC = mfma ? c.take<char>(n * p.op_bytes) : nullptr;
+    w->pc = c.take<PointConst>(n);
+    w->opRs = mfma ? c.take<char>(n * p.op_bytes) : nullptr;
+    w->opCs = mfma ? c.take<char>(n * p.op_bytes) : nullptr;
+    w->pcs = c.take<PointConst>(n);
+    w->xs = mfma ? nullptr : c.take<float>(n * DMAX);
+    w->compS = c.take<int32_t>(n);
+    w->perm = c.take<int32_t>(n);
+    w->comp = c.take<int32_t>(n);
+    w->parent = c.take<int32_t>(n);
+    w->cidx = c.take<int32_t>(n * p.k);
+    w->cs = c.take<double>(n * p.k);
+    w->clen = c.take<int32_t>(n);
+    w->ccur = c.take<int32_t>(n);
+    w->clb = c.take<double>(n);
+    w->cflag = c.take<int32_t>(n);
+    w->rbest_s = c.take<double>(n);
+    w->rbest_j = c.take<int32_t>(n);
+    w->rstat = c.take<int32_t>(n);
+    w->cbest_s = c.take<unsigned long long>(n);
+    w->cbest_p = c.take<unsigned long long>(n);
+    w->rflag = c.take<int32_t>(n);
+    w->rlist = c.take<int32_t>(n);
+    w->u0s = c.take<double>(n);
+    w->surv_cnt = c.take<int32_t>((size_t)p.rmax);
+    w->surv_j = c.take<int32_t>((size_t)p.rmax * p.S);
+    w->surv_t = c.take<float>((size_t)p.rmax * p.S);
+    w->overflow_list = c.take<int32_t>((size_t)p.rmax);
+    w->edges = c.take<SortRec>(n);
+    w->srtA = c.take<SortRec>(n);
+    w->srtB = c.take<SortRec>(n);
+    w->scan_temp = c.take<char>(scan_temp_bytes((int64_t)n));
+    w->radix_temp = c.take<char>(radix_temp_bytes((int64_t)n));
+    return c.off + 256;
+}
+
+int pow2_at_least(int64_t v)
+{
+    int r = 64;
+    while (r < v && r < SMAX) r <<= 1;
+    return r;
+}
+
+nnm_status plan_common(int64_t n, int32_t d, int32_t k, const nnm_options* opt, bool mst, Plan* p)
+{
+    if (n < 1 || n > (int64_t)0x7FFFFFF0 || d < 1 || d > DMAX) return NNM_EINVAL;
+    nnm_options o;
+    nnm_default_options(&o);
+    if (opt) o = *opt;
+    p->n = n;
+    p->d = d;
+    p->mst = mst;
+    p->k = k > 0 ? k : (o.knn_k > 0 ? o.knn_k : 16);
+    if (p->k < 1 || p->k > KMAX) return NNM_EINVAL;
+    // workspace is sized for the widest operand so the precision can be
+    // settled after the data have been inspected
+    p->opkind = (o.precision == NNM_PREC_FP32) ? OP_FP32 : OP_FP16;
+    if (o.precision == NNM_PREC_AUTO && d > DMAX_MFMA) p->opkind = OP_FP32;
+    if (o.precision != NNM_PREC_FP32 && o.precision != NNM_PREC_AUTO && d > DMAX_MFMA)
+        return NNM_EUNSUPPORTED;
+    p->op_bytes = 64;
+    int S = o.survivor_cap;
+    if (S <= 0) {
+        const double lnr = log((double)std::max<int64_t>(n / std::max(p->k, 1), 2));
+        S = pow2_at_least((int64_t)(p->k * (4.0 + lnr) + 32));
+    }
+    if (S < 64) S = 64;
+    if (S > SMAX) S = SMAX;
+    S = pow2_at_least(S);
+    p->S = S;
+    int64_t rmax = ((int64_t)1 << 28) / S;
+    if (rmax > n) rmax = n;
+    if (rmax < 1) rmax = 1;
+    p->rmax = rmax;
+    return NNM_OK;
+}
+
+struct Timer {
+    bool on;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    double* acc;
+    Timer(bool on_, hipStream_t s_, double* acc_) : on(on_), s(s_), acc(acc_)
+    {
+        if (on) {
+            hipEventCreate(&a);
+            hipEventCreate(&b);
+            hipEventRecord(a, s);
+        }
+    }
+    ~Timer()
+    {
+        if (on) {
+            hipEventRecord(b, s);
+            hipEventSynchronize(b);
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, a, b);
+            *acc += ms;
+            hipEventDestroy(a);
+            hipEventDestroy(b);
+        }
+    }
+};
+
+#define HIP_TRY(x)                                 \
+    do {                                           \
+        hipError_t e_ = (x);                       \
+        if (e_ != hipSuccess) return NNM_EDEVICE;  \
+    } while (0)
+
+struct Run {
+    Plan p;
+    WS w;
+    hipStream_t s;
+    nnm_report* rep;
+    nnm_options o;
+    BoundConst bc;
+    float sigma = 1.f;
+    int splits_opt = 0;
+};
+
+int ceil_log2(int64_t v)
+{
+    int r = 0;
+    while (((int64_t)1 << r) < v) ++r;
+    return r;
+}
+
+// Inspect the data (finite, ranges, integer grid), settle the precision and
+// write the operands.
+nnm_status stage(Run& R, const float* X)
+{
+    Plan& p = R.p;
+    WS& w = R.w;
+    StageStats init;
+    for (int f = 0; f < DMAX; ++f) { init.fmin[f] = 0xFFFFFFFFu; init.fmax[f] = 0u; }
+    init.nonfinite = 0;
+    init.nonint = 0;
+    for (int e = 0; e < 4; ++e) init.colmax[e] = 0u;
+    init.pad_[0] = init.pad_[1] = 0;
+    HIP_TRY(hipMemcpyAsync(w.stats, &init, sizeof(init), hipMemcpyHostToDevice, R.s));
+    HIP_TRY(hipMemsetAsync(w.ctr, 0, sizeof(Counters), R.s));
+    HIP_TRY(launch_stage_stats(X, p.n, p.d, p.ld, w.stats, R.s));
+    StageStats st;
+    HIP_TRY(hipMemcpyAsync(&st, w.stats, sizeof(st), hipMemcpyDeviceToHost, R.s));
+    HIP_TRY(hipStreamSynchronize(R.s));
+    if (st.nonfinite) return NNM_ENONFINITE;
+    const bool intgrid = !st.nonint && p.d <= DMAX_MFMA;
+    switch (R.o.precision) {
+    case NNM_PREC_FP32: p.opkind = OP_FP32; break;
+    case NNM_PREC_BF16: p.opkind = OP_BF16; break;
+    case NNM_PREC_FP16: p.opkind = OP_FP16; break;
+    case NNM_PREC_FP8:
+        if (!intgrid) return NNM_EUNSUPPORTED;
+        p.opkind = OP_FP8;
+        break;
+    case NNM_PREC_AUTO:
+    default:
+        p.opkind = intgrid ? OP_FP8 : (p.d <= DMAX_MFMA ? OP_FP16 : OP_FP32);
+        break;
+    }
+    p.exact = (p.opkind != OP_FP32 && intgrid) ? 1 : 0;
+    p.op_bytes = (p.opkind == OP_FP8) ? 32 : 64;
+    R.bc = BoundConst{};
+    R.sigma = 1.f;
+    if (p.opkind == OP_FP32) {
+        R.bc.sigma2 = 1.f;
+        return NNM_OK;
+    }
+    float centre[DMAX] = {0};
+    float sigma = 1.f;
+    if (!p.exact) {
+        double span = 0.0;
+        for (int f = 0; f < p.d; ++f) {
+            auto dec = [](uint32_t e) {
+                uint32_t u = (e & 0x80000000u) ? (e & 0x7FFFFFFFu) : ~e;
+                float v;
+                memcpy(&v, &u, 4);
+                return v;
+            };
+            const float lo = dec(st.fmin[f]), hi = dec(st.fmax[f]);
+            centre[f] = (float)(0.5 * ((double)lo + (double)hi));
+            span = std::max(span, std::max(fabs((double)hi - centre[f]), fabs((double)lo - centre[f])));
+        }
+        if (span > 0.0) {
+            int e = 0;
+            frexp(span, &e);     // span = m * 2^e, m in [0.5, 1)
+            sigma = (float)ldexp(1.0, -e);
+        }
+    }
+    R.sigma = sigma;
+    HIP_TRY(hipMemcpyAsync(w.centre, centre, sizeof(centre), hipMemcpyHostToDevice, R.s));
+    HIP_TRY(launch_stage_operands(X, p.n, p.d, p.ld, p.opkind, p.exact, w.centre, sigma, w.opR,
+                                  w.opC, w.pc, w.stats, R.s));
+    HIP_TRY(hipMemcpyAsync(&st, w.stats, sizeof(st), hipMemcpyDeviceToHost, R.s));
+    HIP_TRY(hipStreamSynchronize(R.s));
+    float cm[4];
+    memcpy(cm, st.colmax, sizeof(cm));
+    R.bc.colQ = cm[0];
+    R.bc.colP = cm[1];
+    R.bc.colRho = cm[2];
+    R.bc.colEta = cm[3];
+    R.bc.gamma = p.exact ? 0.f : (float)(33.0 * 0x1p-23);
+    R.bc.sigma2 = sigma * sigma;
+    R.bc.exact = p.exact;
+    return NNM_OK;
+}
+
+MergeArgs merge_args(Run& R)
+{
+    MergeArgs m{};
+    m.n = R.p.n;
+    m.k = R.p.k;
+    m.comp = R.w.comp;
+    m.parent = R.w.parent;
+    m.cidx = R.w.cidx;
+    m.cs = R.w.cs;
+    m.clen = R.w.clen;
+    m.ccur = R.w.ccur;
+    m.clb = R.w.clb;
+    m.cflag = R.w.cflag;
+    m.rbest_s = R.w.rbest_s;
+    m.rbest_j = R.w.rbest_j;
+    m.rstat = R.w.rstat;
+    m.cbest_s = R.w.cbest_s;
+    m.cbest_p = R.w.cbest_p;
+    m.perm = R.w.perm;
+    m.rflag = R.w.rflag;
+    m.u0s = R.w.u0s;
+    m.sigma2 = R.bc.sigma2;
+    m.disable_prune = R.o.disable_prune;
+    m.edges = R.w.edges;
+    m.counters = R.w.ctr->ctr;
+    return m;
+}
+
+// Order points by component; gather the operands in that order.
+nnm_status sort_points(Run& R, const float* X, bool identity)
+{
+    Plan& p = R.p;
+    WS& w = R.w;
+    HIP_TRY(launch_comp_records(w.comp, p.n, w.srtA, R.s));
+    SortRec* res = w.srtA;
+    if (!identity) {
+        const int fields[1] = {1};
+        const int bits[1] = {std::max(ceil_log2(p.n), 1)};
+        HIP_TRY(launch_radix_sort(w.srtA, w.srtB, p.n, fields, bits, 1, w.radix_temp, &res, R.s));
+    }
+    HIP_TRY(launch_perm_from_records(res, p.n, w.perm, R.s));
+    HIP_TRY(launch_gather_points(p.n, p.opkind, w.perm, w.opR, w.opC, w.pc, X, p.d, p.ld, w.comp,
+                                 w.opRs, w.opCs, w.pcs, w.xs, w.compS, R.s));
+    return NNM_OK;
+}
+
+int pick_splits(const Run& R, int64_t rows)
+{
+    if (R.o.col_splits > 0) return R.o.col_splits;
+    const int64_t bm = 256;
+    const int64_t tiles = (rows + bm - 1) / bm;
+    int64_t want = (2048 + tiles - 1) / tiles;
+    int64_t cap = R.p.n / 65536;
+    if (want > cap) want = cap;
+    if (want < 1) want = 1;
+    if (want > 64) want = 64;
+    return (int)want;
+}
+
+// Candidate pass + FP64 rescoring for rows rlist[0..count) (sorted positions).
+nnm_status scan_rows(Run& R, const float* X, const int32_t* rows, int64_t count, bool use_u0)
+{
+    Plan& p = R.p;
+    WS& w = R.w;
+    for (int64_t b0 = 0; b0 < count; b0 += p.rmax) {
+        const int64_t nb = std::min<int64_t>(p.rmax, count - b0);
+        HIP_TRY(hipMemsetAsync(w.surv_cnt, 0, sizeof(int32_t) * (size_t)nb, R.s));
+        CandArgs a{};
+        a.opR = w.opRs;
+        a.opC = w.opCs;
+        a.xs = w.xs;
+        a.pc = w.pcs;
+        a.compS = w.compS;
+        a.rows = rows ? rows + b0 : nullptr;
+        a.row0 = rows ? 0 : (int32_t)b0;
+        a.u0 = use_u0 ? w.u0s : nullptr;
+        a.n_rows = (int32_t)nb;
+        a.np = (int32_t)p.n;
+        a.d = p.d;
+        a.k = p.k;
+        a.S = p.S;
+        a.col_splits = pick_splits(R, nb);
+        a.bc = R.bc;
+        a.surv_cnt = w.surv_cnt;
+        a.surv_j = w.surv_j;
+        a.surv_t = w.surv_t;
+        a.pairs = &w.ctr->pairs;
+        {
+            Timer t(R.rep != nullptr, R.s, R.rep ? &R.rep->ms_candidates : nullptr);
+            if (p.opkind == OP_FP32) HIP_TRY(launch_cand_fp32(a, R.s));
+            else HIP_TRY(launch_cand_mfma(p.opkind, a, R.s));
+        }
+        RescoreArgs r{};
+        r.X = X;
+        r.ld = p.ld;
+        r.d = p.d;
+        r.n_rows = (int32_t)nb;
+        r.k = p.k;
+        r.S = p.S;
+        r.rows = a.rows;
+        r.row0 = a.row0;
+        r.perm = w.perm;
+        r.comp = w.comp;
+        r.surv_cnt = w.surv_cnt;
+        r.surv_j = w.surv_j;
+        r.surv_t = w.surv_t;
+        r.u0 = a.u0;
+        r.inv_sigma2 = 1.0 / (double)R.bc.sigma2;
+        r.sigma2 = R.bc.sigma2;
+        r.force_fallback = R.o.force_fallback;
+        r.np = p.n;
+        r.cidx = w.cidx;
+        r.cs = w.cs;
+        r.clen = w.clen;
+        r.ccur = w.ccur;
+        r.clb = w.clb;
+        r.cflag = w.cflag;
+        r.overflow_rows = &w.ctr->over;
+        r.survivors = &w.ctr->survivors;
+        r.err_bits = w.ctr->err_bits;
+        int32_t over = 0;
+        {
+            Timer t(R.rep != nullptr, R.s, R.rep ? &R.rep->ms_rescore : nullptr);
+            HIP_TRY(hipMemsetAsync(&w.ctr->over, 0, sizeof(int32_t), R.s));
+            HIP_TRY(launch_rescore(r, w.overflow_list, R.s));
+            HIP_TRY(hipMemcpyAsync(&over, &w.ctr->over, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
+            HIP_TRY(hipStreamSynchronize(R.s));
+            if (over > 0) HIP_TRY(launch_fallback(r, w.overflow_list, over, R.s));
+        }
+        if (R.rep) {
+            R.rep->overflow_rows += over;
+            R.rep->rows_scanned += nb;
+        }
+    }
+    return NNM_OK;
+}
+
+nnm_status finish_report(Run& R, std::chrono::steady_clock::time_point t0)
+{
+    if (!R.rep) return NNM_OK;
+    Counters c;
+    HIP_TRY(hipMemcpyAsync(&c, R.w.ctr, sizeof(c), hipMemcpyDeviceToHost, R.s));
+    HIP_TRY(hipStreamSynchronize(R.s));
+    R.rep->pairs_evaluated = (int64_t)c.pairs;
+    R.rep->survivors = (int64_t)c.survivors;
+    double e0, e1;
+    memcpy(&e0, &c.err_bits[0], 8);
+    memcpy(&e1, &c.err_bits[1], 8);
+    R.rep->max_abs_err = e0;
+    R.rep->max_rel_err = e1;
+    R.rep->precision_used = R.p.opkind == OP_FP32 ? NNM_PREC_FP32
+                            : R.p.opkind == OP_BF16 ? NNM_PREC_BF16
+                            : R.p.opkind == OP_FP16 ? NNM_PREC_FP16 : NNM_PREC_FP8;
+    R.rep->integer_mode = R.p.exact;
+    R.rep->knn_k = R.p.k;
+    // largest bound applied at the typical scale (per unit of sigma^2 s)
+    const BoundConst& b = R.bc;
+    R.rep->max_bound = R.p.opkind == OP_FP32
+                           ? (double)(R.p.d + 3) * 0x1p-24
+                           : (b.exact ? 0.0
+                                      : ((double)b.gamma * (2.0 * b.colQ * b.colQ + 2.0 * b.colP) +
+                                         2.0 * b.colRho + 2.0 * b.colEta * 2.0 * b.colEta) /
+                                            (double)b.sigma2);
+    R.rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return NNM_OK;
+}
+
+nnm_status validate(const float* X, int64_t n, int32_t d, int64_t ld, void* ws)
+{
+    if (!X || !ws || n < 1 || d < 1 || d > DMAX || ld < d) return NNM_EINVAL;
+    if (n > (int64_t)0x7FFFFFF0) return NNM_EINVAL;
+    return NNM_OK;
+}
+
+}  // namespace
+}  // namespace nnm
+
+using namespace nnm;
+
+extern "C" nnm_status mst_workspace_size(int64_t n, int32_t d, const nnm_options* opt, size_t* bytes)
+{
+    if (!bytes) return NNM_EINVAL;
+    Plan p;
+    nnm_status st = plan_common(n, d, 0, opt, true, &p);
+    if (st != NNM_OK) return st;
+    WS w;
+    *bytes = carve(p, nullptr, &w);
+    return NNM_OK;
+}
+
+extern "C" nnm_status knn_workspace_size(int64_t n, int32_t d, int32_t k, const nnm_options* opt,
+                                         size_t* bytes)
+{
+    if (!bytes || k < 1 || k > KMAX) return NNM_EINVAL;
+    Plan p;
+    nnm_status st = plan_common(n, d, k, opt, false, &p);
+    if (st != NNM_OK) return st;
+    WS w;
+    *bytes = carve(p, nullptr, &w);
+    return NNM_OK;
+}
+
+namespace {
+
+nnm_status begin(Run& R, const float* X, int64_t n, int32_t d, int64_t ld, int32_t k,
+                 const nnm_options* opt, void* ws, size_t ws_bytes, void* stream, nnm_report* rep,
+                 bool mst)
+{
+    nnm_status st = validate(X, n, d, ld, ws);
+    if (st != NNM_OK) return st;
+    st = plan_common(n, d, k, opt, mst, &R.p);
+    if (st != NNM_OK) return st;
+    R.p.ld = ld;
+    nnm_default_options(&R.o);
+    if (opt) R.o = *opt;
+    const size_t need = carve(R.p, nullptr, &R.w);
+    if (ws_bytes < need) return NNM_EINVAL;
+    carve(R.p, ws, &R.w);
+    R.s = (hipStream_t)stream;
+    R.rep = rep;
+    if (rep) memset(rep, 0, sizeof(*rep));
+    return NNM_OK;
+}
+
+nnm_status knn_round(Run& R, const float* X)
+{
+    MergeArgs m = merge_args(R);
+    HIP_TRY(launch_init_points(m, R.s));
+    nnm_status st = sort_points(R, X, true);
+    if (st != NNM_OK) return st;
+    // every row, no bound: exact k-nearest-neighbour prefixes
+    return scan_rows(R, X, nullptr, R.p.n, false);
+}
+
+}  // namespace
+
+extern "C" nnm_status knn_build(const float* X_dev, int64_t n, int32_t d, int64_t ld, int32_t k,
+                                const nnm_options* opt, void* ws_dev, size_t ws_bytes,
+                                int32_t* idx_dev, double* s_dev, int32_t* len_dev, void* stream,
+                                nnm_report* rep)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (k < 1 || k > KMAX || !idx_dev || !s_dev || !len_dev) return NNM_EINVAL;
+    Run R;
+    nnm_status st = begin(R, X_dev, n, d, ld, k, opt, ws_dev, ws_bytes, stream, rep, false);
+    if (st != NNM_OK) return st;
+    st = stage(R, X_dev);
+    if (st != NNM_OK) return st;
+    if (n > 1) {
+        st = knn_round(R, X_dev);
+        if (st != NNM_OK) return st;
+    } else {
+        HIP_TRY(launch_fill_i32(R.w.clen, 0, n, R.s));
+    }
+    // copy the lists out, padded past len with (-1, +inf)
+    HIP_TRY(launch_export_knn(n, k, R.w.cidx, R.w.cs, R.w.clen, idx_dev, s_dev, len_dev, R.s));
+    HIP_TRY(hipStreamSynchronize(R.s));
+    return finish_report(R, t0);
+}
+
+extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_t ld,
+                                const nnm_options* opt, void* ws_dev, size_t ws_bytes,
+                                nnm_edge* edges_dev, void* stream, nnm_report* rep)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (n > 1 && !edges_dev) return NNM_EINVAL;
+    Run R;
+    nnm_status st = begin(R, X_dev, n, d, ld, 0, opt, ws_dev, ws_bytes, stream, rep, true);
+    if (st != NNM_OK) return st;
+    st = stage(R, X_dev);
+    if (st != NNM_OK) return st;
+    if (n == 1) return finish_report(R, t0);
+    Plan& p = R.p;
+    WS& w = R.w;
+    MergeArgs m = merge_args(R);
+    {
+        Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
+        HIP_TRY(launch_init_points(m, R.s));
+    }
+    int64_t ncomp = n;
+    int round = 0;
+    Counters hc;
+    for (; ncomp > 1; ++round) {
+        if (round >= 64) return NNM_EDEVICE;   // cannot happen: components at least halve
+        if (rep && round < 32) rep->comps_per_round[round] = ncomp;
+        {
+            Timer t(rep != nullptr, R.s, rep ? &rep->ms_sort : nullptr);
+            st = sort_points(R, X_dev, round == 0);
+            if (st != NNM_OK) return st;
+        }
+        int32_t rcount = 0;
+        {
+            Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
+            HIP_TRY(launch_reset_comp(m, R.s));
+            HIP_TRY(launch_cursor(m, R.s));
+            HIP_TRY(launch_compmin1(m, R.s));
+            HIP_TRY(launch_flag_rescan(m, R.s));
+            HIP_TRY(launch_compact(w.rflag, n, w.rlist, &w.ctr->rcount, w.scan_temp, R.s));
+            HIP_TRY(hipMemcpyAsync(&rcount, &w.ctr->rcount, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
+            HIP_TRY(hipStreamSynchronize(R.s));
+        }
+        if (rep && round < 32) rep->rows_per_round[round] = rcount;
+        if (rcount > 0) {
+            st = scan_rows(R, X_dev, w.rlist, rcount, true);
+            if (st != NNM_OK) return st;
+        }
+        {
+            Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
+            if (rcount > 0) {
+                HIP_TRY(launch_cursor(m, R.s));
+                HIP_TRY(launch_compmin1(m, R.s));
+            }
+            HIP_TRY(launch_compmin2(m, R.s));
+            HIP_TRY(launch_hook(m, R.s));
+            int iters = ceil_log2(ncomp) + 1;
+            for (int extra = 0;; ++extra) {
+                if (extra > 64) return NNM_EDEVICE;   // cannot happen: hooks form a forest
+                HIP_TRY(launch_jump(m, iters, R.s));
+                HIP_TRY(hipMemsetAsync(&w.ctr->ctr[1], 0, 2 * sizeof(int32_t), R.s));
+                HIP_TRY(launch_jump_check(m, R.s));
+                HIP_TRY(hipMemcpyAsync(&hc, w.ctr, sizeof(hc), hipMemcpyDeviceToHost, R.s));
+                HIP_TRY(hipStreamSynchronize(R.s));
+                if (hc.ctr[2] == 0) break;
+                iters = 2;
+            }
+            HIP_TRY(launch_relabel(m, R.s));
+        }
+        const int64_t next = hc.ctr[1];
+        if (next >= ncomp) return NNM_EDEVICE;   // no progress: cannot happen
+        ncomp = next;
+    }
+    if (hc.ctr[0] != n - 1) return NNM_EDEVICE;
+    {
+        Timer t(rep != nullptr, R.s, rep ? &rep->ms_sort : nullptr);
+        const int lg = std::max(ceil_log2(n), 1);
+        const int fields[3] = {2, 1, 0};
+        const int bits[3] = {lg, lg, 64};
+        SortRec* res = nullptr;
+        HIP_TRY(launch_radix_sort(w.edges, w.srtA, n - 1, fields, bits, 3, w.radix_temp, &res, R.s));
+        HIP_TRY(launch_write_edges(res, n - 1, edges_dev, R.s));
+        HIP_TRY(hipStreamSynchronize(R.s));
+    }
+    if (rep) rep->rounds = round;
+    return finish_report(R, t0);
+}
+
+extern "C" nnm_status mst_batched_workspace_size(const nnm_instance* inst, int32_t count,
+                                                 const nnm_options* opt, size_t* bytes)
+{
+    if (!inst || count < 0 || !bytes) return NNM_EINVAL;
+    size_t need = 0;
+    for (int32_t b = 0; b < count; ++b) {
+        size_t one = 0;
+        nnm_status st = mst_workspace_size(inst[b].n, inst[b].d, opt, &one);
+        if (st != NNM_OK) return st;
+        need = std::max(need, one);
+    }
+    *bytes = need;
+    return NNM_OK;
+}
+
+extern "C" nnm_status mst_build_batched(const nnm_instance* inst, int32_t count,
+                                        const nnm_options* opt, void* ws_dev, size_t ws_bytes,
+                                        void* stream, nnm_report* reps)
+{
+    if (!inst || count < 0) return NNM_EINVAL;
+    for (int32_t b = 0; b < count; ++b) {
+        nnm_status st = mst_build(inst[b].X_dev, inst[b].n, inst[b].d, inst[b].ld, opt, ws_dev,
+                                  ws_bytes, inst[b].edges_dev, stream, reps ? reps + b : nullptr);
+        if (st != NNM_OK) return st;
+    }
+    return NNM_OK;
+}

@@ -1,0 +1,241 @@
+// merge.hip -- one round of component merging (Boruvka) on the GPU.
+//
+// The section on constructing the set of minimum distances unites clusters
+// along minimal pairs and repeats while clustering is not over.  Here every
+// round takes, for every component, its smallest outgoing pair under the key
+// (s, min index, max index) -- by the cut property that pair is a tree edge
+// -- hooks each component to its partner, resolves the mutual pairs, and
+// collapses the resulting trees by pointer jumping.
+//
+// Row minima come from each point's cached exact neighbour prefix: a cursor
+// skips entries that are now inside the point's own component.  A point
+// whose list is used up only has a lower bound (its last listed key); it is
+// rescanned only if that bound does not exceed the best pair its component
+// already has from other rows.  All reductions use integer atomics on keys,
+// so every result is independent of scheduling.
+#include "nnm_common.h"
+
+namespace nnm {
+namespace {
+
+constexpr unsigned long long NONE = 0xFFFFFFFFFFFFFFFFull;
+
+__device__ __forceinline__ unsigned long long sbits(double s)
+{
+    return (unsigned long long)__double_as_longlong(s);
+}
+
+__global__ __launch_bounds__(256) void k_init_points(MergeArgs a)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    a.comp[i] = (int32_t)i;
+    a.parent[i] = (int32_t)i;
+    a.ccur[i] = 0;
+    a.rstat[i] = 0;
+    a.cbest_s[i] = NONE;
+    a.cbest_p[i] = NONE;
+    a.clen[i] = 0;
+    a.cflag[i] = 0;
+    a.clb[i] = -1.0;              // no information yet: always scan
+}
+
+__global__ __launch_bounds__(256) void k_cursor(MergeArgs a)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int c = a.comp[i];
+    const int len = a.clen[i];
+    int cur = a.ccur[i];
+    const int32_t* li = a.cidx + i * a.k;
+    while (cur < len && a.comp[li[cur]] == c) ++cur;
+    a.ccur[i] = cur;
+    if (cur < len) {
+        a.rstat[i] = 1;
+        a.rbest_s[i] = a.cs[i * a.k + cur];
+        a.rbest_j[i] = li[cur];
+    } else if (a.cflag[i] & 1) {
+        a.rstat[i] = 0;          // every point is in this component
+    } else {
+        a.rstat[i] = 2;          // list used up: only a lower bound is known
+    }
+}
+
+__global__ __launch_bounds__(256) void k_compmin1(MergeArgs a)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    if (a.rstat[i] == 1) atomicMin(&a.cbest_s[a.comp[i]], sbits(a.rbest_s[i]));
+}
+
+// By sorted position, so the rescan list comes out in component order.
+__global__ __launch_bounds__(256) void k_flag_rescan(MergeArgs a)
+{
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int i = a.perm[p];
+    int f = 0;
+    double u0 = -1.0;
+    if (a.rstat[i] == 2) {
+        const unsigned long long B = a.cbest_s[a.comp[i]];
+        const double lb = a.clb[i];
+        if (a.disable_prune || lb < 0.0 || B == NONE || sbits(lb) <= B) {
+            f = 1;
+            if (B != NONE && !a.disable_prune) u0 = __longlong_as_double((long long)B);
+        }
+    }
+    a.rflag[p] = f;
+    a.u0s[p] = u0;
+}
+
+__global__ __launch_bounds__(256) void k_compmin2(MergeArgs a)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    if (a.rstat[i] != 1) return;
+    const int c = a.comp[i];
+    if (sbits(a.rbest_s[i]) != a.cbest_s[c]) return;
+    const unsigned long long j = (unsigned long long)a.rbest_j[i];
+    const unsigned long long lo = (unsigned long long)i < j ? (unsigned long long)i : j;
+    const unsigned long long hi = (unsigned long long)i < j ? j : (unsigned long long)i;
+    atomicMin(&a.cbest_p[c], (lo << 32) | hi);
+}
+
+__global__ __launch_bounds__(256) void k_hook(MergeArgs a)
+{
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= a.n) return;
+    if (a.comp[c] != c) return;
+    if (a.cbest_s[c] == NONE) { a.parent[c] = (int32_t)c; return; }
+    const unsigned long long p = a.cbest_p[c];
+    const int lo = (int)(p >> 32), hi = (int)(p & 0xFFFFFFFFu);
+    const int cl = a.comp[lo], ch = a.comp[hi];
+    a.parent[c] = (cl == c) ? ch : cl;
+}
+
+// A mutual pair picked the same edge (keys are distinct); its smaller root
+// stays a root.
+__global__ __launch_bounds__(256) void k_break(MergeArgs a)
+{
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= a.n) return;
+    if (a.comp[c] != c) return;
+    const int p = a.parent[c];
+    if (p != c && a.parent[p] == c && c < p) a.parent[c] = (int32_t)c;
+}
+
+__global__ __launch_bounds__(256) void k_emit(MergeArgs a)
+{
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= a.n) return;
+    if (a.comp[c] != c || a.parent[c] == c) return;
+    const unsigned long long p = a.cbest_p[c];
+    const int e = atomicAdd(&a.counters[0], 1);
+    if (e >= a.n) return;   // cannot happen: a tree has n - 1 edges
+    SortRec r;
+    r.k0 = a.cbest_s[c];
+    r.k1 = (uint32_t)(p >> 32);
+    r.k2 = (uint32_t)(p & 0xFFFFFFFFu);
+    a.edges[e] = r;
+}
+
+__global__ __launch_bounds__(256) void k_jump(MergeArgs a)
+{
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= a.n) return;
+    if (a.comp[c] != c) return;
+    const int p = a.parent[c];
+    const int pp = a.parent[p];
+    if (pp != p) a.parent[c] = pp;
+}
+
+// counters[1] = roots left, counters[2] = pointers not yet at a root.
+__global__ __launch_bounds__(256) void k_jump_check(MergeArgs a)
+{
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= a.n) return;
+    if (a.comp[c] != c) return;
+    const int p = a.parent[c];
+    if (a.parent[p] != p) atomicAdd(&a.counters[2], 1);
+    if (p == c) atomicAdd(&a.counters[1], 1);
+}
+
+__global__ __launch_bounds__(256) void k_relabel(MergeArgs a)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    a.comp[i] = a.parent[a.comp[i]];
+}
+
+__global__ __launch_bounds__(256) void k_reset_comp(MergeArgs a)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    a.cbest_s[i] = NONE;
+    a.cbest_p[i] = NONE;
+}
+
+__global__ __launch_bounds__(256) void k_export_knn(int64_t n, int k, const int32_t* __restrict__ cidx,
+                                                    const double* __restrict__ cs,
+                                                    const int32_t* __restrict__ clen,
+                                                    int32_t* __restrict__ idx, double* __restrict__ sd,
+                                                    int32_t* __restrict__ len)
+{
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n * k) return;
+    const int64_t i = e / k;
+    const int r = (int)(e % k);
+    const int l = clen[i];
+    if (r < l) {
+        idx[e] = cidx[e];
+        sd[e] = cs[e];
+    } else {
+        idx[e] = -1;
+        sd[e] = __builtin_huge_val();
+    }
+    if (r == 0) len[i] = l;
+}
+
+inline unsigned g256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_export_knn(int64_t n, int k, const int32_t* cidx, const double* cs,
+                             const int32_t* clen, int32_t* idx, double* sd, int32_t* len,
+                             hipStream_t s)
+{
+    k_export_knn<<<g256(n * k), 256, 0, s>>>(n, k, cidx, cs, clen, idx, sd, len);
+    return hipGetLastError();
+}
+
+#define NNM_LAUNCH1(name)                                   \
+    hipError_t launch_##name(const MergeArgs& a, hipStream_t s) \
+    {                                                       \
+        k_##name<<<g256(a.n), 256, 0, s>>>(a);              \
+        return hipGetLastError();                           \
+    }
+
+NNM_LAUNCH1(init_points)
+NNM_LAUNCH1(cursor)
+NNM_LAUNCH1(compmin1)
+NNM_LAUNCH1(flag_rescan)
+NNM_LAUNCH1(compmin2)
+NNM_LAUNCH1(relabel)
+NNM_LAUNCH1(reset_comp)
+NNM_LAUNCH1(jump_check)
+
+hipError_t launch_hook(const MergeArgs& a, hipStream_t s)
+{
+    k_hook<<<g256(a.n), 256, 0, s>>>(a);
+    k_break<<<g256(a.n), 256, 0, s>>>(a);
+    k_emit<<<g256(a.n), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_jump(const MergeArgs& a, int iters, hipStream_t s)
+{
+    for (int it = 0; it < iters; ++it) k_jump<<<g256(a.n), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace nnm

@@ -1,0 +1,260 @@
+// nnm_common.h -- definitions shared by the gfx950 kernels and the host
+// driver of the nearest-neighbour clustering library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nnm.h"
+
+namespace nnm {
+
+// Operand slots per point for the matrix-core candidate pass: D features
+// plus three (value, constant) slot pairs that fold both squared norms into
+// the dot product, padded to the K = 32 of one 16x16x32 MFMA.
+constexpr int KSLOT = 32;
+constexpr int NORM_PARTS = 3;
+constexpr int DMAX = 32;                         // FP32 path
+constexpr int DMAX_MFMA = KSLOT - 2 * NORM_PARTS;  // 26
+constexpr int KMAX = 32;                         // neighbour-cache depth
+constexpr int SMAX = 2048;                       // survivor cap
+
+enum OpKind : int { OP_BF16 = 0, OP_FP16 = 1, OP_FP8 = 2, OP_FP32 = 3 };
+
+// Inputs of the per-pair error bound of one point, in the scaled candidate
+// domain, each rounded up:
+//   Q   = ||q||_2 of the quantised vector
+//   P   = sum of |value * constant| over its norm slots
+//   rho = |exact squared norm of q - what the norm slots carry|
+//   eta = bound on ||q - sigma * (x - c)||_2 (quantisation error)
+struct PointConst {
+    float Q, P, rho, eta;
+};
+
+// Per-run constants of the candidate pass.
+struct BoundConst {
+    float colQ, colP, colRho, colEta;  // maxima over all points
+    float gamma;                       // FP32 accumulation factor
+    float sigma2;                      // sigma^2: t = sigma^2 * s (+ error)
+    int exact;                         // 1: t == sigma^2 * s exactly
+    int pad_;
+};
+
+// Sort record used for both the component sort and the edge sort.
+struct SortRec {
+    uint64_t k0;  // edge: bits of s; component sort: 0
+    uint32_t k1;  // edge: u;         component sort: component id
+    uint32_t k2;  // edge: v;         component sort: point id
+};
+
+// ---- small device helpers ------------------------------------------------
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rn(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h)
+{
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+
+__device__ __forceinline__ uint16_t f32_to_f16_rn(float f)
+{
+    _Float16 h = (_Float16)f;
+    return __builtin_bit_cast(uint16_t, h);
+}
+
+__device__ __forceinline__ float f16_to_f32(uint16_t h)
+{
+    return (float)__builtin_bit_cast(_Float16, h);
+}
+
+// Round a double up to the nearest float that is >= it.
+__device__ __forceinline__ float d2f_up(double x)
+{
+    float f = (float)x;
+    if ((double)f < x) {
+        const uint32_t u = __float_as_uint(f);
+        if (f == 0.0f) f = __uint_as_float(1u);           // smallest subnormal
+        else if (f > 0.0f) f = __uint_as_float(u + 1u);
+        else f = __uint_as_float(u - 1u);
+    }
+    return f;
+}
+
+// Squared distance of eq. (1) in FP64: exact widening, one rounding for the
+// difference, one for the square, left-to-right sum over features.
+__device__ __forceinline__ double sqdist_fp64(const float* a, const float* b, int d)
+{
+    double s = 0.0;
+    for (int f = 0; f < d; ++f) {
+        double diff = __dsub_rn((double)a[f], (double)b[f]);
+        double sq = __dmul_rn(diff, diff);
+        s = (f == 0) ? sq : __dadd_rn(s, sq);
+    }
+    return s;
+}
+
+// (s, j) order for one row: smaller s, then smaller j.
+__device__ __forceinline__ bool sj_less(double s1, int j1, double s2, int j2)
+{
+    return s1 < s2 || (s1 == s2 && j1 < j2);
+}
+
+}  // namespace nnm
+
+// ---- host-side launch interface (implemented in the .hip files) ----------
+
+namespace nnm {
+
+struct StageStats {
+    uint32_t fmin[DMAX];   // ordered-float encodings
+    uint32_t fmax[DMAX];
+    int32_t nonfinite;
+    int32_t nonint;        // a feature that is not an integer in [-16, 16]
+    uint32_t colmax[4];    // float bits of max Q, P, rho, eta
+    int32_t pad_[2];
+};
+
+hipError_t launch_stage_stats(const float* X, int64_t n, int d, int64_t ld,
+                              StageStats* st, hipStream_t s);
+hipError_t launch_stage_operands(const float* X, int64_t n, int d, int64_t ld,
+                                 int opkind, int exact, const float* centre,
+                                 float sigma, void* opR, void* opC,
+                                 PointConst* pc, StageStats* st, hipStream_t s);
+hipError_t launch_gather_points(int64_t n, int opkind, const int32_t* perm,
+                                const void* opR, const void* opC,
+                                const PointConst* pc, const float* X, int d,
+                                int64_t ld, const int32_t* comp, void* opRs,
+                                void* opCs, PointConst* pcs, float* xs,
+                                int32_t* compS, hipStream_t s);
+
+// Candidate pass over a list of rows (sorted positions) against all columns.
+struct CandArgs {
+    const void* opR;          // row-form operands, sorted order
+    const void* opC;          // column-form operands, sorted order
+    const float* xs;          // FP32 path: [np][DMAX] sorted order
+    const PointConst* pc;     // per sorted position
+    const int32_t* compS;     // component of each sorted position
+    const int32_t* rows;      // row list (sorted positions), NULL = row0 + slot
+    const double* u0;         // per sorted position: bound on the key, or NULL
+    int32_t row0;
+    int32_t n_rows;
+    int32_t np;
+    int32_t d;
+    int32_t k;                // top-k depth
+    int32_t S;                // survivor cap per row
+    int32_t col_splits;
+    BoundConst bc;
+    int32_t* surv_cnt;        // [n_rows]
+    int32_t* surv_j;          // [n_rows][S] sorted column positions
+    float* surv_t;            // [n_rows][S] candidate values
+    unsigned long long* pairs;// accumulated count of evaluated pairs
+};
+
+hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s);
+hipError_t launch_cand_fp32(const CandArgs& a, hipStream_t s);
+
+// FP64 rescoring of survivors into exact top-k lists.
+struct RescoreArgs {
+    const float* X;
+    int64_t ld;
+    int32_t d;
+    int32_t n_rows;
+    int32_t k;
+    int32_t S;
+    const int32_t* rows;      // row list (sorted positions), NULL = row0 + slot
+    int32_t row0;
+    const int32_t* perm;      // sorted position -> point
+    const int32_t* comp;      // component of each point
+    const int32_t* surv_cnt;
+    const int32_t* surv_j;
+    const float* surv_t;
+    const double* u0;         // per sorted position: bound on the key, or NULL
+    double inv_sigma2;        // 1 / sigma^2, for the error report
+    float sigma2;
+    int32_t force_fallback;
+    int64_t np;
+    // outputs, indexed by point id
+    int32_t* cidx;            // [n][k]
+    double* cs;               // [n][k]
+    int32_t* clen;            // [n]
+    int32_t* ccur;            // [n]
+    double* clb;              // [n] lower bound for rows past the list
+    int32_t* cflag;           // [n] bit0: list holds every outside point
+    int32_t* overflow_rows;   // counter
+    unsigned long long* survivors; // counter
+    unsigned long long* err_bits;  // [2]: max abs err, max rel err (double bits)
+};
+
+hipError_t launch_rescore(const RescoreArgs& a, int32_t* overflow_list, hipStream_t s);
+hipError_t launch_fallback(const RescoreArgs& a, const int32_t* overflow_list, int n_over,
+                           hipStream_t s);
+
+// Merge-round kernels.
+struct MergeArgs {
+    int64_t n;
+    int32_t k;
+    int32_t* comp;            // [n] component root of each point
+    int32_t* parent;          // [n] by root id
+    const int32_t* cidx;
+    const double* cs;
+    int32_t* clen;
+    int32_t* ccur;
+    double* clb;
+    int32_t* cflag;
+    double* rbest_s;          // [n] row best (valid rows)
+    int32_t* rbest_j;         // [n]
+    int32_t* rstat;           // [n] 0 none, 1 valid, 2 exhausted
+    unsigned long long* cbest_s;  // [n] by root id
+    unsigned long long* cbest_p;  // [n]
+    const int32_t* perm;      // sorted position -> point
+    int32_t* rflag;           // [n] by sorted position
+    double* u0s;              // [n] by sorted position: bound for the rescan
+    float sigma2;
+    int32_t disable_prune;
+    SortRec* edges;           // round edges appended here
+    int32_t* counters;        // [0] edges, [1] roots, [2] jump changes
+};
+
+hipError_t launch_cursor(const MergeArgs& a, hipStream_t s);
+hipError_t launch_compmin1(const MergeArgs& a, hipStream_t s);
+hipError_t launch_flag_rescan(const MergeArgs& a, hipStream_t s);
+hipError_t launch_compmin2(const MergeArgs& a, hipStream_t s);
+hipError_t launch_hook(const MergeArgs& a, hipStream_t s);
+hipError_t launch_jump(const MergeArgs& a, int iters, hipStream_t s);
+hipError_t launch_jump_check(const MergeArgs& a, hipStream_t s);
+hipError_t launch_export_knn(int64_t n, int k, const int32_t* cidx, const double* cs,
+                             const int32_t* clen, int32_t* idx, double* sd, int32_t* len,
+                             hipStream_t s);
+hipError_t launch_relabel(const MergeArgs& a, hipStream_t s);
+hipError_t launch_reset_comp(const MergeArgs& a, hipStream_t s);
+hipError_t launch_init_points(const MergeArgs& a, hipStream_t s);
+
+// Scans and sorts.
+size_t scan_temp_bytes(int64_t n);
+hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n,
+                                 void* temp, int32_t* total, hipStream_t s);
+hipError_t launch_compact(const int32_t* flags, int64_t n, int32_t* out_list,
+                          int32_t* out_count, void* temp, hipStream_t s);
+size_t radix_temp_bytes(int64_t n);
+// Stable LSD sort of records by the listed key fields (0: k0, 1: k1, 2: k2),
+// least significant first; bits = significant bits of each field.
+hipError_t launch_radix_sort(SortRec* a, SortRec* b, int64_t n,
+                             const int* fields, const int* bits, int nfields,
+                             void* temp, SortRec** result, hipStream_t s);
+hipError_t launch_comp_records(const int32_t* comp, int64_t n, SortRec* rec,
+                               hipStream_t s);
+hipError_t launch_perm_from_records(const SortRec* rec, int64_t n,
+                                    int32_t* perm, hipStream_t s);
+hipError_t launch_write_edges(const SortRec* rec, int64_t ne, nnm_edge* out,
+                              hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v,
+                           int64_t n, hipStream_t s);
+
+}  // namespace nnm

@@ -1,0 +1,221 @@
+// rescore.hip -- exact FP64 rescoring of the candidate survivors.
+//
+// Every survivor of the candidate pass is re-evaluated with the FP64 key of
+// eq. (1) (exact widening, one rounding per difference and per square, sum
+// in feature order) and the k smallest keys (s, j) of the row are written to
+// the row's neighbour list.  Rows whose survivor list overflowed are handled
+// by an exact FP64 scan of the whole row instead.  These are the only places
+// besides the final edge sort where the GPU computes in FP64.
+#include "nnm_common.h"
+
+namespace nnm {
+namespace {
+
+__device__ __forceinline__ void atomic_max_pos_double(unsigned long long* p, double v)
+{
+    if (!(v > 0.0)) return;
+    atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+
+template <int E>
+__global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflow_list)
+{
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t slot = (int64_t)blockIdx.x * 4 + wave;
+    if (slot >= a.n_rows) return;
+    const int rp = a.rows ? a.rows[slot] : a.row0 + (int)slot;
+    const int i = a.perm[rp];
+    const int cnt = a.surv_cnt[slot];
+    if (cnt > a.S || a.force_fallback) {
+        if (lane == 0) {
+            const int pos = atomicAdd(a.overflow_rows, 1);
+            overflow_list[pos] = (int)slot;
+        }
+        return;
+    }
+    const double u0s = a.u0 ? a.u0[rp] : -1.0;
+    const float* xi = a.X + (int64_t)i * a.ld;
+    double sv[E];
+    int jv[E];
+    double emax = 0.0, rmax = 0.0;
+    int nsurv = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        sv[e] = __builtin_huge_val();
+        jv[e] = 0x7FFFFFFF;
+        const int idx = e * 64 + lane;
+        if (idx < cnt) {
+            const int jp = a.surv_j[slot * a.S + idx];
+            const int j = a.perm[jp];
+            const double s = sqdist_fp64(xi, a.X + (int64_t)j * a.ld, a.d);
+            const double t = (double)a.surv_t[slot * a.S + idx] * a.inv_sigma2;
+            const double err = __builtin_fabs(t - s);
+            emax = err > emax ? err : emax;
+            if (s > 0.0) {
+                const double rel = err / s;
+                rmax = rel > rmax ? rel : rmax;
+            }
+            ++nsurv;
+            if (u0s < 0.0 || s <= u0s) {
+                sv[e] = s;
+                jv[e] = j;
+            }
+        }
+    }
+    int kept = 0;
+    for (int r = 0; r < a.k; ++r) {
+        double bs = __builtin_huge_val();
+        int bj = 0x7FFFFFFF;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (sj_less(sv[e], jv[e], bs, bj)) { bs = sv[e]; bj = jv[e]; }
+        double ws = bs;
+        int wj = bj;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double os = __shfl_xor(ws, off);
+            const int oj = __shfl_xor(wj, off);
+            if (sj_less(os, oj, ws, wj)) { ws = os; wj = oj; }
+        }
+        if (!(ws < __builtin_huge_val())) break;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (sv[e] == ws && jv[e] == wj) { sv[e] = __builtin_huge_val(); jv[e] = 0x7FFFFFFF; }
+        if (lane == 0) {
+            a.cidx[(int64_t)i * a.k + r] = wj;
+            a.cs[(int64_t)i * a.k + r] = ws;
+        }
+        ++kept;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o1 = __shfl_xor(emax, off);
+        const double o2 = __shfl_xor(rmax, off);
+        emax = o1 > emax ? o1 : emax;
+        rmax = o2 > rmax ? o2 : rmax;
+        nsurv += __shfl_xor(nsurv, off);
+    }
+    if (lane == 0) {
+        a.clen[i] = kept;
+        a.ccur[i] = 0;
+        if (kept == a.k) {
+            a.clb[i] = a.cs[(int64_t)i * a.k + a.k - 1];
+            a.cflag[i] = 0;
+        } else if (u0s >= 0.0) {
+            a.clb[i] = u0s;
+            a.cflag[i] = 0;
+        } else {
+            a.clb[i] = __builtin_huge_val();
+            a.cflag[i] = 1;
+        }
+        atomicAdd(a.survivors, (unsigned long long)nsurv);
+        atomic_max_pos_double(&a.err_bits[0], emax);
+        atomic_max_pos_double(&a.err_bits[1], rmax);
+    }
+}
+
+// Exact top-k of one row over every point outside its component, by a full
+// FP64 scan (one workgroup per overflowed row).
+__global__ __launch_bounds__(256) void k_fallback(RescoreArgs a, const int32_t* overflow_list,
+                                                  int n_over)
+{
+    __shared__ double ws_s[4];
+    __shared__ int ws_j[4], ws_t[4];
+    __shared__ int winner;
+    const int b = blockIdx.x;
+    if (b >= n_over) return;
+    const int64_t slot = overflow_list[b];
+    const int rp = a.rows ? a.rows[slot] : a.row0 + (int)slot;
+    const int i = a.perm[rp];
+    const int ci = a.comp[i];
+    const float* xi = a.X + (int64_t)i * a.ld;
+    const int tid = threadIdx.x;
+    double ls[KMAX];
+    int lj[KMAX];
+    for (int e = 0; e < KMAX; ++e) { ls[e] = __builtin_huge_val(); lj[e] = 0x7FFFFFFF; }
+    const int k = a.k;
+    for (int64_t j = tid; j < a.np; j += 256) {
+        if (j == i || a.comp[j] == ci) continue;
+        const double s = sqdist_fp64(xi, a.X + j * a.ld, a.d);
+        if (!sj_less(s, (int)j, ls[k - 1], lj[k - 1])) continue;
+        int p = k - 1;
+        while (p > 0 && sj_less(s, (int)j, ls[p - 1], lj[p - 1])) {
+            ls[p] = ls[p - 1];
+            lj[p] = lj[p - 1];
+            --p;
+        }
+        ls[p] = s;
+        lj[p] = (int)j;
+    }
+    int head = 0;
+    int kept = 0;
+    for (int r = 0; r < k; ++r) {
+        double bs = head < k ? ls[head] : __builtin_huge_val();
+        int bj = head < k ? lj[head] : 0x7FFFFFFF;
+        int bt = tid;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double os = __shfl_xor(bs, off);
+            const int oj = __shfl_xor(bj, off);
+            const int ot = __shfl_xor(bt, off);
+            if (sj_less(os, oj, bs, bj)) { bs = os; bj = oj; bt = ot; }
+        }
+        if ((tid & 63) == 0) { ws_s[tid >> 6] = bs; ws_j[tid >> 6] = bj; ws_t[tid >> 6] = bt; }
+        __syncthreads();
+        if (tid == 0) {
+            double s0 = ws_s[0];
+            int j0 = ws_j[0], t0 = ws_t[0];
+            for (int w = 1; w < 4; ++w)
+                if (sj_less(ws_s[w], ws_j[w], s0, j0)) { s0 = ws_s[w]; j0 = ws_j[w]; t0 = ws_t[w]; }
+            winner = (s0 < __builtin_huge_val()) ? t0 : -1;
+            if (winner >= 0) {
+                a.cidx[(int64_t)i * k + r] = j0;
+                a.cs[(int64_t)i * k + r] = s0;
+            }
+        }
+        __syncthreads();
+        const int wt = winner;
+        __syncthreads();
+        if (wt < 0) break;
+        if (tid == wt) ++head;
+        ++kept;
+    }
+    if (tid == 0) {
+        a.clen[i] = kept;
+        a.ccur[i] = 0;
+        if (kept == k) {
+            a.clb[i] = a.cs[(int64_t)i * k + k - 1];
+            a.cflag[i] = 0;
+        } else {
+            a.clb[i] = __builtin_huge_val();
+            a.cflag[i] = 1;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_rescore(const RescoreArgs& a, int32_t* overflow_list, hipStream_t s)
+{
+    if (a.n_rows <= 0) return hipSuccess;
+    unsigned g = (unsigned)((a.n_rows + 3) / 4);
+    switch (a.S / 64) {
+    case 1: k_rescore<1><<<g, 256, 0, s>>>(a, overflow_list); break;
+    case 2: k_rescore<2><<<g, 256, 0, s>>>(a, overflow_list); break;
+    case 4: k_rescore<4><<<g, 256, 0, s>>>(a, overflow_list); break;
+    case 8: k_rescore<8><<<g, 256, 0, s>>>(a, overflow_list); break;
+    case 16: k_rescore<16><<<g, 256, 0, s>>>(a, overflow_list); break;
+    case 32: k_rescore<32><<<g, 256, 0, s>>>(a, overflow_list); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback(const RescoreArgs& a, const int32_t* overflow_list, int n_over,
+                           hipStream_t s)
+{
+    if (n_over <= 0) return hipSuccess;
+    k_fallback<<<(unsigned)n_over, 256, 0, s>>>(a, overflow_list, n_over);
+    return hipGetLastError();
+}
+
+}  // namespace nnm

@@ -1,0 +1,146 @@
+"""The C-ABI boundary on the CPU: symbols, argument checks, host-side cut.
+
+No test here launches GPU work: only calls that fail their argument checks
+(before any device call) and the host-only cluster_cut are exercised.
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from golden_io import read_fixture
+from paper_1402_3789_amd import _native as N
+import paper_1402_3789_amd as nnm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "nnm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(?:nnm_status|void|const char \*)\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = N.lib()
+    declared = _declared()
+    assert set(declared) == set(N.exported_symbols())
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(N.Edge) == 24
+    assert ctypes.sizeof(N.CutParams) == 40
+    assert ctypes.sizeof(N.Options) == 64
+    assert ctypes.sizeof(N.Instance) == 40
+
+
+def test_strerror_and_defaults():
+    assert N.strerror(0) == "ok"
+    assert "non-finite" in N.strerror(N.NNM_ENONFINITE)
+    assert N.strerror(-99) == "unknown status"
+    o = N.Options()
+    N.lib().nnm_default_options(ctypes.byref(o))
+    assert o.precision == N.PREC["auto"] and o.knn_k == 16
+
+
+def _ws(n, d, **kw):
+    o = nnm.options(**kw)
+    nb = ctypes.c_size_t(0)
+    code = N.lib().mst_workspace_size(n, d, ctypes.byref(o), ctypes.byref(nb))
+    return code, nb.value
+
+
+def test_workspace_size_checks():
+    assert _ws(0, 8)[0] == N.NNM_EINVAL
+    assert _ws(10, 0)[0] == N.NNM_EINVAL
+    assert _ws(10, 33)[0] == N.NNM_EINVAL
+    assert _ws(10, 27, precision="bf16")[0] == N.NNM_EUNSUPPORTED
+    assert _ws(10, 27, precision="fp8")[0] == N.NNM_EUNSUPPORTED
+    code, b = _ws(10, 27, precision="auto")
+    assert code == 0 and b > 0
+    code, b1 = _ws(1000, 25)
+    code2, b2 = _ws(100000, 25)
+    assert code == 0 and code2 == 0 and b2 > b1
+    nb = ctypes.c_size_t(0)
+    assert N.lib().knn_workspace_size(100, 8, 0, None, ctypes.byref(nb)) == N.NNM_EINVAL
+    assert N.lib().knn_workspace_size(100, 8, 33, None, ctypes.byref(nb)) == N.NNM_EINVAL
+    assert N.lib().knn_workspace_size(100, 8, 8, None, ctypes.byref(nb)) == 0
+
+
+def test_entry_points_reject_bad_arguments_before_device_work():
+    L = N.lib()
+    o = nnm.options()
+    rep = N.Report()
+    fake = ctypes.c_void_p(0x1000)    # never dereferenced: checks fail first
+    # null X, n < 1, d out of range, ld < d, short workspace
+    assert L.mst_build(None, 10, 4, 4, ctypes.byref(o), fake, 1 << 30, fake, None,
+                       ctypes.byref(rep)) == N.NNM_EINVAL
+    assert L.mst_build(fake, 0, 4, 4, ctypes.byref(o), fake, 1 << 30, fake, None,
+                       ctypes.byref(rep)) == N.NNM_EINVAL
+    assert L.mst_build(fake, 10, 0, 4, ctypes.byref(o), fake, 1 << 30, fake, None,
+                       ctypes.byref(rep)) == N.NNM_EINVAL
+    assert L.mst_build(fake, 10, 40, 40, ctypes.byref(o), fake, 1 << 30, fake, None,
+                       ctypes.byref(rep)) == N.NNM_EINVAL
+    assert L.mst_build(fake, 10, 4, 3, ctypes.byref(o), fake, 1 << 30, fake, None,
+                       ctypes.byref(rep)) == N.NNM_EINVAL
+    assert L.mst_build(fake, 10, 4, 4, ctypes.byref(o), fake, 16, fake, None,
+                       ctypes.byref(rep)) == N.NNM_EINVAL
+    assert L.mst_build(fake, 10, 4, 4, ctypes.byref(o), fake, 1 << 30, None, None,
+                       ctypes.byref(rep)) == N.NNM_EINVAL
+    assert L.knn_build(fake, 10, 4, 4, 0, ctypes.byref(o), fake, 1 << 30, fake, fake, fake,
+                       None, ctypes.byref(rep)) == N.NNM_EINVAL
+    assert L.knn_build(fake, 10, 4, 4, 4, ctypes.byref(o), fake, 1 << 30, None, fake, fake,
+                       None, ctypes.byref(rep)) == N.NNM_EINVAL
+
+
+def _random_tree(rng, n, d=3, ties=False):
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    if ties:
+        X = np.round(X * 2).astype(np.float32)
+    return X, oracle.prim_mst(X)
+
+
+def test_cut_matches_oracle_cut_on_random_settings():
+    rng = np.random.default_rng(101)
+    for trial in range(300):
+        n = int(rng.integers(1, 120))
+        X, (u, v, s, w) = _random_tree(rng, n, ties=trial % 2 == 0)
+        kl1 = int(rng.choice([0, 1, 2, 3, 5, 10]))
+        kl2 = int(rng.choice([-1, 1, 3, 8]))
+        kl3 = int(rng.choice([-1, 2, 5, 12]))
+        kl4 = int(rng.choice([0, 1, 2, 4, 9]))
+        dmax = float(rng.choice([math.inf, 0.5, 1.0, 2.0]))
+        got, k = nnm.cluster_cut((u, v, s, w), n, kl1, kl2, kl3, kl4, dmax)
+        exp, ke = oracle.cut(u, v, s, w, n, kl1, kl2, kl3, kl4, dmax)
+        assert k == ke and np.array_equal(got, exp), (trial, kl1, kl2, kl3, kl4, dmax)
+
+
+def test_cut_golden_line7():
+    X, _, cuts = read_fixture("cut_line7.txt")
+    u, v, s, w = oracle.prim_mst(X)
+    for kl1, kl4, dmax, lab in cuts:
+        got, k = nnm.cluster_cut((u, v, s, w), X.shape[0], kl1=kl1, kl4=kl4, dmax=dmax)
+        assert got.tolist() == lab
+
+
+def test_cut_rejects_bad_edges():
+    u = np.array([0, 1], np.int32)
+    v = np.array([1, 2], np.int32)
+    s = np.array([2.0, 1.0])
+    with pytest.raises(N.NNMError):
+        nnm.cluster_cut((u, v, s, np.sqrt(s)), 3)                       # unsorted
+    with pytest.raises(N.NNMError):
+        nnm.cluster_cut((np.array([1, 1], np.int32), np.array([0, 2], np.int32),
+                         np.array([1.0, 2.0]), np.array([1.0, 1.5])), 3)   # u > v
+    with pytest.raises(N.NNMError):
+        nnm.cluster_cut((u, np.array([1, 5], np.int32), np.array([1.0, 2.0]),
+                         np.array([1.0, 1.5])), 3)                      # v out of range
+    lab, k = nnm.cluster_cut((u[:0], v[:0], s[:0], s[:0]), 1)
+    assert k == 1 and lab.tolist() == [0]

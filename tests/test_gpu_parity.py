@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Bar: tree edges (u, v) and FP64 weights s, w bit-exact; cut labels
+bit-exact; neighbour lists (idx, s) bit-exact.  Every case prints its name,
+seed and shape before it touches the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp32", "fp16", "bf16"]
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def nnm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1402_3789_amd as m
+    return m
+
+
+def _dev(X):
+    return torch.from_numpy(np.ascontiguousarray(X, np.float32)).to("cuda:0")
+
+
+def _tree_equal(nnm, X, **kw):
+    tree = nnm.mst_build(_dev(X), **kw)
+    torch.cuda.synchronize()
+    u, v, s, w = tree.to_numpy()
+    ou, ov, os_, ow = oracle.prim_mst(X)
+    assert len(u) == len(ou)
+    bad = np.nonzero((u != ou) | (v != ov) | (s != os_))[0]
+    assert bad.size == 0, f"first mismatches at {bad[:5]}: gpu {list(zip(u[bad[:5]], v[bad[:5]], s[bad[:5]]))} oracle {list(zip(ou[bad[:5]], ov[bad[:5]], os_[bad[:5]]))}"
+    assert np.array_equal(w, ow)
+    return tree, (ou, ov, os_, ow)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_blobs8_tree_and_cut(nnm, prec):
+    X, y = W.blobs8(0)
+    _say("blobs8", prec, X.shape)
+    tree, (ou, ov, os_, ow) = _tree_equal(nnm, X, precision=prec)
+    lab, k = nnm.cluster_cut(tree, kl1=8)
+    olab, ok = oracle.cut(ou, ov, os_, ow, X.shape[0], kl1=8)
+    assert k == ok == 8 and np.array_equal(lab, olab)
+    rep = tree.report
+    assert rep["rounds"] >= 1
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixture_reduced_with_constraints(nnm, prec):
+    X, _ = W.mixture64(0, n=6000)
+    _say("mixture64 reduced", prec, X.shape)
+    tree, (ou, ov, os_, ow) = _tree_equal(nnm, X, precision=prec)
+    lab, k = nnm.cluster_cut(tree, kl1=64, kl4=50, dmax=0.2)
+    olab, ok = oracle.cut(ou, ov, os_, ow, X.shape[0], kl1=64, kl4=50, dmax=0.2)
+    assert k == ok and np.array_equal(lab, olab)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_aniso_reduced(nnm, prec):
+    X, _ = W.aniso500(0, n=12000, k=40)
+    _say("aniso500 reduced", prec, X.shape)
+    _tree_equal(nnm, X, precision=prec)
+
+
+@pytest.mark.parametrize("prec", ["fp8", "bf16", "fp16", "fp32", "auto"])
+def test_integer_grid_ties(nnm, prec):
+    X = W.int16grid(0, n=5000)
+    _say("int16grid reduced", prec, X.shape)
+    tree, (ou, ov, os_, ow) = _tree_equal(nnm, X, precision=prec)
+    if prec != "fp32":
+        assert tree.report["integer_mode"] == 1
+        assert tree.report["max_abs_err"] == 0.0
+    lab, k = nnm.cluster_cut(tree, kl1=64)
+    olab, ok = oracle.cut(ou, ov, os_, ow, X.shape[0], kl1=64)
+    assert k == ok and np.array_equal(lab, olab)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 255, 256, 257, 1000, 4097])
+def test_ragged_sizes(nnm, n):
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, 5)).astype(np.float32)
+    _say("ragged", n)
+    for prec in ("fp16", "fp32"):
+        tree = nnm.mst_build(_dev(X), precision=prec)
+        torch.cuda.synchronize()
+        u, v, s, w = tree.to_numpy()
+        ou, ov, os_, ow = oracle.prim_mst(X)
+        assert np.array_equal(u, ou) and np.array_equal(v, ov) and np.array_equal(s, os_)
+
+
+@pytest.mark.parametrize("kind", ["dups", "all_same", "collinear", "lattice", "d1", "d26"])
+def test_degenerate_inputs(nnm, kind):
+    rng = np.random.default_rng(7)
+    if kind == "dups":
+        base = rng.standard_normal((50, 6)).astype(np.float32)
+        X = base[rng.integers(0, 50, size=700)]
+    elif kind == "all_same":
+        X = np.ones((300, 4), np.float32)
+    elif kind == "collinear":
+        X = (np.arange(600)[:, None] * np.array([[0.25, -1.0, 3.0]])).astype(np.float32)
+        X = X[rng.permutation(600)]
+    elif kind == "lattice":
+        X = rng.integers(0, 3, size=(900, 3)).astype(np.float32) * 0.5 + 0.25
+    elif kind == "d1":
+        X = rng.standard_normal((800, 1)).astype(np.float32)
+    else:
+        X = rng.uniform(0, 1, size=(1500, 26)).astype(np.float32)
+    _say("degenerate", kind, X.shape)
+    for prec in ("fp16", "bf16", "fp32"):
+        _tree_equal(nnm, X, precision=prec)
+
+
+def test_near_ties_below_half_precision(nnm):
+    # pairs whose squared distances differ far below FP16/BF16 resolution
+    rng = np.random.default_rng(11)
+    base = rng.uniform(0, 1, size=(40, 8)).astype(np.float32)
+    jit = rng.integers(-3, 4, size=(40 * 25, 8)) * 2.0 ** -20
+    X = (np.repeat(base, 25, axis=0) + jit).astype(np.float32)
+    _say("near ties", X.shape)
+    for prec in ("fp16", "bf16", "fp32"):
+        _tree_equal(nnm, X, precision=prec)
+
+
+@pytest.mark.parametrize("knob", ["k1", "k32", "cap64", "fallback", "noprune", "splits4"])
+def test_forced_paths_give_identical_trees(nnm, knob):
+    X, _ = W.mixture64(1, n=3000, d=12)
+    kw = {"k1": dict(knn_k=1), "k32": dict(knn_k=32), "cap64": dict(survivor_cap=64),
+          "fallback": dict(force_fallback=True), "noprune": dict(disable_prune=True),
+          "splits4": dict(col_splits=4)}[knob]
+    _say("forced path", knob, X.shape)
+    for prec in ("fp16", "fp32"):
+        _tree_equal(nnm, X, precision=prec, **kw)
+
+
+def test_nonfinite_and_fp8_rejected(nnm):
+    X = np.zeros((10, 3), np.float32)
+    X[4, 1] = np.nan
+    _say("nonfinite")
+    with pytest.raises(nnm.NNMError) as e:
+        nnm.mst_build(_dev(X))
+    assert e.value.code == -4
+    X = np.random.default_rng(0).uniform(0, 1, (20, 3)).astype(np.float32)
+    with pytest.raises(nnm.NNMError) as e:
+        nnm.mst_build(_dev(X), precision="fp8")
+    assert e.value.code == -5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16", "fp8"])
+def test_knn_matches_oracle(nnm, prec):
+    if prec == "fp8":
+        X = W.int16grid(3, n=2500, d=10)
+    else:
+        X, _ = W.mixture64(2, n=2500, d=16)
+    k = 12
+    _say("knn", prec, X.shape, k)
+    idx, s, ln = nnm.knn_build(_dev(X), k=k, precision=prec)
+    torch.cuda.synchronize()
+    oi, os_, ol = oracle.knn(X, k)
+    assert np.array_equal(ln.cpu().numpy(), ol)
+    assert np.array_equal(idx.cpu().numpy(), oi)
+    assert np.array_equal(s.cpu().numpy(), os_)
+
+
+def test_knn_short_rows(nnm):
+    X = np.random.default_rng(4).standard_normal((5, 3)).astype(np.float32)
+    _say("knn short rows")
+    idx, s, ln = nnm.knn_build(_dev(X), k=8, precision="fp16")
+    oi, os_, ol = oracle.knn(X, 8)
+    assert np.array_equal(ln.cpu().numpy(), ol)
+    assert np.array_equal(idx.cpu().numpy(), oi)
+    assert np.array_equal(s.cpu().numpy(), os_)
+
+
+def test_determinism_across_runs_and_settings(nnm):
+    X, _ = W.mixture64(5, n=4000, d=25)
+    _say("determinism", X.shape)
+    ref = None
+    for kw in (dict(precision="fp16"), dict(precision="fp16"), dict(precision="bf16", knn_k=8),
+               dict(precision="fp32", knn_k=4), dict(precision="fp16", col_splits=3)):
+        t = nnm.mst_build(_dev(X), **kw)
+        raw = t.host_bytes().copy()
+        if ref is None:
+            ref = raw
+        assert np.array_equal(raw, ref)
+
+
+def test_batched_matches_single(nnm):
+    Xs = W.batch256(0, count=6, n_lo=300, n_hi=3000)
+    _say("batched", [x.shape for x in Xs])
+    trees = nnm.mst_build_batched([_dev(x) for x in Xs], precision="fp16")
+    torch.cuda.synchronize()
+    for X, t in zip(Xs, trees):
+        u, v, s, w = t.to_numpy()
+        ou, ov, os_, ow = oracle.prim_mst(X)
+        assert np.array_equal(u, ou) and np.array_equal(v, ov) and np.array_equal(s, os_)
