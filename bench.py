@@ -1,0 +1,205 @@
+"""Benchmark: exact single-linkage tree + constrained cut at N = 2,000,000, D = 25.
+
+One step = mst_build (exact key-ordered minimum spanning tree on the GPU)
++ copy of the N-1 edges to the host + cluster_cut (host).  The input is
+already resident in GPU memory when timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints ONE JSON line with the headline metric (effective pair-distances/s =
+N(N-1)/2 / wall time per step) for the mixed-precision path, the plain FP32
+path's wall time on the same data, the roofline of the dominant kernel (the
+candidate pass, from HIP-event timings recorded on the library's stream)
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MFMA_PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0}
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash(name):
+    p = os.path.join(ROOT, "paper_1402_3789_amd", "csrc", name)
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(precision, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"traffic_cand_{precision}_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        t = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash("cand_mfma.hip"):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(X, seconds):
+    """Dense FP64 Prim (the oracle) on the first n_s points of the workload."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        cores = min(cores, int(env))
+    n0 = min(20000, X.shape[0])
+    t0 = time.perf_counter()
+    oracle.prim_mst(X[:n0], threads=cores)
+    t1 = time.perf_counter() - t0
+    ns = int(n0 * (seconds / max(t1, 1e-3)) ** 0.5)
+    ns = max(n0, min(ns, X.shape[0]))
+    if ns > n0:
+        t0 = time.perf_counter()
+        oracle.prim_mst(X[:ns], threads=cores)
+        t1 = time.perf_counter() - t0
+    pairs = ns * (ns - 1) / 2.0
+    return {"value": pairs / t1, "unit": "pair-distances/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {ns} of the {X.shape[0]} points (dense FP64 Prim, every pair "
+                      f"evaluated once), {t1:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=2_000_000)
+    ap.add_argument("--precision", default="fp16")
+    ap.add_argument("--fp32-steps", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 3}), flush=True)
+        return
+
+    import paper_1402_3789_amd as nnm
+    from workloads import aniso500
+
+    t0 = time.perf_counter()
+    X, _ = aniso500(0, n=args.n)
+    log(f"[bench] workload aniso500 n={args.n} d=25 generated in {time.perf_counter() - t0:.1f}s")
+    n, d = X.shape
+    Xd = torch.from_numpy(X).to("cuda:0")
+    torch.cuda.synchronize()
+
+    def step(precision):
+        tree = nnm.mst_build(Xd, precision=precision)
+        u, v, s, w = tree.to_numpy()             # device -> host copy of the edges
+        labels, k = nnm.cluster_cut((u, v, s, w), n, kl1=500)
+        return tree, k
+
+    for i in range(args.warmup):
+        step(args.precision)
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        tree, k = step(args.precision)
+        reps.append(tree.report)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = 1e3 * elapsed / args.steps
+    log(f"[bench] {args.precision}: {ms:.1f} ms/step over {args.steps} steps, {k} clusters")
+    pairs = n * (n - 1) / 2.0
+
+    # roofline of the candidate pass (dominant kernel)
+    cand_ms = sum(r["ms_candidates"] for r in reps)
+    launches = sum(r["cand_launches"] for r in reps)
+    evaluated = sum(r["pairs_evaluated"] for r in reps)
+    flops = evaluated * (2 * d + 1)              # x.y form: 2D + 1 flops per ordered pair
+    achieved = flops / (cand_ms * 1e-3) / 1e12 if cand_ms > 0 else 0.0
+    peak = MFMA_PEAK_TFLOPS.get(args.precision, FP32_VECTOR_PEAK_TFLOPS)
+    bound = "mfma" if args.precision in MFMA_PEAK_TFLOPS else "alu"
+    traffic = load_traffic(args.precision, "aniso500")
+    roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 5), "traffic": traffic,
+            "kernel": f"k_cand_mfma<{args.precision}>", "launches_per_step": launches / args.steps,
+            "avg_launch_ms": cand_ms / max(launches, 1),
+            "pairs_evaluated_per_step": evaluated / args.steps,
+            "flops_per_pair": 2 * d + 1}
+
+    # plain FP32 path on the same data
+    fp32 = None
+    if args.fp32_steps > 0:
+        step("fp32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.fp32_steps):
+            tr32, _ = step("fp32")
+        torch.cuda.synchronize()
+        ms32 = 1e3 * (time.perf_counter() - t0) / args.fp32_steps
+        same = np.array_equal(tr32.host_bytes(), tree.host_bytes())
+        fp32 = {"ms_per_step": round(ms32, 3), "value": pairs / (ms32 * 1e-3),
+                "mixed_speedup": round(ms32 / ms, 3), "identical_tree": bool(same)}
+        log(f"[bench] fp32: {ms32:.1f} ms/step, identical tree: {same}")
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(X, args.cpu_seconds)
+        log(f"[bench] cpu oracle: {cpu['value']:.3g} pair-distances/s ({cpu['sample']})")
+
+    last = reps[-1]
+    out = {
+        "metric": "MST+cut wall-time at N=2M,D=25; pair-distances/s, mixed-prec vs FP32",
+        "value": pairs / (ms * 1e-3),
+        "unit": "pair-distances/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp16": "f16", "bf16": "bf16", "fp8": "fp8"}.get(args.precision, "f32"),
+        "data": "synthetic",
+        "config": {"workload": "aniso500", "n": n, "d": d, "clusters": 500,
+                   "precision": args.precision, "cut": "kl1=500", "seed": 0},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp32_path": fp32,
+        "report": {k2: last[k2] for k2 in ("rounds", "rows_scanned", "pairs_evaluated",
+                                            "survivors", "overflow_rows", "max_abs_err",
+                                            "max_rel_err", "ms_candidates", "ms_rescore",
+                                            "ms_merge", "ms_sort", "rows_per_round",
+                                            "comps_per_round")},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

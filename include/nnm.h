@@ -69,7 +69,7 @@ typedef enum {
  *   BF16  x.y form on the matrix cores, FP32 accumulation (D <= 26);
  *   FP16  as BF16 with FP16 operands (D <= 26);
  *   FP8   e4m3 operands; only for integer features in [-16, 16] (D <= 26);
- *   AUTO  FP8 for such integer data, else BF16 when D <= 26, else FP32.
+ *   AUTO  FP8 for such integer data, else FP16 when D <= 26, else FP32.
  */
 typedef enum {
     NNM_PREC_FP32 = 0,
@@ -128,7 +128,7 @@ typedef struct {
     int64_t rows_scanned;       /* rows sent through the candidate pass       */
     int64_t pairs_evaluated;    /* candidate pairs evaluated (tiles run)      */
     int64_t survivors;          /* candidates rescored in FP64                */
-    int64_t overflow_rows;      /* rows rescored by the full FP64 scan        */
+    int64_t overflow_rows;      /* rows that needed the exact full FP64 scan  */
     double max_abs_err;         /* max |t - s| over rescored candidates       */
     double max_rel_err;         /* max |t - s| / s over candidates with s > 0 */
     double max_bound;           /* largest error bound applied                */
@@ -139,6 +139,8 @@ typedef struct {
     double ms_sort;             /* edge and component sorts, ms               */
     int64_t rows_per_round[32]; /* rows scanned in each round                 */
     int64_t comps_per_round[32];/* components at the start of each round      */
+    int64_t cand_launches;      /* candidate-kernel launches                  */
+    int64_t rescanned_bounded;  /* overflowed rows scanned again below a bound */
 } nnm_report;
 
 /* Fill *opt with the defaults (AUTO precision, k = 16, automatic caps). */

@@ -46,7 +46,9 @@ class Report(ctypes.Structure):
                 ("ms_candidates", ctypes.c_double), ("ms_rescore", ctypes.c_double),
                 ("ms_merge", ctypes.c_double), ("ms_sort", ctypes.c_double),
                 ("rows_per_round", ctypes.c_int64 * 32),
-                ("comps_per_round", ctypes.c_int64 * 32)]
+                ("comps_per_round", ctypes.c_int64 * 32),
+                ("cand_launches", ctypes.c_int64),
+                ("rescanned_bounded", ctypes.c_int64)]
 
     def as_dict(self):
         out = {}

@@ -1,18 +1,20 @@
 // cand_fp32.hip -- the plain FP32 candidate pass on the vector ALUs.
 //
 // Same contract as the matrix-core pass (pair distances fused with the
-// selection of the k smallest per row, component mask, survivor lists), but
-// the candidate is the FP32 direct-difference sum
+// selection of the k smallest per row, component mask, survivor lists,
+// nearest-first chunk order, ball pruning), but the candidate is the FP32
+// direct-difference sum
 //     t_ij = sum_f fma((x_if - x_jf), (x_if - x_jf), .)
-// which is within a relative (D + 3) 2^-24 of the exact FP64 key.  One row
-// per thread (features in registers); column chunks are broadcast from LDS.
-#include "nnm_common.h"
+// which is within a relative (D + 3) 2^-24 (plus an underflow floor) of the
+// exact FP64 key.  One row per thread (features in registers); column
+// chunks are broadcast from LDS.
+#include "cand_common.h"
 
 namespace nnm {
 namespace {
 
 constexpr int BM = 256;
-constexpr int BN = 128;
+constexpr int BN = CHUNK;
 
 __device__ __forceinline__ float fp32_thresh_from_U(double U, double crel, double a0)
 {
@@ -21,7 +23,7 @@ __device__ __forceinline__ float fp32_thresh_from_U(double U, double crel, doubl
 
 __device__ __forceinline__ double fp32_upper_from_t(double t, double crel, double a0)
 {
-    return (t + a0) / (1.0 - crel);
+    return (t + a0) / (1.0 - crel) * (1.0 + 0x1p-40);
 }
 
 template <int DP>
@@ -30,7 +32,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
     constexpr int F4 = DP / 4;
     __shared__ float4 cbuf[BN * F4];
     __shared__ int32_t ccomp[BN];
-    __shared__ int32_t tileLo, tileHi, tileRows;
+    __shared__ TileShared sh;
     extern __shared__ float topk[];   // [BM][k]
 
     const int tid = threadIdx.x;
@@ -52,38 +54,58 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
     }
     const int rc = valid ? a.compS[rp] : -2;
     float T = -__builtin_huge_valf();
+    float U = 0.f;
     if (valid) {
         T = 3.402823466e38f;
+        U = __builtin_huge_valf();
         if (a.u0) {
             const double u0 = a.u0[rp];
-            if (u0 >= 0.0) T = fminf(T, fp32_thresh_from_U(u0, crel, a0));
+            if (u0 >= 0.0) {
+                T = fminf(T, fp32_thresh_from_U(u0, crel, a0));
+                U = d2f_up(u0);
+            }
         }
     }
     float* tk = topk + tid * k;
     for (int e = 0; e < k; ++e) tk[e] = __builtin_huge_valf();
+    if (a.prune) tile_ball<DP>(sh, xr, valid, a.d);
     if (tid == 0) {
         int64_t last = (int64_t)blockIdx.x * BM + BM - 1;
         if (last >= a.n_rows) last = a.n_rows - 1;
         const int64_t first = (int64_t)blockIdx.x * BM;
-        tileLo = a.compS[a.rows ? a.rows[first] : a.row0 + (int)first];
-        tileHi = a.compS[a.rows ? a.rows[last] : a.row0 + (int)last];
-        tileRows = (int)(last - first + 1);
+        const int r0 = a.rows ? a.rows[first] : a.row0 + (int)first;
+        sh.lo = a.compS[r0];
+        sh.hi = a.compS[a.rows ? a.rows[last] : a.row0 + (int)last];
+        sh.rows = (int)(last - first + 1);
+        sh.first_pos = r0;
     }
     __syncthreads();
-    const int lo_r = tileLo, hi_r = tileHi;
+    const int lo_r = sh.lo, hi_r = sh.hi;
 
-    int64_t cps = ((int64_t)a.np + a.col_splits - 1) / a.col_splits;
-    cps = (cps + BN - 1) / BN * BN;
-    const int64_t c_begin = (int64_t)blockIdx.y * cps;
-    int64_t c_end = c_begin + cps;
-    if (c_end > a.np) c_end = a.np;
+    const int nch = (a.np + BN - 1) / BN;
+    const int cps = (nch + a.col_splits - 1) / a.col_splits;
+    const int ch_lo = (int)blockIdx.y * cps;
+    const int ch_hi = ch_lo + cps < nch ? ch_lo + cps : nch;
+    int start = sh.first_pos / BN;
+    start = start < ch_lo ? ch_lo : (start >= ch_hi ? ch_hi - 1 : start);
     unsigned long long pairs = 0;
 
-    for (int64_t c0 = c_begin; c0 < c_end; c0 += BN) {
-        const int ncols = (int)((c_end - c0) < BN ? (c_end - c0) : BN);
+    for (int step = 0; step < ch_hi - ch_lo; ++step) {
+        const int ci = zigzag(step, start, ch_lo, ch_hi);
+        const int64_t c0 = (int64_t)ci * BN;
+        const int ncols = (int)((a.np - c0) < BN ? (a.np - c0) : BN);
         const int lo_c = a.compS[c0];
         const int hi_c = a.compS[c0 + ncols - 1];
         if (lo_r == hi_r && lo_c == hi_c && lo_r == lo_c) continue;
+        if (a.share && valid) {
+            T = fminf(T, __uint_as_float(a.gT[slot]));
+            U = fminf(U, __uint_as_float(a.gU[slot]));
+        }
+        if (a.prune) {
+            const float umax = block_max(sh, valid ? U : 0.f);
+            const double lb2 = ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE, a.d);
+            if (lb2 > (double)umax) continue;
+        }
         const bool masked = !(hi_c < lo_r || lo_c > hi_r);
         __syncthreads();
         for (int idx = tid; idx < BN * F4; idx += 256) {
@@ -92,7 +114,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
             if (c < ncols) v = reinterpret_cast<const float4*>(a.xs + (c0 + c) * DMAX)[q];
             cbuf[idx] = v;
         }
-        if (tid < BN) ccomp[tid] = (tid < ncols) ? a.compS[c0 + tid] : -1;
+        ccomp[tid] = (tid < ncols) ? a.compS[c0 + tid] : -1;
         __syncthreads();
         pairs += (unsigned long long)ncols;
         for (int c = 0; c < ncols; ++c) {
@@ -122,14 +144,23 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
                     tk[p] = t;
                     const float kth = tk[k - 1];
                     if (kth < __builtin_huge_valf()) {
-                        const float Tn = fp32_thresh_from_U(fp32_upper_from_t((double)kth, crel, a0), crel, a0);
-                        T = fminf(T, Tn);
+                        const double Ud = fp32_upper_from_t((double)kth, crel, a0);
+                        const float Tn = fp32_thresh_from_U(Ud, crel, a0);
+                        const float Un = d2f_up(Ud);
+                        if (Tn < T) {
+                            T = Tn;
+                            if (a.share) atomicMin(&a.gT[slot], __float_as_uint(T));
+                        }
+                        if (Un < U) {
+                            U = Un;
+                            if (a.share) atomicMin(&a.gU[slot], __float_as_uint(U));
+                        }
                     }
                 }
             }
         }
     }
-    if (tid == 0 && a.pairs) atomicAdd(a.pairs, pairs * (unsigned long long)tileRows);
+    if (tid == 0 && a.pairs) atomicAdd(a.pairs, pairs * (unsigned long long)sh.rows);
 }
 
 }  // namespace

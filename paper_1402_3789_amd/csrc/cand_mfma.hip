@@ -15,17 +15,23 @@
 // (value, constant) pairs, so the FP32 accumulator is t itself.
 //
 // Selection.  Each row keeps, in LDS, the k smallest t it has seen; from the
-// k-th of them the proven error bound gives a threshold T_i such that every
-// column whose exact FP64 key can still be among the row's k smallest has
-// t <= T_i.  Every such column is appended to the row's survivor list (global
-// memory) for exact FP64 rescoring.  The per-element work is one min3 chain
-// and one compare per four pairs; the rare hits take a wave-uniform slow path.
+// k-th of them the proven error bound gives (1) U_i, an upper bound on the
+// exact key of the row's k-th nearest column, and (2) a threshold T_i such
+// that every column whose exact key is <= U_i has t <= T_i.  Every column
+// with t <= T_i is appended to the row's survivor list (global memory) for
+// exact FP64 rescoring.  The per-element work is one min3 chain and one
+// compare per four pairs; hits take a wave-uniform slow path.
+//
+// Search order and pruning.  Points are stored in a spatial order, so the
+// chunks are visited nearest-first starting at the tile's own position, and
+// a chunk is skipped when the distance between the tile's bounding ball and
+// the chunk's bounding ball already exceeds every row's U_i.
 //
 // MFMA layouts used (16x16x32): lane l supplies A[m = l%16][k-slice l/16]
 // and B[k-slice l/16][n = l%16]; result register r of lane l is
 // D[m = 4(l/16) + r][n = l%16].  Columns j are the A (M) side, rows i the
 // B (N) side, so each lane ends up with four columns of one row.
-#include "nnm_common.h"
+#include "cand_common.h"
 
 namespace nnm {
 namespace {
@@ -36,8 +42,8 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int WAVES = 4;
 constexpr int RB = 4;                 // 16-row blocks per wave
-constexpr int BM = WAVES * RB * 16;   // rows per workgroup
-constexpr int BN = 256;               // columns per LDS chunk
+constexpr int BM = WAVES * RB * 16;   // rows per workgroup (= threads)
+constexpr int BN = CHUNK;             // columns per LDS chunk
 constexpr float KFAC = 1.0f + 0x1p-20f;
 
 template <int OP> struct OpTraits;
@@ -89,7 +95,7 @@ __device__ __forceinline__ double upper_from_t(double t, double eps, double eta,
     if (exact) return t;
     const double kf = (double)KFAC;
     double tp = t > 0.0 ? t : 0.0;
-    return t + kf * (eps + eta * (2.0 * __builtin_sqrt(tp + eps) + eta));
+    return (t + kf * (eps + eta * (2.0 * __builtin_sqrt(tp + eps) + eta))) * (1.0 + 0x1p-40);
 }
 
 template <int OP>
@@ -97,14 +103,13 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
 {
     typedef OpTraits<OP> Tr;
     typedef typename Tr::frag_t frag_t;
-    constexpr int FRAGS_PER_COL = 4;                       // k-slices
     constexpr int LOADS = BN * Tr::BYTES / 16 / 256;       // uint4 loads per thread
 
-    __shared__ frag_t colbuf[BN / 16 * FRAGS_PER_COL * 16];
+    __shared__ frag_t colbuf[BN / 16 * 4 * 16];
     __shared__ __align__(16) int32_t colcomp[BN];
-    __shared__ float rowT[BM];
+    __shared__ float rowT[BM], rowU[BM];
     __shared__ double rowEps[BM], rowEta[BM];
-    __shared__ int32_t tileLo, tileHi, tileRows;
+    __shared__ TileShared sh;
     extern __shared__ float topk[];                        // [BM][k]
 
     const int tid = threadIdx.x;
@@ -114,40 +119,53 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     const int k = a.k;
     const int64_t row_base = (int64_t)blockIdx.x * BM;
     const int exact = a.bc.exact;
+    const double inv_s2 = 1.0 / (double)a.bc.sigma2;
 
-    // ---- per-row state -------------------------------------------------
+    // ---- per-row state (thread t owns row t of the tile) -----------------
+    const int64_t my_slot = row_base + tid;
+    const bool my_valid = my_slot < a.n_rows;
+    const int my_rp = my_valid ? (a.rows ? a.rows[my_slot] : a.row0 + (int)my_slot) : 0;
     {
-        const int rl = tid;
-        const int64_t slot = row_base + rl;
-        float T = -__builtin_huge_valf();
+        float T = -__builtin_huge_valf(), U = 0.f;
         double eps = 0.0, eta = 0.0;
-        if (slot < a.n_rows) {
-            const int rp = a.rows ? a.rows[slot] : a.row0 + (int)slot;
-            const PointConst p = a.pc[rp];
+        if (my_valid) {
+            const PointConst p = a.pc[my_rp];
             eps = ((double)a.bc.gamma * (2.0 * (double)p.Q * (double)a.bc.colQ + (double)p.P +
                                          (double)a.bc.colP) +
                    (double)p.rho + (double)a.bc.colRho) * (1.0 + 0x1p-40);
             eta = ((double)p.eta + (double)a.bc.colEta) * (1.0 + 0x1p-40);
             T = 3.402823466e38f;                           // FLT_MAX: keep all
+            U = __builtin_huge_valf();
             if (a.u0) {
-                const double u0 = a.u0[rp];
-                if (u0 >= 0.0)
+                const double u0 = a.u0[my_rp];
+                if (u0 >= 0.0) {
                     T = fminf(T, thresh_from_U(u0 * (double)a.bc.sigma2 * (1.0 + 0x1p-50), eps, eta, exact));
+                    U = d2f_up(u0);
+                }
             }
         }
-        rowT[rl] = T;
-        rowEps[rl] = eps;
-        rowEta[rl] = eta;
-        for (int e = 0; e < k; ++e) topk[rl * k + e] = __builtin_huge_valf();
-        if (tid == 0) {
-            int64_t last = row_base + BM - 1;
-            if (last >= a.n_rows) last = a.n_rows - 1;
-            const int r0 = a.rows ? a.rows[row_base] : a.row0 + (int)row_base;
-            const int r1 = a.rows ? a.rows[last] : a.row0 + (int)last;
-            tileLo = a.compS[r0];
-            tileHi = a.compS[r1];
-            tileRows = (int)(last - row_base + 1);
-        }
+        rowT[tid] = T;
+        rowU[tid] = U;
+        rowEps[tid] = eps;
+        rowEta[tid] = eta;
+        for (int e = 0; e < k; ++e) topk[tid * k + e] = __builtin_huge_valf();
+    }
+    if (a.prune) {
+        float x[DMAX];
+        const float* src = a.X + (int64_t)(my_valid ? a.perm[my_rp] : 0) * a.ld;
+#pragma unroll
+        for (int f = 0; f < DMAX; ++f) x[f] = (f < a.d && my_valid) ? src[f] : 0.f;
+        tile_ball<DMAX>(sh, x, my_valid, a.d);
+    }
+    if (tid == 0) {
+        int64_t last = row_base + BM - 1;
+        if (last >= a.n_rows) last = a.n_rows - 1;
+        const int r0 = a.rows ? a.rows[row_base] : a.row0 + (int)row_base;
+        const int r1 = a.rows ? a.rows[last] : a.row0 + (int)last;
+        sh.lo = a.compS[r0];
+        sh.hi = a.compS[r1];
+        sh.rows = (int)(last - row_base + 1);
+        sh.first_pos = r0;
     }
     // row fragments stay in registers for the whole sweep
     frag_t bfrag[RB];
@@ -159,7 +177,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         const int64_t slot = row_base + rl;
         rvalid[rb] = slot < a.n_rows;
         const int rp = rvalid[rb] ? (a.rows ? a.rows[slot] : a.row0 + (int)slot) : 0;
-        const frag_t* src = reinterpret_cast<const frag_t*>(a.opR) + (int64_t)rp * FRAGS_PER_COL + grp;
+        const frag_t* src = reinterpret_cast<const frag_t*>(a.opR) + (int64_t)rp * 4 + grp;
         bfrag[rb] = *src;
         rcomp[rb] = rvalid[rb] ? a.compS[rp] : -2;
     }
@@ -167,21 +185,33 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     float Treg[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) Treg[rb] = rowT[wave * RB * 16 + rb * 16 + (lane & 15)];
-    const int lo_r = tileLo, hi_r = tileHi;
+    const int lo_r = sh.lo, hi_r = sh.hi;
 
-    // ---- column sweep --------------------------------------------------
-    int64_t cps = ((int64_t)a.np + a.col_splits - 1) / a.col_splits;
-    cps = (cps + BN - 1) / BN * BN;
-    const int64_t c_begin = (int64_t)blockIdx.y * cps;
-    int64_t c_end = c_begin + cps;
-    if (c_end > a.np) c_end = a.np;
+    // ---- column sweep, nearest chunks first ------------------------------
+    const int nch = (a.np + BN - 1) / BN;
+    const int cps = (nch + a.col_splits - 1) / a.col_splits;
+    const int ch_lo = (int)blockIdx.y * cps;
+    const int ch_hi = ch_lo + cps < nch ? ch_lo + cps : nch;
+    int start = sh.first_pos / BN;
+    start = start < ch_lo ? ch_lo : (start >= ch_hi ? ch_hi - 1 : start);
     unsigned long long pairs = 0;
 
-    for (int64_t c0 = c_begin; c0 < c_end; c0 += BN) {
-        const int ncols = (int)((c_end - c0) < BN ? (c_end - c0) : BN);
+    for (int step = 0; step < ch_hi - ch_lo; ++step) {
+        const int ci = zigzag(step, start, ch_lo, ch_hi);
+        const int64_t c0 = (int64_t)ci * BN;
+        const int ncols = (int)((a.np - c0) < BN ? (a.np - c0) : BN);
         const int lo_c = a.compS[c0];
         const int hi_c = a.compS[c0 + ncols - 1];
         if (lo_r == hi_r && lo_c == hi_c && lo_r == lo_c) continue;   // all one component
+        if (a.share && my_valid) {
+            rowT[tid] = fminf(rowT[tid], __uint_as_float(a.gT[my_slot]));
+            rowU[tid] = fminf(rowU[tid], __uint_as_float(a.gU[my_slot]));
+        }
+        if (a.prune) {
+            const float umax = block_max(sh, my_valid ? rowU[tid] : 0.f);
+            const double lb2 = ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE, a.d);
+            if (lb2 > (double)umax) continue;
+        }
         const bool masked = (ncols < BN) || !(hi_c < lo_r || lo_c > hi_r);
         __syncthreads();
         // stage the column chunk into LDS in fragment order
@@ -205,6 +235,8 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         }
         colcomp[tid] = (tid < ncols) ? a.compS[c0 + tid] : -1;
         __syncthreads();
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) Treg[rb] = rowT[wave * RB * 16 + rb * 16 + (lane & 15)];
         pairs += (unsigned long long)ncols;
 
         const int nblk = (ncols + 15) >> 4;
@@ -259,7 +291,15 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                                     if (kth < __builtin_huge_valf()) {
                                         const double U = upper_from_t((double)kth, rowEps[rl], rowEta[rl], exact);
                                         const float T = thresh_from_U(U, rowEps[rl], rowEta[rl], exact);
-                                        if (T < rowT[rl]) rowT[rl] = T;
+                                        const float Us = d2f_up(exact ? U : U * inv_s2 * (1.0 + 0x1p-40));
+                                        if (T < rowT[rl]) {
+                                            rowT[rl] = T;
+                                            if (a.share) atomicMin(&a.gT[slot], __float_as_uint(T));
+                                        }
+                                        if (Us < rowU[rl]) {
+                                            rowU[rl] = Us;
+                                            if (a.share) atomicMin(&a.gU[slot], __float_as_uint(Us));
+                                        }
                                     }
                                 }
                             }
@@ -274,7 +314,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
             }
         }
     }
-    if (tid == 0 && a.pairs) atomicAdd(a.pairs, pairs * (unsigned long long)tileRows);
+    if (tid == 0 && a.pairs) atomicAdd(a.pairs, pairs * (unsigned long long)sh.rows);
 }
 
 }  // namespace

@@ -19,7 +19,7 @@
 #include <chrono>
 #include <vector>
 
-#include "nnm_common.h"
+#include "cand_common.h"
 
 namespace nnm {
 namespace {
@@ -45,6 +45,7 @@ struct Plan {
     int64_t rmax = 0;               // rows per candidate launch
     int op_bytes = 64;
     bool mst = true;
+    int L1 = 1, L2 = 1;             // fine / coarse landmarks of the spatial order
 };
 
 struct WS {
@@ -63,6 +64,11 @@ struct WS {
     int32_t* overflow_list;
     SortRec* edges; SortRec* srtA; SortRec* srtB;
     void* scan_temp; void* radix_temp;
+    int32_t* perm0; int32_t* rank0; int32_t* ckey; int32_t* flag; int32_t* excl;
+    float* balls;
+    uint32_t* gT; uint32_t* gU;
+    void* spatial_temp;
+    double* u0b; int32_t* oflag; int32_t* olist; int32_t* rep_pos; int32_t* rflag2;
 };
 
 struct Carver {
@@ -120,6 +126,20 @@ size_t carve(const Plan& p, void* base, WS* w)
     w->srtB = c.take<SortRec>(n);
     w->scan_temp = c.take<char>(scan_temp_bytes((int64_t)n));
     w->radix_temp = c.take<char>(radix_temp_bytes((int64_t)n));
+    w->perm0 = c.take<int32_t>(n);
+    w->rank0 = c.take<int32_t>(n);
+    w->ckey = c.take<int32_t>(n);
+    w->flag = c.take<int32_t>(n);
+    w->excl = c.take<int32_t>(n);
+    w->balls = c.take<float>((n + CHUNK - 1) / CHUNK * BALL_STRIDE);
+    w->gT = c.take<uint32_t>((size_t)p.rmax);
+    w->gU = c.take<uint32_t>((size_t)p.rmax);
+    w->spatial_temp = c.take<char>(spatial_temp_bytes((int64_t)n, p.L1, p.L2));
+    w->u0b = c.take<double>(n);
+    w->oflag = c.take<int32_t>(n);
+    w->olist = c.take<int32_t>(n);
+    w->rep_pos = c.take<int32_t>(n);
+    w->rflag2 = c.take<int32_t>(n);
     return c.off + 256;
 }
 
@@ -161,6 +181,14 @@ nnm_status plan_common(int64_t n, int32_t d, int32_t k, const nnm_options* opt, 
     if (rmax > n) rmax = n;
     if (rmax < 1) rmax = 1;
     p->rmax = rmax;
+    int64_t l1 = n / 384;
+    if (l1 < 1) l1 = 1;
+    if (l1 > 16384) l1 = 16384;
+    int64_t l2 = (int64_t)llround(sqrt((double)l1));
+    if (l2 < 1) l2 = 1;
+    if (l2 > 256) l2 = 256;
+    p->L1 = (int)l1;
+    p->L2 = (int)l2;
     return NNM_OK;
 }
 
@@ -323,21 +351,27 @@ MergeArgs merge_args(Run& R)
     return m;
 }
 
-// Order points by component; gather the operands in that order.
-nnm_status sort_points(Run& R, const float* X, bool identity)
+// Order points by component (components by their earliest spatial position,
+// members by spatial position); gather the operands in that order and
+// compute the bounding ball of every chunk.
+nnm_status sort_points(Run& R, const float* X)
 {
     Plan& p = R.p;
     WS& w = R.w;
-    HIP_TRY(launch_comp_records(w.comp, p.n, w.srtA, R.s));
-    SortRec* res = w.srtA;
-    if (!identity) {
-        const int fields[1] = {1};
-        const int bits[1] = {std::max(ceil_log2(p.n), 1)};
-        HIP_TRY(launch_radix_sort(w.srtA, w.srtB, p.n, fields, bits, 1, w.radix_temp, &res, R.s));
-    }
-    HIP_TRY(launch_perm_from_records(res, p.n, w.perm, R.s));
+    HIP_TRY(launch_component_order(w.comp, w.perm0, w.rank0, p.n, w.ckey, w.srtA, w.srtB, w.perm,
+                                   w.compS, w.flag, w.excl, w.radix_temp, w.scan_temp, R.s));
     HIP_TRY(launch_gather_points(p.n, p.opkind, w.perm, w.opR, w.opC, w.pc, X, p.d, p.ld, w.comp,
                                  w.opRs, w.opCs, w.pcs, w.xs, w.compS, R.s));
+    HIP_TRY(launch_chunk_balls(X, p.n, p.d, p.ld, w.perm, CHUNK, w.balls, R.s));
+    return NNM_OK;
+}
+
+nnm_status spatial_order(Run& R, const float* X)
+{
+    Plan& p = R.p;
+    WS& w = R.w;
+    HIP_TRY(launch_spatial_order(X, p.n, p.d, p.ld, p.L1, p.L2, w.perm0, w.rank0, w.srtA, w.srtB,
+                                 w.spatial_temp, R.s));
     return NNM_OK;
 }
 
@@ -354,79 +388,131 @@ int pick_splits(const Run& R, int64_t rows)
     return (int)want;
 }
 
-// Candidate pass + FP64 rescoring for rows rlist[0..count) (sorted positions).
+// One candidate launch + FP64 rescoring for nb rows (a row list of sorted
+// positions, or row0 + slot).  level 1: overflowed rows are flagged in
+// w.oflag with a bound in w.u0b; level 2: they get the exact full scan.
+nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0, int64_t nb,
+                      const double* u0, int level, int32_t* n_over)
+{
+    Plan& p = R.p;
+    WS& w = R.w;
+    HIP_TRY(hipMemsetAsync(w.surv_cnt, 0, sizeof(int32_t) * (size_t)nb, R.s));
+    CandArgs a{};
+    a.opR = w.opRs;
+    a.opC = w.opCs;
+    a.xs = w.xs;
+    a.pc = w.pcs;
+    a.compS = w.compS;
+    a.rows = rows;
+    a.row0 = row0;
+    a.u0 = u0;
+    a.n_rows = (int32_t)nb;
+    a.np = (int32_t)p.n;
+    a.d = p.d;
+    a.k = p.k;
+    a.S = p.S;
+    a.col_splits = pick_splits(R, nb);
+    a.bc = R.bc;
+    a.surv_cnt = w.surv_cnt;
+    a.surv_j = w.surv_j;
+    a.surv_t = w.surv_t;
+    a.pairs = &w.ctr->pairs;
+    a.X = X;
+    a.ld = p.ld;
+    a.perm = w.perm;
+    a.balls = w.balls;
+    a.prune = R.o.disable_prune ? 0 : 1;
+    a.share = a.col_splits > 1 ? 1 : 0;
+    a.gT = w.gT;
+    a.gU = w.gU;
+    if (a.share) {
+        HIP_TRY(launch_fill_i32((int32_t*)w.gT, 0x7F800000, nb, R.s));
+        HIP_TRY(launch_fill_i32((int32_t*)w.gU, 0x7F800000, nb, R.s));
+    }
+    {
+        Timer t(R.rep != nullptr, R.s, R.rep ? &R.rep->ms_candidates : nullptr);
+        if (p.opkind == OP_FP32) HIP_TRY(launch_cand_fp32(a, R.s));
+        else HIP_TRY(launch_cand_mfma(p.opkind, a, R.s));
+    }
+    RescoreArgs r{};
+    r.X = X;
+    r.ld = p.ld;
+    r.d = p.d;
+    r.n_rows = (int32_t)nb;
+    r.k = p.k;
+    r.S = p.S;
+    r.rows = rows;
+    r.row0 = row0;
+    r.perm = w.perm;
+    r.comp = w.comp;
+    r.surv_cnt = w.surv_cnt;
+    r.surv_j = w.surv_j;
+    r.surv_t = w.surv_t;
+    r.u0 = u0;
+    r.inv_sigma2 = 1.0 / (double)R.bc.sigma2;
+    r.sigma2 = R.bc.sigma2;
+    r.force_fallback = R.o.force_fallback;
+    r.np = p.n;
+    r.cidx = w.cidx;
+    r.cs = w.cs;
+    r.clen = w.clen;
+    r.ccur = w.ccur;
+    r.clb = w.clb;
+    r.cflag = w.cflag;
+    r.overflow_rows = &w.ctr->over;
+    r.level = level;
+    // the tree only needs exact prefixes, so an overflowed row is re-scanned
+    // below its 4th key; knn_build needs all k
+    r.kb = p.mst ? std::min(p.k, 4) : p.k;
+    r.u0b = w.u0b;
+    r.oflag = w.oflag;
+    r.survivors = &w.ctr->survivors;
+    r.err_bits = w.ctr->err_bits;
+    int32_t over = 0;
+    {
+        Timer t(R.rep != nullptr, R.s, R.rep ? &R.rep->ms_rescore : nullptr);
+        HIP_TRY(hipMemsetAsync(&w.ctr->over, 0, sizeof(int32_t), R.s));
+        HIP_TRY(launch_rescore(r, w.overflow_list, R.s));
+        HIP_TRY(hipMemcpyAsync(&over, &w.ctr->over, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
+        HIP_TRY(hipStreamSynchronize(R.s));
+        // rows sent straight to the exact scan
+        if (over > 0 && (level == 2 || R.o.force_fallback))
+            HIP_TRY(launch_fallback(r, w.overflow_list, over, R.s));
+    }
+    if (R.rep) {
+        R.rep->rows_scanned += nb;
+        R.rep->cand_launches += 1;
+        if (level == 2 || R.o.force_fallback) R.rep->overflow_rows += over;
+    }
+    *n_over = over;
+    return NNM_OK;
+}
+
+// Candidate pass + FP64 rescoring for rows rows[0..count) (sorted positions,
+// ascending) or, with rows == NULL, for positions 0..count-1.
 nnm_status scan_rows(Run& R, const float* X, const int32_t* rows, int64_t count, bool use_u0)
 {
     Plan& p = R.p;
     WS& w = R.w;
     for (int64_t b0 = 0; b0 < count; b0 += p.rmax) {
         const int64_t nb = std::min<int64_t>(p.rmax, count - b0);
-        HIP_TRY(hipMemsetAsync(w.surv_cnt, 0, sizeof(int32_t) * (size_t)nb, R.s));
-        CandArgs a{};
-        a.opR = w.opRs;
-        a.opC = w.opCs;
-        a.xs = w.xs;
-        a.pc = w.pcs;
-        a.compS = w.compS;
-        a.rows = rows ? rows + b0 : nullptr;
-        a.row0 = rows ? 0 : (int32_t)b0;
-        a.u0 = use_u0 ? w.u0s : nullptr;
-        a.n_rows = (int32_t)nb;
-        a.np = (int32_t)p.n;
-        a.d = p.d;
-        a.k = p.k;
-        a.S = p.S;
-        a.col_splits = pick_splits(R, nb);
-        a.bc = R.bc;
-        a.surv_cnt = w.surv_cnt;
-        a.surv_j = w.surv_j;
-        a.surv_t = w.surv_t;
-        a.pairs = &w.ctr->pairs;
-        {
-            Timer t(R.rep != nullptr, R.s, R.rep ? &R.rep->ms_candidates : nullptr);
-            if (p.opkind == OP_FP32) HIP_TRY(launch_cand_fp32(a, R.s));
-            else HIP_TRY(launch_cand_mfma(p.opkind, a, R.s));
-        }
-        RescoreArgs r{};
-        r.X = X;
-        r.ld = p.ld;
-        r.d = p.d;
-        r.n_rows = (int32_t)nb;
-        r.k = p.k;
-        r.S = p.S;
-        r.rows = a.rows;
-        r.row0 = a.row0;
-        r.perm = w.perm;
-        r.comp = w.comp;
-        r.surv_cnt = w.surv_cnt;
-        r.surv_j = w.surv_j;
-        r.surv_t = w.surv_t;
-        r.u0 = a.u0;
-        r.inv_sigma2 = 1.0 / (double)R.bc.sigma2;
-        r.sigma2 = R.bc.sigma2;
-        r.force_fallback = R.o.force_fallback;
-        r.np = p.n;
-        r.cidx = w.cidx;
-        r.cs = w.cs;
-        r.clen = w.clen;
-        r.ccur = w.ccur;
-        r.clb = w.clb;
-        r.cflag = w.cflag;
-        r.overflow_rows = &w.ctr->over;
-        r.survivors = &w.ctr->survivors;
-        r.err_bits = w.ctr->err_bits;
+        HIP_TRY(launch_fill_i32(w.oflag, 0, p.n, R.s));
         int32_t over = 0;
-        {
-            Timer t(R.rep != nullptr, R.s, R.rep ? &R.rep->ms_rescore : nullptr);
-            HIP_TRY(hipMemsetAsync(&w.ctr->over, 0, sizeof(int32_t), R.s));
-            HIP_TRY(launch_rescore(r, w.overflow_list, R.s));
-            HIP_TRY(hipMemcpyAsync(&over, &w.ctr->over, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
-            HIP_TRY(hipStreamSynchronize(R.s));
-            if (over > 0) HIP_TRY(launch_fallback(r, w.overflow_list, over, R.s));
-        }
-        if (R.rep) {
-            R.rep->overflow_rows += over;
-            R.rep->rows_scanned += nb;
+        nnm_status st = scan_batch(R, X, rows ? rows + b0 : nullptr, rows ? 0 : (int32_t)b0, nb,
+                                   use_u0 ? w.u0s : nullptr, 1, &over);
+        if (st != NNM_OK) return st;
+        if (over == 0 || R.o.force_fallback) continue;
+        // overflowed rows: scan again below the bound their first survivors give
+        int32_t on = 0;
+        HIP_TRY(launch_compact(w.oflag, p.n, w.olist, &w.ctr->rcount, w.scan_temp, R.s));
+        HIP_TRY(hipMemcpyAsync(&on, &w.ctr->rcount, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
+        HIP_TRY(hipStreamSynchronize(R.s));
+        if (R.rep) R.rep->rescanned_bounded += on;
+        for (int64_t c0 = 0; c0 < on; c0 += p.rmax) {
+            const int64_t nc = std::min<int64_t>(p.rmax, on - c0);
+            int32_t over2 = 0;
+            st = scan_batch(R, X, w.olist + c0, 0, nc, w.u0b, 2, &over2);
+            if (st != NNM_OK) return st;
         }
     }
     return NNM_OK;
@@ -523,7 +609,9 @@ nnm_status knn_round(Run& R, const float* X)
 {
     MergeArgs m = merge_args(R);
     HIP_TRY(launch_init_points(m, R.s));
-    nnm_status st = sort_points(R, X, true);
+    nnm_status st = spatial_order(R, X);
+    if (st != NNM_OK) return st;
+    st = sort_points(R, X);
     if (st != NNM_OK) return st;
     // every row, no bound: exact k-nearest-neighbour prefixes
     return scan_rows(R, X, nullptr, R.p.n, false);
@@ -574,6 +662,11 @@ extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_
         Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
         HIP_TRY(launch_init_points(m, R.s));
     }
+    {
+        Timer t(rep != nullptr, R.s, rep ? &rep->ms_sort : nullptr);
+        st = spatial_order(R, X_dev);
+        if (st != NNM_OK) return st;
+    }
     int64_t ncomp = n;
     int round = 0;
     Counters hc;
@@ -582,7 +675,7 @@ extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_
         if (rep && round < 32) rep->comps_per_round[round] = ncomp;
         {
             Timer t(rep != nullptr, R.s, rep ? &rep->ms_sort : nullptr);
-            st = sort_points(R, X_dev, round == 0);
+            st = sort_points(R, X_dev);
             if (st != NNM_OK) return st;
         }
         int32_t rcount = 0;
@@ -596,7 +689,33 @@ extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_
             HIP_TRY(hipMemcpyAsync(&rcount, &w.ctr->rcount, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
             HIP_TRY(hipStreamSynchronize(R.s));
         }
-        if (rep && round < 32) rep->rows_per_round[round] = rcount;
+        if (rcount > 0 && !R.o.disable_prune) {
+            // components without any cached candidate: scan one row of each
+            // first, so that every other row is scanned below a known bound
+            int32_t nrep = 0;
+            {
+                Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
+                HIP_TRY(launch_pick_reps(m, w.compS, w.rep_pos, ncomp, w.rflag2, R.s));
+                HIP_TRY(launch_compact(w.rflag2, n, w.olist, &w.ctr->rcount, w.scan_temp, R.s));
+                HIP_TRY(hipMemcpyAsync(&nrep, &w.ctr->rcount, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
+                HIP_TRY(hipStreamSynchronize(R.s));
+            }
+            if (nrep > 0 && nrep < rcount) {
+                HIP_TRY(hipMemcpyAsync(w.rlist, w.olist, sizeof(int32_t) * (size_t)nrep,
+                                       hipMemcpyDeviceToDevice, R.s));
+                st = scan_rows(R, X_dev, w.rlist, nrep, false);
+                if (st != NNM_OK) return st;
+                if (rep && round < 32) rep->rows_per_round[round] += nrep;
+                Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
+                HIP_TRY(launch_cursor(m, R.s));
+                HIP_TRY(launch_compmin1(m, R.s));
+                HIP_TRY(launch_flag_rescan(m, R.s));
+                HIP_TRY(launch_compact(w.rflag, n, w.rlist, &w.ctr->rcount, w.scan_temp, R.s));
+                HIP_TRY(hipMemcpyAsync(&rcount, &w.ctr->rcount, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
+                HIP_TRY(hipStreamSynchronize(R.s));
+            }
+        }
+        if (rep && round < 32) rep->rows_per_round[round] += rcount;
         if (rcount > 0) {
             st = scan_rows(R, X_dev, w.rlist, rcount, true);
             if (st != NNM_OK) return st;

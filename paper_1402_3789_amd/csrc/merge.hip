@@ -88,6 +88,36 @@ __global__ __launch_bounds__(256) void k_flag_rescan(MergeArgs a)
     a.u0s[p] = u0;
 }
 
+// Flagged rows of components that have no bound yet (every row of such a
+// component is flagged): up to REPS rows evenly spaced along the component's
+// segment of the sorted order (which is spatially ordered) represent it.
+constexpr int REPS = 16;
+
+__global__ __launch_bounds__(256) void k_rep_flags(MergeArgs a, const int32_t* seg,
+                                                   const int32_t* segstart, int64_t nseg,
+                                                   int32_t* flag2)
+{
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    int f = 0;
+    if (a.rflag[p] && a.u0s[p] < 0.0) {
+        const int sg = seg[p];
+        const int64_t st = segstart[sg];
+        const int64_t en = (sg + 1 < nseg) ? segstart[sg + 1] : a.n;
+        int64_t stride = (en - st) / REPS;
+        if (stride < 1) stride = 1;
+        f = ((p - st) % stride == 0) ? 1 : 0;
+    }
+    flag2[p] = f;
+}
+
+__global__ __launch_bounds__(256) void k_seg_starts(const int32_t* seg, int64_t n, int32_t* segstart)
+{
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    if (p == 0 || seg[p] != seg[p - 1]) segstart[seg[p]] = (int32_t)p;
+}
+
 __global__ __launch_bounds__(256) void k_compmin2(MergeArgs a)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -229,6 +259,14 @@ hipError_t launch_hook(const MergeArgs& a, hipStream_t s)
     k_hook<<<g256(a.n), 256, 0, s>>>(a);
     k_break<<<g256(a.n), 256, 0, s>>>(a);
     k_emit<<<g256(a.n), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pick_reps(const MergeArgs& a, const int32_t* seg, int32_t* segstart,
+                            int64_t nseg, int32_t* flag2, hipStream_t s)
+{
+    k_seg_starts<<<g256(a.n), 256, 0, s>>>(seg, a.n, segstart);
+    k_rep_flags<<<g256(a.n), 256, 0, s>>>(a, seg, segstart, nseg, flag2);
     return hipGetLastError();
 }
 

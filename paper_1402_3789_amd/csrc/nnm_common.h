@@ -154,6 +154,16 @@ struct CandArgs {
     int32_t* surv_j;          // [n_rows][S] sorted column positions
     float* surv_t;            // [n_rows][S] candidate values
     unsigned long long* pairs;// accumulated count of evaluated pairs
+    // chunk pruning and near-first order
+    const float* X;           // original features (row-tile balls)
+    int64_t ld;
+    const int32_t* perm;      // sorted position -> point
+    const float* balls;       // [ceil(np / CHUNK)][DMAX + 1]
+    int32_t prune;
+    // thresholds shared by the column splits of one row (float bits)
+    int32_t share;
+    uint32_t* gT;             // [n_rows] candidate-domain threshold
+    uint32_t* gU;             // [n_rows] bound on the key of the k-th neighbour
 };
 
 hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s);
@@ -187,6 +197,10 @@ struct RescoreArgs {
     double* clb;              // [n] lower bound for rows past the list
     int32_t* cflag;           // [n] bit0: list holds every outside point
     int32_t* overflow_rows;   // counter
+    int32_t level;            // 1: overflowed rows get a bound and a re-scan; 2: full scan
+    int32_t kb;               // level 1 bound: the kb-th key of the first S survivors
+    double* u0b;              // [n] by sorted position: bound for the re-scan (level 1)
+    int32_t* oflag;           // [n] by sorted position: row overflowed (level 1)
     unsigned long long* survivors; // counter
     unsigned long long* err_bits;  // [2]: max abs err, max rel err (double bits)
 };
@@ -228,6 +242,8 @@ hipError_t launch_compmin2(const MergeArgs& a, hipStream_t s);
 hipError_t launch_hook(const MergeArgs& a, hipStream_t s);
 hipError_t launch_jump(const MergeArgs& a, int iters, hipStream_t s);
 hipError_t launch_jump_check(const MergeArgs& a, hipStream_t s);
+hipError_t launch_pick_reps(const MergeArgs& a, const int32_t* seg, int32_t* segstart,
+                            int64_t nseg, int32_t* flag2, hipStream_t s);
 hipError_t launch_export_knn(int64_t n, int k, const int32_t* cidx, const double* cs,
                              const int32_t* clen, int32_t* idx, double* sd, int32_t* len,
                              hipStream_t s);
@@ -254,6 +270,18 @@ hipError_t launch_perm_from_records(const SortRec* rec, int64_t n,
 hipError_t launch_write_edges(const SortRec* rec, int64_t ne, nnm_edge* out,
                               hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+// Spatial order, component order and chunk balls (spatial.hip).
+size_t spatial_temp_bytes(int64_t n, int L1, int L2);
+hipError_t launch_spatial_order(const float* X, int64_t n, int d, int64_t ld, int L1, int L2,
+                                int32_t* perm0, int32_t* rank0, SortRec* recA, SortRec* recB,
+                                void* temp, hipStream_t s);
+hipError_t launch_component_order(const int32_t* comp, const int32_t* perm0, const int32_t* rank0,
+                                  int64_t n, int32_t* ckey, SortRec* recA, SortRec* recB,
+                                  int32_t* perm, int32_t* seg, int32_t* flag, int32_t* excl,
+                                  void* radix_temp, void* scan_temp, hipStream_t s);
+hipError_t launch_chunk_balls(const float* X, int64_t n, int d, int64_t ld, const int32_t* perm,
+                              int bn, float* balls, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v,
                            int64_t n, hipStream_t s);
 

@@ -17,6 +17,11 @@ __device__ __forceinline__ void atomic_max_pos_double(unsigned long long* p, dou
     atomicMax(p, (unsigned long long)__double_as_longlong(v));
 }
 
+// A row whose survivor list overflowed keeps its first S survivors, all real
+// columns outside its component: the kb-th smallest exact key among them
+// (kb <= k) bounds the row's kb-th key from above, so the row is
+// scanned again below that bound and gets an exact prefix of at least kb
+// neighbours (level 1).  A row that overflows again goes to the exact scan.
 template <int E>
 __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflow_list)
 {
@@ -27,13 +32,15 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
     const int rp = a.rows ? a.rows[slot] : a.row0 + (int)slot;
     const int i = a.perm[rp];
     const int cnt = a.surv_cnt[slot];
-    if (cnt > a.S || a.force_fallback) {
+    const bool over = cnt > a.S;
+    if (a.force_fallback || (over && a.level == 2)) {
         if (lane == 0) {
             const int pos = atomicAdd(a.overflow_rows, 1);
             overflow_list[pos] = (int)slot;
         }
         return;
     }
+    const int m = over ? a.S : cnt;
     const double u0s = a.u0 ? a.u0[rp] : -1.0;
     const float* xi = a.X + (int64_t)i * a.ld;
     double sv[E];
@@ -45,7 +52,7 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
         sv[e] = __builtin_huge_val();
         jv[e] = 0x7FFFFFFF;
         const int idx = e * 64 + lane;
-        if (idx < cnt) {
+        if (idx < m) {
             const int jp = a.surv_j[slot * a.S + idx];
             const int j = a.perm[jp];
             const double s = sqdist_fp64(xi, a.X + (int64_t)j * a.ld, a.d);
@@ -57,13 +64,18 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
                 rmax = rel > rmax ? rel : rmax;
             }
             ++nsurv;
-            if (u0s < 0.0 || s <= u0s) {
+            if (over || u0s < 0.0 || s <= u0s) {
                 sv[e] = s;
                 jv[e] = j;
             }
         }
     }
     int kept = 0;
+    double last = __builtin_huge_val();
+    // an overflowed row is scanned again below its kb-th key: that still
+    // yields an exact prefix of its neighbour list (at least kb entries)
+    const int kb = a.kb < a.k ? a.kb : a.k;
+    double bound = __builtin_huge_val();
     for (int r = 0; r < a.k; ++r) {
         double bs = __builtin_huge_val();
         int bj = 0x7FFFFFFF;
@@ -82,11 +94,13 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
 #pragma unroll
         for (int e = 0; e < E; ++e)
             if (sv[e] == ws && jv[e] == wj) { sv[e] = __builtin_huge_val(); jv[e] = 0x7FFFFFFF; }
-        if (lane == 0) {
+        if (!over && lane == 0) {
             a.cidx[(int64_t)i * a.k + r] = wj;
             a.cs[(int64_t)i * a.k + r] = ws;
         }
+        last = ws;
         ++kept;
+        if (kept == kb) bound = ws;
     }
     for (int off = 32; off > 0; off >>= 1) {
         const double o1 = __shfl_xor(emax, off);
@@ -95,23 +109,30 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
         rmax = o2 > rmax ? o2 : rmax;
         nsurv += __shfl_xor(nsurv, off);
     }
-    if (lane == 0) {
-        a.clen[i] = kept;
-        a.ccur[i] = 0;
-        if (kept == a.k) {
-            a.clb[i] = a.cs[(int64_t)i * a.k + a.k - 1];
-            a.cflag[i] = 0;
-        } else if (u0s >= 0.0) {
-            a.clb[i] = u0s;
-            a.cflag[i] = 0;
-        } else {
-            a.clb[i] = __builtin_huge_val();
-            a.cflag[i] = 1;
-        }
-        atomicAdd(a.survivors, (unsigned long long)nsurv);
-        atomic_max_pos_double(&a.err_bits[0], emax);
-        atomic_max_pos_double(&a.err_bits[1], rmax);
+    if (lane != 0) return;
+    atomic_max_pos_double(&a.err_bits[0], emax);
+    atomic_max_pos_double(&a.err_bits[1], rmax);
+    if (over) {
+        double b = kept >= kb ? bound : -1.0;
+        if (u0s >= 0.0 && (b < 0.0 || u0s < b)) b = u0s;
+        a.u0b[rp] = b;
+        a.oflag[rp] = 1;
+        atomicAdd(a.overflow_rows, 1);
+        return;
     }
+    a.clen[i] = kept;
+    a.ccur[i] = 0;
+    if (kept == a.k) {
+        a.clb[i] = a.cs[(int64_t)i * a.k + a.k - 1];
+        a.cflag[i] = 0;
+    } else if (u0s >= 0.0) {
+        a.clb[i] = u0s;
+        a.cflag[i] = 0;
+    } else {
+        a.clb[i] = __builtin_huge_val();
+        a.cflag[i] = 1;
+    }
+    atomicAdd(a.survivors, (unsigned long long)nsurv);
 }
 
 // Exact top-k of one row over every point outside its component, by a full

@@ -259,7 +259,6 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, const int32_t* __rest
         opCs[p * W + w] = opC[i * W + w];
     }
     pcs[p] = pc[i];
-    compS[p] = comp[i];
 }
 
 __global__ __launch_bounds__(256) void k_gather_fp32(int64_t n, const int32_t* __restrict__ perm,
@@ -282,7 +281,6 @@ __global__ __launch_bounds__(256) void k_gather_fp32(int64_t n, const int32_t* _
         v.w = (4 * w + 3 < d) ? X[i * ld + 4 * w + 3] : 0.f;
         dst[w] = v;
     }
-    compS[p] = comp[i];
 }
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }

@@ -145,6 +145,16 @@ def test_forced_paths_give_identical_trees(nnm, knob):
         _tree_equal(nnm, X, precision=prec, **kw)
 
 
+def test_overflow_twice_goes_to_exact_scan(nnm):
+    # binary features: hundreds of columns tie at every distance, so even the
+    # bounded re-scan overflows a 64-entry survivor list
+    X = np.random.default_rng(12).integers(0, 2, size=(3000, 6)).astype(np.float32)
+    _say("overflow twice", X.shape)
+    for prec in ("fp16", "fp32", "fp8"):
+        tree, _ = _tree_equal(nnm, X, precision=prec, survivor_cap=64, knn_k=32)
+        assert tree.report["overflow_rows"] > 0 and tree.report["rescanned_bounded"] > 0
+
+
 def test_nonfinite_and_fp8_rejected(nnm):
     X = np.zeros((10, 3), np.float32)
     X[4, 1] = np.nan
