@@ -141,6 +141,9 @@ typedef struct {
     int64_t comps_per_round[32];/* components at the start of each round      */
     int64_t cand_launches;      /* candidate-kernel launches                  */
     int64_t rescanned_bounded;  /* overflowed rows scanned again below a bound */
+    int64_t pairs_per_round[32];/* candidate pairs evaluated in each round    */
+    int64_t over_per_round[32]; /* survivor-list overflows in each round      */
+    int64_t exact_per_round[32];/* rows needing the exact scan in each round  */
 } nnm_report;
 
 /* Fill *opt with the defaults (AUTO precision, k = 16, automatic caps). */
@@ -202,9 +205,14 @@ typedef struct {
 
 /*
  * Many independent instances of uneven n and d in one call; each instance's
- * tree is exactly what mst_build gives for it alone.
- *   inst   [count] host array of instance descriptors;
- *   reps   [count] host reports or NULL.
+ * tree is exactly what mst_build gives for it alone.  The instances are
+ * processed together: one launch per phase of the merge rounds serves all of
+ * them (the paper's aim of keeping the GPU loaded with many uneven tasks,
+ * section "Overall idea of the algorithm").
+ *   inst   [count] host array of instance descriptors (n >= 1, 1 <= d <= 32,
+ *          ld >= d, X_dev non-null, edges_dev non-null when n > 1);
+ *   reps   NULL, or [count] host reports: every entry receives the report of
+ *          the whole call.
  * The workspace must hold mst_batched_workspace_size() bytes.
  */
 nnm_status mst_batched_workspace_size(const nnm_instance *inst, int32_t count,

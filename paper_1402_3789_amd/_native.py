@@ -48,13 +48,16 @@ class Report(ctypes.Structure):
                 ("rows_per_round", ctypes.c_int64 * 32),
                 ("comps_per_round", ctypes.c_int64 * 32),
                 ("cand_launches", ctypes.c_int64),
-                ("rescanned_bounded", ctypes.c_int64)]
+                ("rescanned_bounded", ctypes.c_int64),
+                ("pairs_per_round", ctypes.c_int64 * 32),
+                ("over_per_round", ctypes.c_int64 * 32),
+                ("exact_per_round", ctypes.c_int64 * 32)]
 
     def as_dict(self):
         out = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
-            if name in ("rows_per_round", "comps_per_round"):
+            if name.endswith("_per_round"):
                 v = [int(x) for x in v[: max(self.rounds, 0)]]
             out[name] = v
         out["precision_used"] = PREC_NAME.get(self.precision_used, str(self.precision_used))

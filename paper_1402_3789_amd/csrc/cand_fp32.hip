@@ -37,8 +37,9 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
 
     const int tid = threadIdx.x;
     const int k = a.k;
-    const int64_t slot = (int64_t)blockIdx.x * BM + tid;
-    const bool valid = slot < a.n_rows;
+    const int4 tile = tile_of(a, BM);
+    const int64_t slot = (int64_t)tile.x + tid;
+    const bool valid = slot < tile.y;
     const int rp = valid ? (a.rows ? a.rows[slot] : a.row0 + (int)slot) : 0;
     const double crel = (double)(a.d + 3) * 0x1p-24 + 0x1p-40;
     const double a0 = (double)a.d * 0x1p-148;
@@ -70,9 +71,10 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
     for (int e = 0; e < k; ++e) tk[e] = __builtin_huge_valf();
     if (a.prune) tile_ball<DP>(sh, xr, valid, a.d);
     if (tid == 0) {
-        int64_t last = (int64_t)blockIdx.x * BM + BM - 1;
-        if (last >= a.n_rows) last = a.n_rows - 1;
-        const int64_t first = (int64_t)blockIdx.x * BM;
+        const int64_t last = (int64_t)tile.y - 1;
+        const int64_t first = tile.x;
+        sh.col_lo = tile.z;
+        sh.col_hi = tile.w;
         const int r0 = a.rows ? a.rows[first] : a.row0 + (int)first;
         sh.lo = a.compS[r0];
         sh.hi = a.compS[a.rows ? a.rows[last] : a.row0 + (int)last];
@@ -82,31 +84,20 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
     __syncthreads();
     const int lo_r = sh.lo, hi_r = sh.hi;
 
-    const int nch = (a.np + BN - 1) / BN;
-    const int cps = (nch + a.col_splits - 1) / a.col_splits;
-    const int ch_lo = (int)blockIdx.y * cps;
-    const int ch_hi = ch_lo + cps < nch ? ch_lo + cps : nch;
-    int start = sh.first_pos / BN;
-    start = start < ch_lo ? ch_lo : (start >= ch_hi ? ch_hi - 1 : start);
     unsigned long long pairs = 0;
+    wave_max_store(sh, valid ? U : 0.f);
+    __syncthreads();
+    const float umax0 = fmaxf(fmaxf(sh.wmax[0], sh.wmax[1]), fmaxf(sh.wmax[2], sh.wmax[3]));
 
-    for (int step = 0; step < ch_hi - ch_lo; ++step) {
-        const int ci = zigzag(step, start, ch_lo, ch_hi);
+    sweep_chunks(sh, a, lo_r, hi_r, umax0, [&](int ci, int lo_c, int hi_c) {
         const int64_t c0 = (int64_t)ci * BN;
         const int ncols = (int)((a.np - c0) < BN ? (a.np - c0) : BN);
-        const int lo_c = a.compS[c0];
-        const int hi_c = a.compS[c0 + ncols - 1];
-        if (lo_r == hi_r && lo_c == hi_c && lo_r == lo_c) continue;
+        const int cl = sh.col_lo, ch = sh.col_hi;
+        const bool masked = c0 < cl || c0 + BN > ch || !(hi_c < lo_r || lo_c > hi_r);
         if (a.share && valid) {
             T = fminf(T, __uint_as_float(a.gT[slot]));
             U = fminf(U, __uint_as_float(a.gU[slot]));
         }
-        if (a.prune) {
-            const float umax = block_max(sh, valid ? U : 0.f);
-            const double lb2 = ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE, a.d);
-            if (lb2 > (double)umax) continue;
-        }
-        const bool masked = !(hi_c < lo_r || lo_c > hi_r);
         __syncthreads();
         for (int idx = tid; idx < BN * F4; idx += 256) {
             const int c = idx / F4, q = idx % F4;
@@ -114,7 +105,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
             if (c < ncols) v = reinterpret_cast<const float4*>(a.xs + (c0 + c) * DMAX)[q];
             cbuf[idx] = v;
         }
-        ccomp[tid] = (tid < ncols) ? a.compS[c0 + tid] : -1;
+        ccomp[tid] = (tid < ncols && c0 + tid >= cl && c0 + tid < ch) ? a.compS[c0 + tid] : -1;
         __syncthreads();
         pairs += (unsigned long long)ncols;
         for (int c = 0; c < ncols; ++c) {
@@ -131,7 +122,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
                 t = __builtin_fmaf(d2, d2, t);
                 t = __builtin_fmaf(d3, d3, t);
             }
-            if (masked && ccomp[c] == rc) t = __builtin_huge_valf();
+            if (masked && (ccomp[c] == rc || ccomp[c] < 0)) t = __builtin_huge_valf();
             if (t <= T) {
                 const int pos = atomicAdd(&a.surv_cnt[slot], 1);
                 if (pos < a.S) {
@@ -159,7 +150,8 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
                 }
             }
         }
-    }
+        wave_max_store(sh, valid ? U : 0.f);
+    });
     if (tid == 0 && a.pairs) atomicAdd(a.pairs, pairs * (unsigned long long)sh.rows);
 }
 
@@ -168,7 +160,9 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
 hipError_t launch_cand_fp32(const CandArgs& a, hipStream_t s)
 {
     if (a.n_rows <= 0) return hipSuccess;
-    dim3 grid((unsigned)((a.n_rows + BM - 1) / BM), (unsigned)a.col_splits);
+    const unsigned nt = a.tiles ? (unsigned)a.n_tiles : (unsigned)((a.n_rows + BM - 1) / BM);
+    if (nt == 0) return hipSuccess;
+    dim3 grid(nt, (unsigned)a.col_splits);
     size_t shm = (size_t)BM * a.k * sizeof(float);
     const int dp = (a.d + 3) / 4 * 4;
     switch (dp) {

@@ -117,13 +117,15 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     const int lane = tid & 63;
     const int grp = lane >> 4;
     const int k = a.k;
-    const int64_t row_base = (int64_t)blockIdx.x * BM;
+    const int4 tile = tile_of(a, BM);
+    const int64_t row_base = tile.x;
+    const int64_t row_end = tile.y;
     const int exact = a.bc.exact;
     const double inv_s2 = 1.0 / (double)a.bc.sigma2;
 
     // ---- per-row state (thread t owns row t of the tile) -----------------
     const int64_t my_slot = row_base + tid;
-    const bool my_valid = my_slot < a.n_rows;
+    const bool my_valid = my_slot < row_end;
     const int my_rp = my_valid ? (a.rows ? a.rows[my_slot] : a.row0 + (int)my_slot) : 0;
     {
         float T = -__builtin_huge_valf(), U = 0.f;
@@ -158,14 +160,15 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         tile_ball<DMAX>(sh, x, my_valid, a.d);
     }
     if (tid == 0) {
-        int64_t last = row_base + BM - 1;
-        if (last >= a.n_rows) last = a.n_rows - 1;
+        const int64_t last = row_end - 1;
         const int r0 = a.rows ? a.rows[row_base] : a.row0 + (int)row_base;
         const int r1 = a.rows ? a.rows[last] : a.row0 + (int)last;
         sh.lo = a.compS[r0];
         sh.hi = a.compS[r1];
         sh.rows = (int)(last - row_base + 1);
         sh.first_pos = r0;
+        sh.col_lo = tile.z;
+        sh.col_hi = tile.w;
     }
     // row fragments stay in registers for the whole sweep
     frag_t bfrag[RB];
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     for (int rb = 0; rb < RB; ++rb) {
         const int rl = wave * RB * 16 + rb * 16 + (lane & 15);
         const int64_t slot = row_base + rl;
-        rvalid[rb] = slot < a.n_rows;
+        rvalid[rb] = slot < row_end;
         const int rp = rvalid[rb] ? (a.rows ? a.rows[slot] : a.row0 + (int)slot) : 0;
         const frag_t* src = reinterpret_cast<const frag_t*>(a.opR) + (int64_t)rp * 4 + grp;
         bfrag[rb] = *src;
@@ -188,31 +191,20 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     const int lo_r = sh.lo, hi_r = sh.hi;
 
     // ---- column sweep, nearest chunks first ------------------------------
-    const int nch = (a.np + BN - 1) / BN;
-    const int cps = (nch + a.col_splits - 1) / a.col_splits;
-    const int ch_lo = (int)blockIdx.y * cps;
-    const int ch_hi = ch_lo + cps < nch ? ch_lo + cps : nch;
-    int start = sh.first_pos / BN;
-    start = start < ch_lo ? ch_lo : (start >= ch_hi ? ch_hi - 1 : start);
     unsigned long long pairs = 0;
+    wave_max_store(sh, my_valid ? rowU[tid] : 0.f);
+    __syncthreads();
+    const float umax0 = fmaxf(fmaxf(sh.wmax[0], sh.wmax[1]), fmaxf(sh.wmax[2], sh.wmax[3]));
 
-    for (int step = 0; step < ch_hi - ch_lo; ++step) {
-        const int ci = zigzag(step, start, ch_lo, ch_hi);
+    sweep_chunks(sh, a, lo_r, hi_r, umax0, [&](int ci, int lo_c, int hi_c) {
         const int64_t c0 = (int64_t)ci * BN;
         const int ncols = (int)((a.np - c0) < BN ? (a.np - c0) : BN);
-        const int lo_c = a.compS[c0];
-        const int hi_c = a.compS[c0 + ncols - 1];
-        if (lo_r == hi_r && lo_c == hi_c && lo_r == lo_c) continue;   // all one component
+        const int cl = sh.col_lo, ch = sh.col_hi;
+        const bool masked = (ncols < BN) || c0 < cl || c0 + BN > ch || !(hi_c < lo_r || lo_c > hi_r);
         if (a.share && my_valid) {
             rowT[tid] = fminf(rowT[tid], __uint_as_float(a.gT[my_slot]));
             rowU[tid] = fminf(rowU[tid], __uint_as_float(a.gU[my_slot]));
         }
-        if (a.prune) {
-            const float umax = block_max(sh, my_valid ? rowU[tid] : 0.f);
-            const double lb2 = ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE, a.d);
-            if (lb2 > (double)umax) continue;
-        }
-        const bool masked = (ncols < BN) || !(hi_c < lo_r || lo_c > hi_r);
         __syncthreads();
         // stage the column chunk into LDS in fragment order
         const uint4* gsrc = reinterpret_cast<const uint4*>(a.opC) + c0 * (Tr::BYTES / 16);
@@ -233,7 +225,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                 cb2[((c >> 4) * 4 + 2 * h + 1) * 16 + (c & 15)] = make_uint2(v.z, v.w);
             }
         }
-        colcomp[tid] = (tid < ncols) ? a.compS[c0 + tid] : -1;
+        colcomp[tid] = (tid < ncols && c0 + tid >= cl && c0 + tid < ch) ? a.compS[c0 + tid] : -1;
         __syncthreads();
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) Treg[rb] = rowT[wave * RB * 16 + rb * 16 + (lane & 15)];
@@ -313,7 +305,8 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                 for (int rb = 0; rb < RB; ++rb) Treg[rb] = rowT[wave * RB * 16 + rb * 16 + (lane & 15)];
             }
         }
-    }
+        wave_max_store(sh, my_valid ? rowU[tid] : 0.f);
+    });
     if (tid == 0 && a.pairs) atomicAdd(a.pairs, pairs * (unsigned long long)sh.rows);
 }
 
@@ -322,7 +315,9 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
 hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s)
 {
     if (a.n_rows <= 0) return hipSuccess;
-    dim3 grid((unsigned)((a.n_rows + BM - 1) / BM), (unsigned)a.col_splits);
+    const unsigned nt = a.tiles ? (unsigned)a.n_tiles : (unsigned)((a.n_rows + BM - 1) / BM);
+    if (nt == 0) return hipSuccess;
+    dim3 grid(nt, (unsigned)a.col_splits);
     size_t shm = (size_t)BM * a.k * sizeof(float);
     switch (opkind) {
     case OP_BF16: k_cand_mfma<OP_BF16><<<grid, 256, shm, s>>>(a); break;

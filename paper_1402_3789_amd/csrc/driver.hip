@@ -28,7 +28,8 @@ struct Counters {
     int32_t ctr[8];                 // [0] edges [1] roots [2] jump misses
     int32_t rcount;                 // rows to rescan
     int32_t over;                   // overflowed rows in the last batch
-    int32_t pad_[6];
+    int32_t tcount;                 // tiles of the last batch
+    int32_t pad_[5];
     unsigned long long pairs;
     unsigned long long survivors;
     unsigned long long err_bits[2];
@@ -46,6 +47,7 @@ struct Plan {
     int op_bytes = 64;
     bool mst = true;
     int L1 = 1, L2 = 1;             // fine / coarse landmarks of the spatial order
+    int ninst = 1;                  // instances in the point set (batched calls)
 };
 
 struct WS {
@@ -66,9 +68,12 @@ struct WS {
     void* scan_temp; void* radix_temp;
     int32_t* perm0; int32_t* rank0; int32_t* ckey; int32_t* flag; int32_t* excl;
     float* balls;
+    float* sballs;
     uint32_t* gT; uint32_t* gU;
     void* spatial_temp;
     double* u0b; int32_t* oflag; int32_t* olist; int32_t* rep_pos; int32_t* rflag2;
+    int4* tiles; int32_t* tflag; int32_t* tstart;
+    float* Xcat; int32_t* inst_off; InstDev* inst; nnm_edge** outp;
 };
 
 struct Carver {
@@ -132,6 +137,7 @@ size_t carve(const Plan& p, void* base, WS* w)
     w->flag = c.take<int32_t>(n);
     w->excl = c.take<int32_t>(n);
     w->balls = c.take<float>((n + CHUNK - 1) / CHUNK * BALL_STRIDE);
+    w->sballs = c.take<float>((n + CHUNK * SUPER - 1) / (CHUNK * SUPER) * BALL_STRIDE);
     w->gT = c.take<uint32_t>((size_t)p.rmax);
     w->gU = c.take<uint32_t>((size_t)p.rmax);
     w->spatial_temp = c.take<char>(spatial_temp_bytes((int64_t)n, p.L1, p.L2));
@@ -140,6 +146,14 @@ size_t carve(const Plan& p, void* base, WS* w)
     w->olist = c.take<int32_t>(n);
     w->rep_pos = c.take<int32_t>(n);
     w->rflag2 = c.take<int32_t>(n);
+    w->tiles = c.take<int4>((size_t)p.rmax);
+    w->tflag = c.take<int32_t>((size_t)p.rmax);
+    w->tstart = c.take<int32_t>((size_t)p.rmax);
+    const bool multi = p.ninst > 1;
+    w->Xcat = multi ? c.take<float>(n * (size_t)p.d) : nullptr;
+    w->inst_off = c.take<int32_t>((size_t)p.ninst + 1);
+    w->inst = multi ? c.take<InstDev>((size_t)p.ninst) : nullptr;
+    w->outp = multi ? c.take<nnm_edge*>((size_t)p.ninst) : nullptr;
     return c.off + 256;
 }
 
@@ -234,6 +248,7 @@ struct Run {
     BoundConst bc;
     float sigma = 1.f;
     int splits_opt = 0;
+    int round = 0;          // current merge round (per-round report entries)
 };
 
 int ceil_log2(int64_t v)
@@ -363,6 +378,7 @@ nnm_status sort_points(Run& R, const float* X)
     HIP_TRY(launch_gather_points(p.n, p.opkind, w.perm, w.opR, w.opC, w.pc, X, p.d, p.ld, w.comp,
                                  w.opRs, w.opCs, w.pcs, w.xs, w.compS, R.s));
     HIP_TRY(launch_chunk_balls(X, p.n, p.d, p.ld, w.perm, CHUNK, w.balls, R.s));
+    HIP_TRY(launch_chunk_balls(X, p.n, p.d, p.ld, w.perm, CHUNK * SUPER, w.sballs, R.s));
     return NNM_OK;
 }
 
@@ -372,6 +388,9 @@ nnm_status spatial_order(Run& R, const float* X)
     WS& w = R.w;
     HIP_TRY(launch_spatial_order(X, p.n, p.d, p.ld, p.L1, p.L2, w.perm0, w.rank0, w.srtA, w.srtB,
                                  w.spatial_temp, R.s));
+    if (p.ninst > 1)
+        HIP_TRY(launch_instance_major(w.perm0, w.rank0, w.inst_off, p.ninst, p.n, w.srtA, w.srtB,
+                                      w.radix_temp, R.s));
     return NNM_OK;
 }
 
@@ -392,7 +411,7 @@ int pick_splits(const Run& R, int64_t rows)
 // positions, or row0 + slot).  level 1: overflowed rows are flagged in
 // w.oflag with a bound in w.u0b; level 2: they get the exact full scan.
 nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0, int64_t nb,
-                      const double* u0, int level, int32_t* n_over)
+                      const double* u0, bool final_pass, int32_t* n_over)
 {
     Plan& p = R.p;
     WS& w = R.w;
@@ -412,6 +431,18 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     a.k = p.k;
     a.S = p.S;
     a.col_splits = pick_splits(R, nb);
+    if (p.ninst > 1) {
+        // tiles never mix instances; each pairs only with its own instance
+        int32_t nt = 0;
+        HIP_TRY(launch_tiles(rows, row0, nb, w.inst_off, p.ninst, 256, w.tflag, w.tstart,
+                             &w.ctr->tcount, w.scan_temp, R.s));
+        HIP_TRY(hipMemcpyAsync(&nt, &w.ctr->tcount, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
+        HIP_TRY(hipStreamSynchronize(R.s));
+        HIP_TRY(launch_tile_desc(w.tstart, nt, rows, row0, nb, w.inst_off, p.ninst, 256, w.tiles, R.s));
+        a.tiles = w.tiles;
+        a.n_tiles = nt;
+        a.col_splits = pick_splits(R, (int64_t)nt * 256);
+    }
     a.bc = R.bc;
     a.surv_cnt = w.surv_cnt;
     a.surv_j = w.surv_j;
@@ -421,6 +452,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     a.ld = p.ld;
     a.perm = w.perm;
     a.balls = w.balls;
+    a.sballs = w.sballs;
     a.prune = R.o.disable_prune ? 0 : 1;
     a.share = a.col_splits > 1 ? 1 : 0;
     a.gT = w.gT;
@@ -460,7 +492,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     r.clb = w.clb;
     r.cflag = w.cflag;
     r.overflow_rows = &w.ctr->over;
-    r.level = level;
+    r.level = final_pass ? 2 : 1;
     // the tree only needs exact prefixes, so an overflowed row is re-scanned
     // below its 4th key; knn_build needs all k
     r.kb = p.mst ? std::min(p.k, 4) : p.k;
@@ -476,20 +508,31 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
         HIP_TRY(hipMemcpyAsync(&over, &w.ctr->over, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
         HIP_TRY(hipStreamSynchronize(R.s));
         // rows sent straight to the exact scan
-        if (over > 0 && (level == 2 || R.o.force_fallback))
+        if (over > 0 && (final_pass || R.o.force_fallback))
             HIP_TRY(launch_fallback(r, w.overflow_list, over, R.s));
     }
     if (R.rep) {
         R.rep->rows_scanned += nb;
         R.rep->cand_launches += 1;
-        if (level == 2 || R.o.force_fallback) R.rep->overflow_rows += over;
+        const int rd = R.round < 32 ? R.round : 31;
+        if (final_pass || R.o.force_fallback) {
+            R.rep->overflow_rows += over;
+            R.rep->exact_per_round[rd] += over;
+        } else {
+            R.rep->over_per_round[rd] += over;
+        }
     }
     *n_over = over;
     return NNM_OK;
 }
 
 // Candidate pass + FP64 rescoring for rows rows[0..count) (sorted positions,
-// ascending) or, with rows == NULL, for positions 0..count-1.
+// ascending) or, with rows == NULL, for positions 0..count-1.  Rows whose
+// survivor list overflows are scanned again below the bound their first
+// survivors give (each pass tightens it); after OVER_PASSES such passes the
+// rest get the exact full-row scan.
+constexpr int OVER_PASSES = 4;
+
 nnm_status scan_rows(Run& R, const float* X, const int32_t* rows, int64_t count, bool use_u0)
 {
     Plan& p = R.p;
@@ -499,20 +542,25 @@ nnm_status scan_rows(Run& R, const float* X, const int32_t* rows, int64_t count,
         HIP_TRY(launch_fill_i32(w.oflag, 0, p.n, R.s));
         int32_t over = 0;
         nnm_status st = scan_batch(R, X, rows ? rows + b0 : nullptr, rows ? 0 : (int32_t)b0, nb,
-                                   use_u0 ? w.u0s : nullptr, 1, &over);
+                                   use_u0 ? w.u0s : nullptr, false, &over);
         if (st != NNM_OK) return st;
-        if (over == 0 || R.o.force_fallback) continue;
-        // overflowed rows: scan again below the bound their first survivors give
-        int32_t on = 0;
-        HIP_TRY(launch_compact(w.oflag, p.n, w.olist, &w.ctr->rcount, w.scan_temp, R.s));
-        HIP_TRY(hipMemcpyAsync(&on, &w.ctr->rcount, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
-        HIP_TRY(hipStreamSynchronize(R.s));
-        if (R.rep) R.rep->rescanned_bounded += on;
-        for (int64_t c0 = 0; c0 < on; c0 += p.rmax) {
-            const int64_t nc = std::min<int64_t>(p.rmax, on - c0);
-            int32_t over2 = 0;
-            st = scan_batch(R, X, w.olist + c0, 0, nc, w.u0b, 2, &over2);
-            if (st != NNM_OK) return st;
+        for (int pass = 1; over > 0 && !R.o.force_fallback; ++pass) {
+            // overflowed rows (flagged in oflag, bound in u0b): scan again
+            int32_t on = 0;
+            HIP_TRY(launch_compact(w.oflag, p.n, w.olist, &w.ctr->rcount, w.scan_temp, R.s));
+            HIP_TRY(hipMemcpyAsync(&on, &w.ctr->rcount, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
+            HIP_TRY(hipStreamSynchronize(R.s));
+            HIP_TRY(launch_fill_i32(w.oflag, 0, p.n, R.s));
+            if (R.rep) R.rep->rescanned_bounded += on;
+            const bool final_pass = pass >= OVER_PASSES;
+            over = 0;
+            for (int64_t c0 = 0; c0 < on; c0 += p.rmax) {
+                const int64_t nc = std::min<int64_t>(p.rmax, on - c0);
+                int32_t o2 = 0;
+                st = scan_batch(R, X, w.olist + c0, 0, nc, w.u0b, final_pass, &o2);
+                if (st != NNM_OK) return st;
+                if (!final_pass) over += o2;
+            }
         }
     }
     return NNM_OK;
@@ -643,20 +691,17 @@ extern "C" nnm_status knn_build(const float* X_dev, int64_t n, int32_t d, int64_
     return finish_report(R, t0);
 }
 
-extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_t ld,
-                                const nnm_options* opt, void* ws_dev, size_t ws_bytes,
-                                nnm_edge* edges_dev, void* stream, nnm_report* rep)
+namespace {
+
+// Merge rounds until every instance is one component; the n - ninst tree
+// edges are left (unsorted) in w.edges.
+nnm_status mst_rounds(Run& R, const float* X)
 {
-    auto t0 = std::chrono::steady_clock::now();
-    if (n > 1 && !edges_dev) return NNM_EINVAL;
-    Run R;
-    nnm_status st = begin(R, X_dev, n, d, ld, 0, opt, ws_dev, ws_bytes, stream, rep, true);
-    if (st != NNM_OK) return st;
-    st = stage(R, X_dev);
-    if (st != NNM_OK) return st;
-    if (n == 1) return finish_report(R, t0);
     Plan& p = R.p;
     WS& w = R.w;
+    nnm_report* rep = R.rep;
+    const int64_t n = p.n;
+    nnm_status st;
     MergeArgs m = merge_args(R);
     {
         Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
@@ -664,18 +709,21 @@ extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_
     }
     {
         Timer t(rep != nullptr, R.s, rep ? &rep->ms_sort : nullptr);
-        st = spatial_order(R, X_dev);
+        st = spatial_order(R, X);
         if (st != NNM_OK) return st;
     }
     int64_t ncomp = n;
     int round = 0;
     Counters hc;
-    for (; ncomp > 1; ++round) {
+    memset(&hc, 0, sizeof(hc));
+    unsigned long long pairs_before = 0;
+    for (; ncomp > p.ninst; ++round) {
         if (round >= 64) return NNM_EDEVICE;   // cannot happen: components at least halve
+        R.round = round;
         if (rep && round < 32) rep->comps_per_round[round] = ncomp;
         {
             Timer t(rep != nullptr, R.s, rep ? &rep->ms_sort : nullptr);
-            st = sort_points(R, X_dev);
+            st = sort_points(R, X);
             if (st != NNM_OK) return st;
         }
         int32_t rcount = 0;
@@ -690,8 +738,9 @@ extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_
             HIP_TRY(hipStreamSynchronize(R.s));
         }
         if (rcount > 0 && !R.o.disable_prune) {
-            // components without any cached candidate: scan one row of each
-            // first, so that every other row is scanned below a known bound
+            // components without any cached candidate: scan a few spread-out
+            // rows of each first, so that every other row is scanned below a
+            // known bound
             int32_t nrep = 0;
             {
                 Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
@@ -703,7 +752,7 @@ extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_
             if (nrep > 0 && nrep < rcount) {
                 HIP_TRY(hipMemcpyAsync(w.rlist, w.olist, sizeof(int32_t) * (size_t)nrep,
                                        hipMemcpyDeviceToDevice, R.s));
-                st = scan_rows(R, X_dev, w.rlist, nrep, false);
+                st = scan_rows(R, X, w.rlist, nrep, false);
                 if (st != NNM_OK) return st;
                 if (rep && round < 32) rep->rows_per_round[round] += nrep;
                 Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
@@ -717,7 +766,7 @@ extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_
         }
         if (rep && round < 32) rep->rows_per_round[round] += rcount;
         if (rcount > 0) {
-            st = scan_rows(R, X_dev, w.rlist, rcount, true);
+            st = scan_rows(R, X, w.rlist, rcount, true);
             if (st != NNM_OK) return st;
         }
         {
@@ -744,46 +793,156 @@ extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_
         const int64_t next = hc.ctr[1];
         if (next >= ncomp) return NNM_EDEVICE;   // no progress: cannot happen
         ncomp = next;
+        if (rep && round < 32) {
+            rep->pairs_per_round[round] = (int64_t)(hc.pairs - pairs_before);
+            pairs_before = hc.pairs;
+        }
     }
-    if (hc.ctr[0] != n - 1) return NNM_EDEVICE;
+    if (ncomp != p.ninst || (int64_t)hc.ctr[0] != n - p.ninst) return NNM_EDEVICE;
+    if (rep) rep->rounds = round;
+    return NNM_OK;
+}
+
+// Sort the n - ninst collected edges by key (s, u, v); returns the sorted buffer.
+nnm_status sort_edges(Run& R, SortRec** res)
+{
+    const int64_t ne = R.p.n - R.p.ninst;
+    const int lg = std::max(ceil_log2(R.p.n), 1);
+    const int fields[3] = {2, 1, 0};
+    const int bits[3] = {lg, lg, 64};
+    HIP_TRY(launch_radix_sort(R.w.edges, R.w.srtA, ne, fields, bits, 3, R.w.radix_temp, res, R.s));
+    return NNM_OK;
+}
+
+}  // namespace
+
+extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_t ld,
+                                const nnm_options* opt, void* ws_dev, size_t ws_bytes,
+                                nnm_edge* edges_dev, void* stream, nnm_report* rep)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (n > 1 && !edges_dev) return NNM_EINVAL;
+    Run R;
+    nnm_status st = begin(R, X_dev, n, d, ld, 0, opt, ws_dev, ws_bytes, stream, rep, true);
+    if (st != NNM_OK) return st;
+    st = stage(R, X_dev);
+    if (st != NNM_OK) return st;
+    if (n == 1) return finish_report(R, t0);
+    const int32_t off[2] = {0, (int32_t)n};
+    HIP_TRY(hipMemcpyAsync(R.w.inst_off, off, sizeof(off), hipMemcpyHostToDevice, R.s));
+    st = mst_rounds(R, X_dev);
+    if (st != NNM_OK) return st;
     {
         Timer t(rep != nullptr, R.s, rep ? &rep->ms_sort : nullptr);
-        const int lg = std::max(ceil_log2(n), 1);
-        const int fields[3] = {2, 1, 0};
-        const int bits[3] = {lg, lg, 64};
         SortRec* res = nullptr;
-        HIP_TRY(launch_radix_sort(w.edges, w.srtA, n - 1, fields, bits, 3, w.radix_temp, &res, R.s));
+        st = sort_edges(R, &res);
+        if (st != NNM_OK) return st;
         HIP_TRY(launch_write_edges(res, n - 1, edges_dev, R.s));
         HIP_TRY(hipStreamSynchronize(R.s));
     }
-    if (rep) rep->rounds = round;
     return finish_report(R, t0);
 }
+
+namespace {
+
+nnm_status batched_plan(const nnm_instance* inst, int32_t count, const nnm_options* opt,
+                        Plan* p, int64_t* ntot, int32_t* dmax)
+{
+    if (!inst || count < 1) return NNM_EINVAL;
+    int64_t tot = 0;
+    int32_t dm = 1;
+    for (int32_t b = 0; b < count; ++b) {
+        if (inst[b].n < 1 || inst[b].d < 1 || inst[b].d > DMAX || inst[b].ld < inst[b].d) return NNM_EINVAL;
+        if (!inst[b].X_dev || (inst[b].n > 1 && !inst[b].edges_dev)) return NNM_EINVAL;
+        tot += inst[b].n;
+        dm = std::max(dm, inst[b].d);
+    }
+    if (tot > (int64_t)0x7FFFFFF0) return NNM_EINVAL;
+    nnm_status st = plan_common(tot, dm, 0, opt, true, p);
+    if (st != NNM_OK) return st;
+    p->ninst = count;
+    p->ld = dm;
+    *ntot = tot;
+    *dmax = dm;
+    return NNM_OK;
+}
+
+}  // namespace
 
 extern "C" nnm_status mst_batched_workspace_size(const nnm_instance* inst, int32_t count,
                                                  const nnm_options* opt, size_t* bytes)
 {
-    if (!inst || count < 0 || !bytes) return NNM_EINVAL;
-    size_t need = 0;
-    for (int32_t b = 0; b < count; ++b) {
-        size_t one = 0;
-        nnm_status st = mst_workspace_size(inst[b].n, inst[b].d, opt, &one);
-        if (st != NNM_OK) return st;
-        need = std::max(need, one);
-    }
-    *bytes = need;
+    if (!bytes) return NNM_EINVAL;
+    if (count == 0) { *bytes = 0; return NNM_OK; }
+    Plan p;
+    int64_t tot;
+    int32_t dm;
+    nnm_status st = batched_plan(inst, count, opt, &p, &tot, &dm);
+    if (st != NNM_OK) return st;
+    WS w;
+    *bytes = carve(p, nullptr, &w);
     return NNM_OK;
 }
 
+// All instances are concatenated into one point set (features zero-padded to
+// the widest instance, which leaves every FP64 key bit-identical), kept
+// contiguous in every order the rounds use, and every tile of rows pairs only
+// with its own instance's columns.  One launch per phase serves all
+// instances; the rounds stop when every instance is a single tree.
 extern "C" nnm_status mst_build_batched(const nnm_instance* inst, int32_t count,
                                         const nnm_options* opt, void* ws_dev, size_t ws_bytes,
                                         void* stream, nnm_report* reps)
 {
-    if (!inst || count < 0) return NNM_EINVAL;
+    auto t0 = std::chrono::steady_clock::now();
+    if (count == 0) return NNM_OK;
+    if (!ws_dev) return NNM_EINVAL;
+    Run R;
+    int64_t tot;
+    int32_t dm;
+    nnm_status st = batched_plan(inst, count, opt, &R.p, &tot, &dm);
+    if (st != NNM_OK) return st;
+    nnm_default_options(&R.o);
+    if (opt) R.o = *opt;
+    const size_t need = carve(R.p, nullptr, &R.w);
+    if (ws_bytes < need) return NNM_EINVAL;
+    carve(R.p, ws_dev, &R.w);
+    R.s = (hipStream_t)stream;
+    nnm_report rep0;
+    memset(&rep0, 0, sizeof(rep0));
+    R.rep = reps ? &rep0 : nullptr;
+    std::vector<int32_t> off(count + 1, 0);
+    std::vector<InstDev> hin(count);
+    std::vector<nnm_edge*> outp(count);
     for (int32_t b = 0; b < count; ++b) {
-        nnm_status st = mst_build(inst[b].X_dev, inst[b].n, inst[b].d, inst[b].ld, opt, ws_dev,
-                                  ws_bytes, inst[b].edges_dev, stream, reps ? reps + b : nullptr);
-        if (st != NNM_OK) return st;
+        off[b + 1] = off[b] + (int32_t)inst[b].n;
+        hin[b].X = inst[b].X_dev;
+        hin[b].ld = inst[b].ld;
+        hin[b].d = inst[b].d;
+        hin[b].pad_ = 0;
+        outp[b] = inst[b].edges_dev;
     }
+    HIP_TRY(hipMemcpyAsync(R.w.inst_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, R.s));
+    HIP_TRY(hipMemcpyAsync(R.w.inst, hin.data(), sizeof(InstDev) * hin.size(), hipMemcpyHostToDevice, R.s));
+    HIP_TRY(hipMemcpyAsync(R.w.outp, outp.data(), sizeof(nnm_edge*) * outp.size(), hipMemcpyHostToDevice, R.s));
+    HIP_TRY(launch_concat(R.w.inst, R.w.inst_off, count, tot, dm, R.w.Xcat, R.s));
+    const float* X = R.w.Xcat;
+    st = stage(R, X);
+    if (st != NNM_OK) return st;
+    if (tot > count) {
+        st = mst_rounds(R, X);
+        if (st != NNM_OK) return st;
+        Timer t(R.rep != nullptr, R.s, R.rep ? &R.rep->ms_sort : nullptr);
+        SortRec* res = nullptr;
+        st = sort_edges(R, &res);
+        if (st != NNM_OK) return st;
+        SortRec* other = (res == R.w.srtA) ? R.w.edges : R.w.srtA;
+        HIP_TRY(launch_write_edges_batched(res, tot - count, R.w.inst_off, count, other, R.w.srtB,
+                                           R.w.radix_temp, R.w.outp, R.s));
+    }
+    HIP_TRY(hipStreamSynchronize(R.s));
+    st = finish_report(R, t0);
+    if (st != NNM_OK) return st;
+    if (reps)
+        for (int32_t b = 0; b < count; ++b) reps[b] = rep0;
     return NNM_OK;
 }

@@ -144,6 +144,11 @@ struct CandArgs {
     const double* u0;         // per sorted position: bound on the key, or NULL
     int32_t row0;
     int32_t n_rows;
+    // optional tile descriptors (one per workgroup): x = first row slot,
+    // y = end row slot, z = first column, w = end column (sorted positions);
+    // NULL = tiles of 256 consecutive slots, columns [0, np)
+    const int4* tiles;
+    int32_t n_tiles;
     int32_t np;
     int32_t d;
     int32_t k;                // top-k depth
@@ -159,6 +164,7 @@ struct CandArgs {
     int64_t ld;
     const int32_t* perm;      // sorted position -> point
     const float* balls;       // [ceil(np / CHUNK)][DMAX + 1]
+    const float* sballs;      // [ceil(np / (CHUNK * SUPER))][DMAX + 1]
     int32_t prune;
     // thresholds shared by the column splits of one row (float bits)
     int32_t share;
@@ -282,6 +288,28 @@ hipError_t launch_component_order(const int32_t* comp, const int32_t* perm0, con
                                   void* radix_temp, void* scan_temp, hipStream_t s);
 hipError_t launch_chunk_balls(const float* X, int64_t n, int d, int64_t ld, const int32_t* perm,
                               int bn, float* balls, hipStream_t s);
+
+// Many instances in one point set (spatial.hip).
+struct InstDev {
+    const float* X;
+    int64_t ld;
+    int32_t d;
+    int32_t pad_;
+};
+hipError_t launch_concat(const InstDev* inst, const int32_t* off, int ninst, int64_t n, int dmax,
+                         float* Xc, hipStream_t s);
+hipError_t launch_instance_major(int32_t* perm0, int32_t* rank0, const int32_t* off, int ninst,
+                                 int64_t n, SortRec* recA, SortRec* recB, void* radix_temp,
+                                 hipStream_t s);
+hipError_t launch_tiles(const int32_t* rows, int32_t row0, int64_t nb, const int32_t* off, int ninst,
+                        int bm, int32_t* flag, int32_t* tstart, int32_t* ntiles_dev, void* scan_temp,
+                        hipStream_t s);
+hipError_t launch_tile_desc(const int32_t* tstart, int ntiles, const int32_t* rows, int32_t row0,
+                            int64_t nb, const int32_t* off, int ninst, int bm, int4* tiles,
+                            hipStream_t s);
+hipError_t launch_write_edges_batched(const SortRec* sorted, int64_t ne, const int32_t* off, int ninst,
+                                      SortRec* recA, SortRec* recB, void* radix_temp,
+                                      nnm_edge* const* out, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v,
                            int64_t n, hipStream_t s);
 

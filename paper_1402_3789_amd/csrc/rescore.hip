@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
     const int i = a.perm[rp];
     const int cnt = a.surv_cnt[slot];
     const bool over = cnt > a.S;
-    if (a.force_fallback || (over && a.level == 2)) {
+    if (a.force_fallback || (over && a.level == 2)) {   // final pass: exact scan
         if (lane == 0) {
             const int pos = atomicAdd(a.overflow_rows, 1);
             overflow_list[pos] = (int)slot;

@@ -323,3 +323,183 @@ hipError_t launch_chunk_balls(const float* X, int64_t n, int d, int64_t ld, cons
 }
 
 }  // namespace nnm
+
+// ---- many instances in one point set --------------------------------------
+namespace nnm {
+namespace {
+
+__device__ __forceinline__ int instance_of(const int32_t* off, int ninst, int64_t p)
+{
+    int lo = 0, hi = ninst;          // off[lo] <= p < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)off[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// first r in [0, nb) whose position is >= pos (rows ascending; NULL = row0 + r)
+__device__ __forceinline__ int64_t first_row_at(const int32_t* rows, int32_t row0, int64_t nb,
+                                                int64_t pos)
+{
+    if (!rows) {
+        int64_t r = pos - row0;
+        return r < 0 ? 0 : (r > nb ? nb : r);
+    }
+    int64_t lo = 0, hi = nb;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)rows[mid] < pos) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_concat(const InstDev* __restrict__ inst,
+                                                const int32_t* __restrict__ off, int ninst,
+                                                int64_t n, int dmax, float* __restrict__ Xc)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int b = instance_of(off, ninst, i);
+    const InstDev in = inst[b];
+    const float* src = in.X + (i - off[b]) * in.ld;
+    for (int f = 0; f < dmax; ++f) Xc[i * dmax + f] = f < in.d ? src[f] : 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_inst_records(const int32_t* __restrict__ perm,
+                                                      const int32_t* __restrict__ off, int ninst,
+                                                      int64_t n, SortRec* __restrict__ rec)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    SortRec r;
+    r.k0 = 0;
+    r.k1 = (uint32_t)instance_of(off, ninst, perm[q]);
+    r.k2 = (uint32_t)perm[q];
+    rec[q] = r;
+}
+
+__global__ __launch_bounds__(256) void k_tile_flags(const int32_t* __restrict__ rows, int32_t row0,
+                                                    int64_t nb, const int32_t* __restrict__ off,
+                                                    int ninst, int bm, int32_t* __restrict__ flag)
+{
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= nb) return;
+    const int64_t p = rows ? rows[r] : row0 + r;
+    const int b = instance_of(off, ninst, p);
+    const int64_t st = first_row_at(rows, row0, nb, off[b]);
+    flag[r] = ((r - st) % bm == 0) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_tile_desc(const int32_t* __restrict__ tstart, int ntiles,
+                                                   const int32_t* __restrict__ rows, int32_t row0,
+                                                   int64_t nb, const int32_t* __restrict__ off,
+                                                   int ninst, int bm, int4* __restrict__ tiles)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const int64_t rbeg = tstart[t];
+    const int64_t p = rows ? rows[rbeg] : row0 + rbeg;
+    const int b = instance_of(off, ninst, p);
+    const int64_t run_end = first_row_at(rows, row0, nb, off[b + 1]);
+    const int64_t rend = rbeg + bm < run_end ? rbeg + bm : run_end;
+    tiles[t] = make_int4((int)rbeg, (int)rend, off[b], off[b + 1]);
+}
+
+// sorted edges -> records (k0 = edge index, k1 = instance of u)
+__global__ __launch_bounds__(256) void k_edge_inst_records(const SortRec* __restrict__ e, int64_t ne,
+                                                           const int32_t* __restrict__ off, int ninst,
+                                                           SortRec* __restrict__ rec)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= ne) return;
+    SortRec r;
+    r.k0 = (uint64_t)q;
+    r.k1 = (uint32_t)instance_of(off, ninst, e[q].k1);
+    r.k2 = 0;
+    rec[q] = r;
+}
+
+__global__ __launch_bounds__(256) void k_write_edges_inst(const SortRec* __restrict__ sorted,
+                                                          const SortRec* __restrict__ order, int64_t ne,
+                                                          const int32_t* __restrict__ off,
+                                                          nnm_edge* const* __restrict__ out)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= ne) return;
+    const int b = (int)order[q].k1;
+    const SortRec r = sorted[order[q].k0];
+    const int64_t local = q - ((int64_t)off[b] - b);   // instance b owns edges [off_b - b, ...)
+    nnm_edge o;
+    o.u = (int32_t)(r.k1 - (uint32_t)off[b]);
+    o.v = (int32_t)(r.k2 - (uint32_t)off[b]);
+    o.s = __longlong_as_double((long long)r.k0);
+    o.w = __dsqrt_rn(o.s);
+    out[b][local] = o;
+}
+
+}  // namespace
+
+hipError_t launch_concat(const InstDev* inst, const int32_t* off, int ninst, int64_t n, int dmax,
+                         float* Xc, hipStream_t s)
+{
+    k_concat<<<g256(n), 256, 0, s>>>(inst, off, ninst, n, dmax, Xc);
+    return hipGetLastError();
+}
+
+// perm0 made instance-major (stable: spatial order kept inside instances)
+hipError_t launch_instance_major(int32_t* perm0, int32_t* rank0, const int32_t* off, int ninst,
+                                 int64_t n, SortRec* recA, SortRec* recB, void* radix_temp,
+                                 hipStream_t s)
+{
+    k_inst_records<<<g256(n), 256, 0, s>>>(perm0, off, ninst, n, recA);
+    int lg = 1;
+    while ((1 << lg) < ninst) ++lg;
+    const int f1[1] = {1};
+    const int b1[1] = {lg};
+    SortRec* res = nullptr;
+    hipError_t e = launch_radix_sort(recA, recB, n, f1, b1, 1, radix_temp, &res, s);
+    if (e != hipSuccess) return e;
+    e = launch_perm_from_records(res, n, perm0, s);
+    if (e != hipSuccess) return e;
+    k_rank_of<<<g256(n), 256, 0, s>>>(perm0, n, rank0);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles(const int32_t* rows, int32_t row0, int64_t nb, const int32_t* off, int ninst,
+                        int bm, int32_t* flag, int32_t* tstart, int32_t* ntiles_dev, void* scan_temp,
+                        hipStream_t s)
+{
+    k_tile_flags<<<g256(nb), 256, 0, s>>>(rows, row0, nb, off, ninst, bm, flag);
+    return launch_compact(flag, nb, tstart, ntiles_dev, scan_temp, s);
+}
+
+hipError_t launch_tile_desc(const int32_t* tstart, int ntiles, const int32_t* rows, int32_t row0,
+                            int64_t nb, const int32_t* off, int ninst, int bm, int4* tiles,
+                            hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    k_tile_desc<<<g256(ntiles), 256, 0, s>>>(tstart, ntiles, rows, row0, nb, off, ninst, bm, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_write_edges_batched(const SortRec* sorted, int64_t ne, const int32_t* off, int ninst,
+                                      SortRec* recA, SortRec* recB, void* radix_temp,
+                                      nnm_edge* const* out, hipStream_t s)
+{
+    if (ne <= 0) return hipSuccess;
+    k_edge_inst_records<<<g256(ne), 256, 0, s>>>(sorted, ne, off, ninst, recA);
+    int lg = 1;
+    while ((1 << lg) < ninst) ++lg;
+    const int f1[1] = {1};
+    const int b1[1] = {lg};
+    SortRec* res = nullptr;
+    hipError_t e = launch_radix_sort(recA, recB, ne, f1, b1, 1, radix_temp, &res, s);
+    if (e != hipSuccess) return e;
+    k_write_edges_inst<<<g256(ne), 256, 0, s>>>(sorted, res, ne, off, out);
+    return hipGetLastError();
+}
+
+}  // namespace nnm

@@ -208,11 +208,17 @@ def test_determinism_across_runs_and_settings(nnm):
 
 
 def test_batched_matches_single(nnm):
-    Xs = W.batch256(0, count=6, n_lo=300, n_hi=3000)
+    Xs = W.batch256(0, count=10, n_lo=300, n_hi=3000)
+    rng = np.random.default_rng(3)
+    Xs.insert(3, rng.standard_normal((1, 7)).astype(np.float32))     # single point
+    Xs.insert(5, rng.standard_normal((2, 3)).astype(np.float32))     # one edge
+    Xs.append(rng.integers(0, 3, size=(400, 4)).astype(np.float32))  # ties
     _say("batched", [x.shape for x in Xs])
-    trees = nnm.mst_build_batched([_dev(x) for x in Xs], precision="fp16")
-    torch.cuda.synchronize()
-    for X, t in zip(Xs, trees):
-        u, v, s, w = t.to_numpy()
-        ou, ov, os_, ow = oracle.prim_mst(X)
-        assert np.array_equal(u, ou) and np.array_equal(v, ov) and np.array_equal(s, os_)
+    for prec in ("fp16", "fp32"):
+        trees = nnm.mst_build_batched([_dev(x) for x in Xs], precision=prec)
+        torch.cuda.synchronize()
+        for X, t in zip(Xs, trees):
+            u, v, s, w = t.to_numpy()
+            ou, ov, os_, ow = oracle.prim_mst(X)
+            assert np.array_equal(u, ou) and np.array_equal(v, ov) and np.array_equal(s, os_)
+            assert np.array_equal(w, ow)
