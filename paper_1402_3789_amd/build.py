@@ -26,10 +26,18 @@ FLAGS = [
 ]
 
 
+# The candidate passes only ever see finite values (inputs are checked) and
+# +inf as a mask: NaN handling would cost a canonicalisation per min.
+PER_FILE = {
+    "cand_mfma.hip": ["-fno-honor-nans"],
+    "cand_fp32.hip": ["-fno-honor-nans"],
+}
+
+
 def _compile(src: str, verbose: bool) -> str:
     out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", out]
+    cmd = [HIPCC, *FLAGS, *PER_FILE.get(src, []), *lang, "-c", os.path.join(CSRC, src), "-o", out]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

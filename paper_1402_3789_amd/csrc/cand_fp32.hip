@@ -93,7 +93,6 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
         const int64_t c0 = (int64_t)ci * BN;
         const int ncols = (int)((a.np - c0) < BN ? (a.np - c0) : BN);
         const int cl = sh.col_lo, ch = sh.col_hi;
-        const bool masked = c0 < cl || c0 + BN > ch || !(hi_c < lo_r || lo_c > hi_r);
         if (a.share && valid) {
             T = fminf(T, __uint_as_float(a.gT[slot]));
             U = fminf(U, __uint_as_float(a.gU[slot]));
@@ -122,8 +121,10 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
                 t = __builtin_fmaf(d2, d2, t);
                 t = __builtin_fmaf(d3, d3, t);
             }
-            if (masked && (ccomp[c] == rc || ccomp[c] < 0)) t = __builtin_huge_valf();
             if (t <= T) {
+                // same component, or a column this tile must not pair with
+                const int cc = ccomp[c];
+                if (cc < 0 || cc == rc) continue;
                 const int pos = atomicAdd(&a.surv_cnt[slot], 1);
                 if (pos < a.S) {
                     a.surv_j[slot * a.S + pos] = (int)(c0 + c);

@@ -20,7 +20,8 @@
 // that every column whose exact key is <= U_i has t <= T_i.  Every column
 // with t <= T_i is appended to the row's survivor list (global memory) for
 // exact FP64 rescoring.  The per-element work is one min3 chain and one
-// compare per four pairs; hits take a wave-uniform slow path.
+// compare per eight pairs; hits take a wave-uniform slow path, which also
+// applies the component mask.
 //
 // Search order and pruning.  Points are stored in a spatial order, so the
 // chunks are visited nearest-first starting at the tile's own position, and
@@ -99,7 +100,7 @@ __device__ __forceinline__ double upper_from_t(double t, double eps, double eta,
 }
 
 template <int OP>
-__global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
+__global__ __launch_bounds__(256, 3) void k_cand_mfma(CandArgs a)
 {
     typedef OpTraits<OP> Tr;
     typedef typename Tr::frag_t frag_t;
@@ -200,7 +201,6 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         const int64_t c0 = (int64_t)ci * BN;
         const int ncols = (int)((a.np - c0) < BN ? (a.np - c0) : BN);
         const int cl = sh.col_lo, ch = sh.col_hi;
-        const bool masked = (ncols < BN) || c0 < cl || c0 + BN > ch || !(hi_c < lo_r || lo_c > hi_r);
         if (a.share && my_valid) {
             rowT[tid] = fminf(rowT[tid], __uint_as_float(a.gT[my_slot]));
             rowU[tid] = fminf(rowU[tid], __uint_as_float(a.gU[my_slot]));
@@ -232,22 +232,95 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         pairs += (unsigned long long)ncols;
 
         const int nblk = (ncols + 15) >> 4;
-        for (int cb = 0; cb < nblk; ++cb) {
+        // slow path for one 16-column block: one lane group at a time so the
+        // 4 lanes of a row never touch its LDS state together
+        auto slow = [&](int cb, const f32x4_t (&acc)[RB]) {
+            for (int g = 0; g < 4; ++g) {
+                if (grp == g) {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        if (!rvalid[rb]) continue;
+                        const int rl = wave * RB * 16 + rb * 16 + (lane & 15);
+                        const int64_t slot = row_base + rl;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float v = acc[rb][r];
+                            if (!(v <= rowT[rl])) continue;
+                            // same component, or a column this tile must not pair with
+                            const int cc = colcomp[cb * 16 + 4 * g + r];
+                            if (cc < 0 || cc == rcomp[rb]) continue;
+                            const int col = (int)(c0 + cb * 16 + 4 * g + r);
+                            const int pos = atomicAdd(&a.surv_cnt[slot], 1);
+                            if (pos < a.S) {
+                                a.surv_j[slot * a.S + pos] = col;
+                                a.surv_t[slot * a.S + pos] = v;
+                            }
+                            float* tk = topk + rl * k;
+                            if (v < tk[k - 1]) {
+                                int p = k - 1;
+                                while (p > 0 && tk[p - 1] > v) { tk[p] = tk[p - 1]; --p; }
+                                tk[p] = v;
+                                const float kth = tk[k - 1];
+                                if (kth < __builtin_huge_valf()) {
+                                    const double U = upper_from_t((double)kth, rowEps[rl], rowEta[rl], exact);
+                                    const float T = thresh_from_U(U, rowEps[rl], rowEta[rl], exact);
+                                    const float Us = d2f_up(exact ? U : U * inv_s2 * (1.0 + 0x1p-40));
+                                    if (T < rowT[rl]) {
+                                        rowT[rl] = T;
+                                        if (a.share) atomicMin(&a.gT[slot], __float_as_uint(T));
+                                    }
+                                    if (Us < rowU[rl]) {
+                                        rowU[rl] = Us;
+                                        if (a.share) atomicMin(&a.gU[slot], __float_as_uint(Us));
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
+        };
+        auto reload_T = [&]() {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) Treg[rb] = rowT[wave * RB * 16 + rb * 16 + (lane & 15)];
+        };
+        // two 16-column blocks per step: 8 MFMAs, then one min3 chain and
+        // one compare per row block for 8 candidates.  The component mask is
+        // applied in the slow path only: masked columns (same component,
+        // outside the tile's column range) are rare and merely cause a
+        // detour there.
+        int cb = 0;
+        for (; cb + 1 < nblk; cb += 2) {
+            const frag_t af0 = colbuf[(cb * 4 + grp) * 16 + (lane & 15)];
+            const frag_t af1 = colbuf[((cb + 1) * 4 + grp) * 16 + (lane & 15)];
+            f32x4_t acc0[RB], acc1[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc0[rb] = Tr::mma(af0, bfrag[rb]);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc1[rb] = Tr::mma(af1, bfrag[rb]);
+            bool hit = false;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                float m = fminf(fminf(acc0[rb][0], acc0[rb][1]), acc0[rb][2]);
+                m = fminf(fminf(m, acc0[rb][3]), acc1[rb][0]);
+                m = fminf(fminf(m, acc1[rb][1]), acc1[rb][2]);
+                m = fminf(m, acc1[rb][3]);
+                hit |= (m <= Treg[rb]);
+            }
+            if (__ballot(hit)) {
+                slow(cb, acc0);
+                slow(cb + 1, acc1);
+                reload_T();
+            }
+        }
+        if (cb < nblk) {
             const frag_t af = colbuf[(cb * 4 + grp) * 16 + (lane & 15)];
             f32x4_t acc[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc[rb] = Tr::mma(af, bfrag[rb]);
-            if (masked) {
-                const int4 cc = *reinterpret_cast<const int4*>(&colcomp[cb * 16 + 4 * grp]);
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    const float inf = __builtin_huge_valf();
-                    if (cc.x == rcomp[rb] || cc.x < 0) acc[rb][0] = inf;
-                    if (cc.y == rcomp[rb] || cc.y < 0) acc[rb][1] = inf;
-                    if (cc.z == rcomp[rb] || cc.z < 0) acc[rb][2] = inf;
-                    if (cc.w == rcomp[rb] || cc.w < 0) acc[rb][3] = inf;
-                }
-            }
             bool hit = false;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
@@ -255,54 +328,8 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                 hit |= (m <= Treg[rb]);
             }
             if (__ballot(hit)) {
-                // slow path: one lane group at a time so the 4 lanes of a
-                // row never touch its LDS state together
-                for (int g = 0; g < 4; ++g) {
-                    if (grp == g) {
-#pragma unroll
-                        for (int rb = 0; rb < RB; ++rb) {
-                            if (!rvalid[rb]) continue;
-                            const int rl = wave * RB * 16 + rb * 16 + (lane & 15);
-                            const int64_t slot = row_base + rl;
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                const float v = acc[rb][r];
-                                if (!(v <= rowT[rl])) continue;
-                                const int col = (int)(c0 + cb * 16 + 4 * g + r);
-                                const int pos = atomicAdd(&a.surv_cnt[slot], 1);
-                                if (pos < a.S) {
-                                    a.surv_j[slot * a.S + pos] = col;
-                                    a.surv_t[slot * a.S + pos] = v;
-                                }
-                                float* tk = topk + rl * k;
-                                if (v < tk[k - 1]) {
-                                    int p = k - 1;
-                                    while (p > 0 && tk[p - 1] > v) { tk[p] = tk[p - 1]; --p; }
-                                    tk[p] = v;
-                                    const float kth = tk[k - 1];
-                                    if (kth < __builtin_huge_valf()) {
-                                        const double U = upper_from_t((double)kth, rowEps[rl], rowEta[rl], exact);
-                                        const float T = thresh_from_U(U, rowEps[rl], rowEta[rl], exact);
-                                        const float Us = d2f_up(exact ? U : U * inv_s2 * (1.0 + 0x1p-40));
-                                        if (T < rowT[rl]) {
-                                            rowT[rl] = T;
-                                            if (a.share) atomicMin(&a.gT[slot], __float_as_uint(T));
-                                        }
-                                        if (Us < rowU[rl]) {
-                                            rowU[rl] = Us;
-                                            if (a.share) atomicMin(&a.gU[slot], __float_as_uint(Us));
-                                        }
-                                    }
-                                }
-                            }
-                        }
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                }
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb) Treg[rb] = rowT[wave * RB * 16 + rb * 16 + (lane & 15)];
+                slow(cb, acc);
+                reload_T();
             }
         }
         wave_max_store(sh, my_valid ? rowU[tid] : 0.f);

@@ -3,11 +3,14 @@
 // The candidate pass visits, for every tile of rows, the chunks of columns
 // nearest to it first and skips chunks that provably hold no pair the rows
 // still need.  Both rely on consecutive points being close in space:
-//   - a two-level landmark partition: every point goes to its nearest of
-//     L2 coarse landmarks, then to its nearest fine landmark among those
-//     that fell into the same coarse cell; points are ordered by fine cell
-//     (cells of one coarse cell adjacent).  The order only steers the
-//     search; results never depend on it.
+//   - a hierarchical landmark partition: level by level, every cell picks up
+//     to 32 of its points as landmarks, orders them along a greedy
+//     nearest-neighbour chain (so neighbouring landmarks get neighbouring
+//     numbers) and every point moves to the child cell of its nearest
+//     landmark; at the finest level points are ordered by their distance to
+//     that landmark.  A compact cluster stays in one cell at every level
+//     above its own scale and therefore forms one contiguous run.  The order
+//     only steers the search; results never depend on it.
 //   - after each merge round components are ordered by the earliest spatial
 //     position of their members, points inside a component by spatial
 //     position, and every sorted position gets a monotone segment id.
@@ -23,106 +26,10 @@ namespace {
 
 inline unsigned g256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// nearest of L2 coarse landmarks (landmark l is point lm[l]); FP32, ties to
-// the smaller landmark number
-__global__ __launch_bounds__(256) void k_assign_coarse(const float* __restrict__ X, int64_t n, int d,
-                                                       int64_t ld, const int32_t* __restrict__ lm,
-                                                       int L2, int32_t* __restrict__ coarse)
-{
-    extern __shared__ float lc[];   // [L2][d]
-    for (int e = threadIdx.x; e < L2 * d; e += blockDim.x) {
-        const int l = e / d, f = e % d;
-        lc[e] = X[(int64_t)lm[l] * ld + f];
-    }
-    __syncthreads();
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float x[DMAX];
-    for (int f = 0; f < d; ++f) x[f] = X[i * ld + f];
-    float best = __builtin_huge_valf();
-    int bl = 0;
-    for (int l = 0; l < L2; ++l) {
-        float t = 0.f;
-        for (int f = 0; f < d; ++f) {
-            const float df = x[f] - lc[l * d + f];
-            t = __builtin_fmaf(df, df, t);
-        }
-        if (t < best) { best = t; bl = l; }
-    }
-    coarse[i] = bl;
-}
 
-// Fine landmarks sorted by coarse cell: flm[q] (point id), q in
-// [goff[c], goff[c+1]) for coarse cell c.  key[i] = fine position.
-__global__ __launch_bounds__(256) void k_assign_fine(const float* __restrict__ X, int64_t n, int d,
-                                                     int64_t ld, const int32_t* __restrict__ coarse,
-                                                     const int32_t* __restrict__ flm,
-                                                     const int32_t* __restrict__ goff,
-                                                     uint32_t* __restrict__ key)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int c = coarse[i];
-    const int q0 = goff[c], q1 = goff[c + 1];
-    float x[DMAX];
-    for (int f = 0; f < d; ++f) x[f] = X[i * ld + f];
-    float best = __builtin_huge_valf();
-    int bq = q0;
-    for (int q = q0; q < q1; ++q) {
-        const float* y = X + (int64_t)flm[q] * ld;
-        float t = 0.f;
-        for (int f = 0; f < d; ++f) {
-            const float df = x[f] - y[f];
-            t = __builtin_fmaf(df, df, t);
-        }
-        if (t < best) { best = t; bq = q; }
-    }
-    key[i] = (uint32_t)bq;
-}
 
-__global__ __launch_bounds__(256) void k_records_u32(const uint32_t* __restrict__ key, int64_t n,
-                                                     SortRec* __restrict__ rec)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    SortRec r;
-    r.k0 = 0;
-    r.k1 = key[i];
-    r.k2 = (uint32_t)i;
-    rec[i] = r;
-}
 
-// fine landmark records: k1 = coarse cell of the landmark, k2 = point id
-__global__ __launch_bounds__(256) void k_fine_records(const int32_t* __restrict__ coarse,
-                                                      const int32_t* __restrict__ lm, int L1,
-                                                      SortRec* __restrict__ rec)
-{
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= L1) return;
-    SortRec r;
-    r.k0 = 0;
-    r.k1 = (uint32_t)coarse[lm[q]];
-    r.k2 = (uint32_t)lm[q];
-    rec[q] = r;
-}
 
-// One block: flm from the sorted records, goff[c] = first q of cell c.
-__global__ __launch_bounds__(1024) void k_fine_groups(const SortRec* __restrict__ rec, int L1, int L2,
-                                                      int32_t* __restrict__ flm,
-                                                      int32_t* __restrict__ goff)
-{
-    for (int q = threadIdx.x; q < L1; q += blockDim.x) flm[q] = (int32_t)rec[q].k2;
-    for (int c = threadIdx.x; c <= L2; c += blockDim.x) {
-        // lower bound of c among the sorted coarse ids
-        int lo = 0, hi = L1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if ((int)rec[mid].k1 < c) lo = mid + 1;
-            else hi = mid;
-        }
-        goff[c] = lo;
-    }
-}
 
 __global__ __launch_bounds__(256) void k_rank_of(const int32_t* __restrict__ perm, int64_t n,
                                                  int32_t* __restrict__ rank)
@@ -234,55 +141,201 @@ __global__ __launch_bounds__(256) void k_chunk_balls(const float* __restrict__ X
         balls[(int64_t)blockIdx.x * (DMAX + 1) + threadIdx.x] = threadIdx.x < d ? cen[threadIdx.x] : 0.f;
 }
 
+constexpr int FANOUT = 32;
+
+__global__ __launch_bounds__(256) void k_cell_records(const int32_t* __restrict__ order,
+                                                      const int32_t* __restrict__ cell, int64_t n,
+                                                      SortRec* __restrict__ rec)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int i = order ? order[q] : (int)q;
+    SortRec r;
+    r.k0 = 0;
+    r.k1 = (uint32_t)cell[i];
+    r.k2 = (uint32_t)i;
+    rec[q] = r;
+}
+
+// cstart / cend of every non-empty cell in the cell-sorted order
+__global__ __launch_bounds__(256) void k_cell_bounds(const SortRec* __restrict__ rec, int64_t n,
+                                                     int32_t* __restrict__ cstart,
+                                                     int32_t* __restrict__ cend)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const uint32_t c = rec[q].k1;
+    if (q == 0 || rec[q - 1].k1 != c) cstart[c] = (int32_t)q;
+    if (q == n - 1 || rec[q + 1].k1 != c) cend[c] = (int32_t)(q + 1);
+}
+
+// One wave per cell: up to FANOUT landmarks strided over the cell's members,
+// numbered along a greedy nearest-neighbour chain starting at the first.
+__global__ __launch_bounds__(64) void k_cell_landmarks(const float* __restrict__ X, int d, int64_t ld,
+                                                       const SortRec* __restrict__ rec,
+                                                       const int32_t* __restrict__ cstart,
+                                                       const int32_t* __restrict__ cend, int ncells,
+                                                       int32_t* __restrict__ lm, int32_t* __restrict__ lrank,
+                                                       int32_t* __restrict__ lcount)
+{
+    __shared__ float dist[FANOUT][FANOUT];
+    __shared__ int ids[FANOUT];
+    const int c = blockIdx.x;
+    if (c >= ncells) return;
+    const int st = cstart[c], en = cend[c];
+    const int lane = threadIdx.x;
+    if (en <= st) {
+        if (lane == 0) lcount[c] = 0;
+        return;
+    }
+    const int sz = en - st;
+    const int m = sz < FANOUT ? sz : FANOUT;
+    if (lane < m) ids[lane] = (int)rec[st + (int64_t)lane * sz / m].k2;
+    __syncthreads();
+    if (lane < m) {
+        const float* xa = X + (int64_t)ids[lane] * ld;
+        for (int b = 0; b < m; ++b) {
+            const float* xb = X + (int64_t)ids[b] * ld;
+            float t = 0.f;
+            for (int f = 0; f < d; ++f) {
+                const float df = xa[f] - xb[f];
+                t = __builtin_fmaf(df, df, t);
+            }
+            dist[lane][b] = t;
+        }
+    }
+    __syncthreads();
+    if (lane == 0) {
+        unsigned int seen = 1u;
+        int cur = 0;
+        lrank[c * FANOUT + 0] = 0;
+        for (int r = 1; r < m; ++r) {
+            int nx = -1;
+            float best = __builtin_huge_valf();
+            for (int b = 0; b < m; ++b)
+                if (!((seen >> b) & 1u) && dist[cur][b] < best) { best = dist[cur][b]; nx = b; }
+            if (nx < 0) {   // equal or infinite distances: take the first unvisited
+                for (int b = 0; b < m; ++b) if (!((seen >> b) & 1u)) { nx = b; break; }
+            }
+            seen |= 1u << nx;
+            lrank[c * FANOUT + nx] = r;
+            cur = nx;
+        }
+        lcount[c] = m;
+    }
+    if (lane < m) lm[c * FANOUT + lane] = ids[lane];
+}
+
+__global__ __launch_bounds__(256) void k_cell_assign(const float* __restrict__ X, int64_t n, int d,
+                                                     int64_t ld, int32_t* __restrict__ cell,
+                                                     const int32_t* __restrict__ lm,
+                                                     const int32_t* __restrict__ lrank,
+                                                     const int32_t* __restrict__ lcount,
+                                                     float* __restrict__ dist)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = cell[i];
+    const int m = lcount[c];
+    const float* xi = X + i * ld;
+    float best = __builtin_huge_valf();
+    int bj = 0;
+    for (int j = 0; j < m; ++j) {
+        const float* y = X + (int64_t)lm[c * FANOUT + j] * ld;
+        float t = 0.f;
+        for (int f = 0; f < d; ++f) {
+            const float df = xi[f] - y[f];
+            t = __builtin_fmaf(df, df, t);
+        }
+        if (t < best) { best = t; bj = j; }
+    }
+    cell[i] = c * FANOUT + (m > 0 ? lrank[c * FANOUT + bj] : 0);
+    dist[i] = m > 0 ? best : 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_dist_records(const float* __restrict__ dist,
+                                                      const int32_t* __restrict__ cell, int64_t n,
+                                                      SortRec* __restrict__ rec)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    SortRec r;
+    r.k0 = (uint64_t)__float_as_uint(dist[i]);   // non-negative: bits order as values
+    r.k1 = (uint32_t)cell[i];
+    r.k2 = (uint32_t)i;
+    rec[i] = r;
+}
+
+int order_levels(int64_t n)
+{
+    int lev = 0;
+    double cells = 1.0;
+    while ((double)n / cells > 64.0 && lev < 3) { cells *= FANOUT; ++lev; }
+    return lev < 1 ? 1 : lev;
+}
+
 }  // namespace
 
-size_t spatial_temp_bytes(int64_t n, int L1, int L2)
+size_t spatial_temp_bytes(int64_t n, int, int)
 {
-    return (size_t)n * 4 * 3 + (size_t)L1 * 4 * 2 + (size_t)(L2 + 1) * 4 + (size_t)L1 * sizeof(SortRec) * 2 +
-           radix_temp_bytes(L1 > n ? L1 : n) + 4096;
+    const int64_t maxcells = (int64_t)FANOUT * FANOUT * FANOUT;
+    return (size_t)n * 4 * 3 + (size_t)maxcells * 4 * (3 + 2 * FANOUT) + radix_temp_bytes(n) + 8192;
 }
 
 // perm0 (spatial order) and rank0 (its inverse) for n points.
-hipError_t launch_spatial_order(const float* X, int64_t n, int d, int64_t ld, int L1, int L2,
+hipError_t launch_spatial_order(const float* X, int64_t n, int d, int64_t ld, int, int,
                                 int32_t* perm0, int32_t* rank0, SortRec* recA, SortRec* recB,
                                 void* temp, hipStream_t s)
 {
     char* t = (char*)temp;
     auto take = [&](size_t bytes) { char* p = t; t += (bytes + 255) & ~(size_t)255; return p; };
-    int32_t* coarse = (int32_t*)take((size_t)n * 4);
-    uint32_t* key = (uint32_t*)take((size_t)n * 4);
-    int32_t* lm2 = (int32_t*)take((size_t)L2 * 4);
-    int32_t* lm1 = (int32_t*)take((size_t)L1 * 4);
-    int32_t* flm = (int32_t*)take((size_t)L1 * 4);
-    int32_t* goff = (int32_t*)take((size_t)(L2 + 1) * 4);
-    SortRec* fa = (SortRec*)take((size_t)L1 * sizeof(SortRec));
-    SortRec* fb = (SortRec*)take((size_t)L1 * sizeof(SortRec));
-    void* rtemp = take(radix_temp_bytes(L1 > n ? L1 : n));
-    // landmarks: evenly strided point ids
-    std::vector<int32_t> h2(L2), h1(L1);
-    for (int l = 0; l < L2; ++l) h2[l] = (int32_t)((int64_t)l * n / L2);
-    for (int l = 0; l < L1; ++l) h1[l] = (int32_t)((int64_t)l * n / L1);
-    hipError_t e = hipMemcpyAsync(lm2, h2.data(), (size_t)L2 * 4, hipMemcpyHostToDevice, s);
+    const int levels = order_levels(n);
+    int64_t maxcells = 1;
+    for (int l = 0; l < levels; ++l) maxcells *= FANOUT;
+    int32_t* cell = (int32_t*)take((size_t)n * 4);
+    float* dist = (float*)take((size_t)n * 4);
+    int32_t* order = (int32_t*)take((size_t)n * 4);
+    int32_t* cstart = (int32_t*)take((size_t)maxcells * 4);
+    int32_t* cend = (int32_t*)take((size_t)maxcells * 4);
+    int32_t* lcount = (int32_t*)take((size_t)maxcells * 4);
+    int32_t* lm = (int32_t*)take((size_t)maxcells * FANOUT * 4);
+    int32_t* lrank = (int32_t*)take((size_t)maxcells * FANOUT * 4);
+    void* rtemp = take(radix_temp_bytes(n));
+    hipError_t e = hipMemsetAsync(cell, 0, (size_t)n * 4, s);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(lm1, h1.data(), (size_t)L1 * 4, hipMemcpyHostToDevice, s);
+    int64_t ncells = 1;
+    const int32_t* prev = nullptr;     // order of the previous level (NULL = identity)
+    for (int lev = 0; lev < levels; ++lev) {
+        k_cell_records<<<g256(n), 256, 0, s>>>(prev, cell, n, recA);
+        int bits = 5 * lev;
+        SortRec* res = recA;
+        if (bits > 0) {
+            const int f1[1] = {1};
+            const int b1[1] = {bits};
+            e = launch_radix_sort(recA, recB, n, f1, b1, 1, rtemp, &res, s);
+            if (e != hipSuccess) return e;
+        }
+        e = hipMemsetAsync(cstart, 0, (size_t)ncells * 4, s);
+        if (e != hipSuccess) return e;
+        e = hipMemsetAsync(cend, 0, (size_t)ncells * 4, s);
+        if (e != hipSuccess) return e;
+        k_cell_bounds<<<g256(n), 256, 0, s>>>(res, n, cstart, cend);
+        k_cell_landmarks<<<(unsigned)ncells, 64, 0, s>>>(X, d, ld, res, cstart, cend, (int)ncells, lm,
+                                                        lrank, lcount);
+        k_cell_assign<<<g256(n), 256, 0, s>>>(X, n, d, ld, cell, lm, lrank, lcount, dist);
+        e = launch_perm_from_records(res, n, order, s);
+        if (e != hipSuccess) return e;
+        prev = order;
+        ncells *= FANOUT;
+    }
+    // finest cells, each ordered by distance to its landmark
+    k_dist_records<<<g256(n), 256, 0, s>>>(dist, cell, n, recA);
+    const int f2[2] = {0, 1};
+    const int b2[2] = {32, 5 * levels};
+    SortRec* res = nullptr;
+    e = launch_radix_sort(recA, recB, n, f2, b2, 2, rtemp, &res, s);
     if (e != hipSuccess) return e;
-    k_assign_coarse<<<g256(n), 256, (size_t)L2 * d * sizeof(float), s>>>(X, n, d, ld, lm2, L2, coarse);
-    k_fine_records<<<g256(L1), 256, 0, s>>>(coarse, lm1, L1, fa);
-    const int lgL2 = L2 > 1 ? 32 - __builtin_clz((unsigned)(L2 - 1)) : 1;
-    const int f1[1] = {1};
-    const int b1[1] = {lgL2};
-    SortRec* fs = nullptr;
-    e = launch_radix_sort(fa, fb, L1, f1, b1, 1, rtemp, &fs, s);
-    if (e != hipSuccess) return e;
-    k_fine_groups<<<1, 1024, 0, s>>>(fs, L1, L2, flm, goff);
-    k_assign_fine<<<g256(n), 256, 0, s>>>(X, n, d, ld, coarse, flm, goff, key);
-    k_records_u32<<<g256(n), 256, 0, s>>>(key, n, recA);
-    const int lgL1 = L1 > 1 ? 32 - __builtin_clz((unsigned)(L1 - 1)) : 1;
-    const int b2[1] = {lgL1};
-    SortRec* ps = nullptr;
-    e = launch_radix_sort(recA, recB, n, f1, b2, 1, rtemp, &ps, s);
-    if (e != hipSuccess) return e;
-    e = launch_perm_from_records(ps, n, perm0, s);
+    e = launch_perm_from_records(res, n, perm0, s);
     if (e != hipSuccess) return e;
     k_rank_of<<<g256(n), 256, 0, s>>>(perm0, n, rank0);
     return hipGetLastError();
