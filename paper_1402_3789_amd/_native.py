@@ -51,14 +51,16 @@ class Report(ctypes.Structure):
                 ("rescanned_bounded", ctypes.c_int64),
                 ("pairs_per_round", ctypes.c_int64 * 32),
                 ("over_per_round", ctypes.c_int64 * 32),
-                ("exact_per_round", ctypes.c_int64 * 32)]
+                ("exact_per_round", ctypes.c_int64 * 32),
+                ("cand_ms_per_round", ctypes.c_double * 32)]
 
     def as_dict(self):
         out = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
             if name.endswith("_per_round"):
-                v = [int(x) for x in v[: max(self.rounds, 0)]]
+                v = [round(float(x), 3) if name.startswith("cand_ms") else int(x)
+                     for x in v[: max(self.rounds, 0)]]
             out[name] = v
         out["precision_used"] = PREC_NAME.get(self.precision_used, str(self.precision_used))
         return out

@@ -25,6 +25,7 @@ struct TileShared {
     int decision;
     int lo, hi, rows, first_pos;
     int col_lo, col_hi;      // columns this tile may pair with (sorted positions)
+    int wneed[4];            // per wave: does any of its rows need the current chunk
 };
 
 // Row slots [rbeg, rend) and column range [cl, ch) of this workgroup's tile.
@@ -100,6 +101,32 @@ __device__ inline double ball_lb2(const TileShared& sh, const float* ball, int d
     const double lb = dist - (double)sh.rball - (double)ball[DMAX];
     if (!(lb > 0.0)) return 0.0;
     return lb * lb * (1.0 - 0x1p-40);
+}
+
+// Lower bound, rounded down, on the squared distance between the point x
+// (FP32, NQ float4s, features >= d ignored) and every point of the ball
+// (centre[DMAX], radius ball[DMAX], radius rounded up).  Plain FP32: the
+// computed sum of squares is within (d + 2) 2^-24 of the exact one, which the
+// margins on the root and on the square cover.
+template <int NQ>
+__device__ __forceinline__ float point_ball_lb2(const float4 (&x)[NQ], const float* ball, int d)
+{
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const float v[4] = {x[q].x, x[q].y, x[q].z, x[q].w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int f = 4 * q + h;
+            if (f < d) {
+                const float df = v[h] - ball[f];
+                s = __builtin_fmaf(df, df, s);
+            }
+        }
+    }
+    const float lb = __builtin_sqrtf(s) * (1.0f - 0x1p-18f) - ball[DMAX];
+    if (!(lb > 0.f)) return 0.f;
+    return lb * lb * (1.0f - 0x1p-20f);
 }
 
 // Workgroup-wide max of one float per thread (all 256 threads call it).
@@ -187,6 +214,117 @@ __device__ inline void sweep_chunks(TileShared& sh, const CandArgs& a, int lo_r,
         }
     }
 }
+
+// Nearest-first iterator over the chunks of this workgroup's column range:
+// super-chunks in zigzag order around the tile's own, then the chunks of
+// each super-chunk in zigzag order.  A candidate is skipped when it lies
+// entirely inside the tile's only component, or when the tile ball is
+// farther from its ball than the bound umax.  The tests run one candidate
+// per lane, 64 at a time; their outcome is kept until the candidates are
+// used up (a larger, older umax only keeps more).  Every wave evaluates the
+// same candidates, so all threads of the workgroup step in lockstep when
+// they call next() with the same umax.
+struct ChunkIter {
+    int ch_lo, ch_hi, start;         // chunk range of this split; the tile's own chunk
+    int sc_lo, sc_hi, sc_start;      // super-chunk range; the tile's own super-chunk
+    int ss;                          // next super-chunk step
+    int sbase;                       // super-chunk steps [sbase, sbase + 64) tested
+    unsigned long long smask;
+    int c_lo, c_hi, cstart, cs;      // current super-chunk's chunks; next step
+    int cbase;                       // chunk steps [cbase, cbase + 64) tested
+    unsigned long long cmask;
+    int my_lo, my_hi;                // this lane's tested chunk: component range
+    bool in_super;
+
+    __device__ void init(const TileShared& sh, const CandArgs& a)
+    {
+        const int first_ch = sh.col_lo / CHUNK;
+        const int nch = (sh.col_hi + CHUNK - 1) / CHUNK - first_ch;
+        const int cps = (nch + a.col_splits - 1) / a.col_splits;
+        ch_lo = first_ch + (int)blockIdx.y * cps;
+        ch_hi = ch_lo + cps < first_ch + nch ? ch_lo + cps : first_ch + nch;
+        start = sh.first_pos / CHUNK;
+        start = start < ch_lo ? ch_lo : (start >= ch_hi ? ch_hi - 1 : start);
+        sc_lo = ch_lo / SUPER;
+        sc_hi = ch_lo < ch_hi ? (ch_hi - 1) / SUPER + 1 : sc_lo;
+        sc_start = start / SUPER;
+        ss = 0;
+        sbase = -64;
+        smask = 0ull;
+        in_super = false;
+        my_lo = my_hi = 0;
+    }
+
+    // Next chunk to process, or -1; *lo_c / *hi_c receive its component range.
+    __device__ int next(const TileShared& sh, const CandArgs& a, int lo_r, int hi_r, float umax,
+                        int* lo_c, int* hi_c)
+    {
+        const int lane = threadIdx.x & 63;
+        for (;;) {
+            if (in_super) {
+                const int nc = c_hi - c_lo;
+                while (cs < nc) {
+                    if (cs >= cbase + 64) {
+                        cbase = cs;
+                        const int step = cs + lane;
+                        bool pass = false;
+                        if (step < nc) {
+                            const int ci = zigzag(step, cstart, c_lo, c_hi);
+                            const int64_t c0 = (int64_t)ci * CHUNK;
+                            const int64_t c1 = (a.np - c0) < CHUNK ? a.np - 1 : c0 + CHUNK - 1;
+                            my_lo = a.compS[c0];
+                            my_hi = a.compS[c1];
+                            pass = !(lo_r == hi_r && my_lo == my_hi && lo_r == my_lo);
+                            if (pass && a.prune)
+                                pass = ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE, a.d) <= (double)umax;
+                        }
+                        cmask = __ballot(pass);
+                    }
+                    const unsigned long long m = cmask >> (cs - cbase);
+                    if (m == 0ull) {
+                        cs = cbase + 64;
+                        continue;
+                    }
+                    const int off = cs - cbase + (int)__builtin_ctzll(m);
+                    cs = cbase + off + 1;
+                    *lo_c = __shfl(my_lo, off);
+                    *hi_c = __shfl(my_hi, off);
+                    return zigzag(cbase + off, cstart, c_lo, c_hi);
+                }
+                in_super = false;
+            }
+            const int nsc = sc_hi - sc_lo;
+            if (ss >= nsc) return -1;
+            if (ss >= sbase + 64) {
+                sbase = ss;
+                const int step = ss + lane;
+                bool pass = false;
+                if (step < nsc) {
+                    pass = true;
+                    if (a.prune) {
+                        const int sc = zigzag(step, sc_start, sc_lo, sc_hi);
+                        pass = ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE, a.d) <= (double)umax;
+                    }
+                }
+                smask = __ballot(pass);
+            }
+            const unsigned long long m = smask >> (ss - sbase);
+            if (m == 0ull) {
+                ss = sbase + 64;
+                continue;
+            }
+            const int off = ss - sbase + (int)__builtin_ctzll(m);
+            ss = sbase + off + 1;
+            const int sc = zigzag(sbase + off, sc_start, sc_lo, sc_hi);
+            c_lo = sc * SUPER > ch_lo ? sc * SUPER : ch_lo;
+            c_hi = sc * SUPER + SUPER < ch_hi ? sc * SUPER + SUPER : ch_hi;
+            cstart = (sc == sc_start) ? start : (sc > sc_start ? c_lo : c_hi - 1);
+            cs = 0;
+            cbase = -64;
+            in_super = true;
+        }
+    }
+};
 
 // Max over the 64 rows of the calling wave of v (one value per lane), stored
 // in sh.wmax[wave].

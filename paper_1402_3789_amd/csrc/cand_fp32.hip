@@ -69,6 +69,38 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
     }
     float* tk = topk + tid * k;
     for (int e = 0; e < k; ++e) tk[e] = __builtin_huge_valf();
+    if (valid && !(U < __builtin_huge_valf())) {
+        // no bound yet: seed one from the row's neighbours in the sorted
+        // order (distinct admissible columns, keys bounded from FP32)
+        for (int o = -k; o <= k; ++o) {
+            const int64_t q = (int64_t)rp + o;
+            if (o == 0 || q < tile.z || q >= tile.w || q >= a.np || a.compS[q] == rc) continue;
+            const float4* src = reinterpret_cast<const float4*>(a.xs + q * DMAX);
+            float sq = 0.f;
+#pragma unroll
+            for (int f4 = 0; f4 < F4; ++f4) {
+                const float4 y = src[f4];
+                const float d0 = xr[4 * f4 + 0] - y.x, d1 = xr[4 * f4 + 1] - y.y;
+                const float d2 = xr[4 * f4 + 2] - y.z, d3 = xr[4 * f4 + 3] - y.w;
+                sq = __builtin_fmaf(d0, d0, sq);
+                sq = __builtin_fmaf(d1, d1, sq);
+                sq = __builtin_fmaf(d2, d2, sq);
+                sq = __builtin_fmaf(d3, d3, sq);
+            }
+            const float ub = __builtin_fmaf(sq, (float)(a.d + 6) * 0x1p-24f, sq) + 0x1p-126f;
+            if (ub < tk[k - 1]) {
+                int p = k - 1;
+                while (p > 0 && tk[p - 1] > ub) { tk[p] = tk[p - 1]; --p; }
+                tk[p] = ub;
+            }
+        }
+        if (tk[k - 1] < __builtin_huge_valf()) {
+            U = tk[k - 1];
+            T = fminf(T, fp32_thresh_from_U((double)U, crel, a0));
+        }
+        for (int e = 0; e < k; ++e) tk[e] = __builtin_huge_valf();
+    }
+    int cnt = 0;                         // survivors (rows not shared by splits)
     if (a.prune) tile_ball<DP>(sh, xr, valid, a.d);
     if (tid == 0) {
         const int64_t last = (int64_t)tile.y - 1;
@@ -90,6 +122,8 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
     const float umax0 = fmaxf(fmaxf(sh.wmax[0], sh.wmax[1]), fmaxf(sh.wmax[2], sh.wmax[3]));
 
     sweep_chunks(sh, a, lo_r, hi_r, umax0, [&](int ci, int lo_c, int hi_c) {
+        // a chunk made only of the row's own component holds no candidate
+        const bool own = lo_c == hi_c && lo_c == rc;
         const int64_t c0 = (int64_t)ci * BN;
         const int ncols = (int)((a.np - c0) < BN ? (a.np - c0) : BN);
         const int cl = sh.col_lo, ch = sh.col_hi;
@@ -97,7 +131,23 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
             T = fminf(T, __uint_as_float(a.gT[slot]));
             U = fminf(U, __uint_as_float(a.gU[slot]));
         }
+        // per-row ball test: a wave whose rows are all farther from the
+        // chunk's ball than their bounds skips the chunk; if every wave
+        // does, so does the workgroup
+        {
+            bool need = valid && !own;
+            if (a.prune && need) {
+                float4 x4[F4];
+#pragma unroll
+                for (int q = 0; q < F4; ++q) x4[q] = make_float4(xr[4 * q], xr[4 * q + 1], xr[4 * q + 2], xr[4 * q + 3]);
+                need = point_ball_lb2(x4, a.balls + (int64_t)ci * BALL_STRIDE, a.d) <= U;
+            }
+            const unsigned long long b = __ballot(need);
+            if ((tid & 63) == 0) sh.wneed[tid >> 6] = b != 0ull;
+        }
         __syncthreads();
+        if (!(sh.wneed[0] | sh.wneed[1] | sh.wneed[2] | sh.wneed[3])) return;
+        const bool wrun = sh.wneed[tid >> 6] != 0;
         for (int idx = tid; idx < BN * F4; idx += 256) {
             const int c = idx / F4, q = idx % F4;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -106,6 +156,10 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
         }
         ccomp[tid] = (tid < ncols && c0 + tid >= cl && c0 + tid < ch) ? a.compS[c0 + tid] : -1;
         __syncthreads();
+        if (!wrun) {
+            wave_max_store(sh, valid ? U : 0.f);
+            return;
+        }
         pairs += (unsigned long long)ncols;
         for (int c = 0; c < ncols; ++c) {
             float t = 0.f;
@@ -121,11 +175,11 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
                 t = __builtin_fmaf(d2, d2, t);
                 t = __builtin_fmaf(d3, d3, t);
             }
-            if (t <= T) {
+            if (t <= T && !own) {
                 // same component, or a column this tile must not pair with
                 const int cc = ccomp[c];
                 if (cc < 0 || cc == rc) continue;
-                const int pos = atomicAdd(&a.surv_cnt[slot], 1);
+                const int pos = a.share ? atomicAdd(&a.surv_cnt[slot], 1) : cnt++;
                 if (pos < a.S) {
                     a.surv_j[slot * a.S + pos] = (int)(c0 + c);
                     a.surv_t[slot * a.S + pos] = t;
@@ -153,7 +207,10 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
         }
         wave_max_store(sh, valid ? U : 0.f);
     });
-    if (tid == 0 && a.pairs) atomicAdd(a.pairs, pairs * (unsigned long long)sh.rows);
+    if (!a.share && valid) a.surv_cnt[slot] = cnt;
+    const int wrows = sh.rows - (tid >> 6) * 64;
+    if ((tid & 63) == 0 && a.pairs && wrows > 0)
+        atomicAdd(a.pairs, pairs * (unsigned long long)(wrows < 64 ? wrows : 64));
 }
 
 }  // namespace

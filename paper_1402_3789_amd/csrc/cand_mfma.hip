@@ -14,12 +14,19 @@
 // K slots 0..D-1, the two squared norms ride in slots 26..31 as
 // (value, constant) pairs, so the FP32 accumulator is t itself.
 //
-// Selection.  Each row keeps, in LDS, the k smallest t it has seen; from the
-// k-th of them the proven error bound gives (1) U_i, an upper bound on the
-// exact key of the row's k-th nearest column, and (2) a threshold T_i such
-// that every column whose exact key is <= U_i has t <= T_i.  Every column
-// with t <= T_i is appended to the row's survivor list (global memory) for
-// exact FP64 rescoring.  The per-element work is one min3 chain and one
+// Frame.  For BF16 / FP16 on general data both operands are quantised in a
+// frame centred at the row tile's own centre (built in-kernel from an FP32
+// copy), so the quantisation error is relative to the distance from the
+// tile, not from the data's centre; exact integer data (FP8, or BF16/FP16 on
+// integer grids) use precomputed global operands.
+//
+// Selection.  For every column that reaches the slow path the proven error
+// bound gives an upper bound on its exact key; each row keeps, in LDS, the k
+// smallest such bounds, whose k-th is U_i >= the row's k-th smallest key.  Per
+// chunk the bound also gives a threshold T_i such that every column of the
+// chunk whose exact key is <= U_i has t <= T_i.  Every column with t <= T_i
+// is appended to the row's survivor list (global memory) for exact FP64
+// rescoring.  The per-element work is one min3 chain and one
 // compare per eight pairs; hits take a wave-uniform slow path, which also
 // applies the component mask.
 //
@@ -46,6 +53,7 @@ constexpr int RB = 4;                 // 16-row blocks per wave
 constexpr int BM = WAVES * RB * 16;   // rows per workgroup (= threads)
 constexpr int BN = CHUNK;             // columns per LDS chunk
 constexpr float KFAC = 1.0f + 0x1p-20f;
+constexpr int NQR = (DMAX_MFMA + 3) / 4;   // float4s of a row's coordinates
 
 template <int OP> struct OpTraits;
 template <> struct OpTraits<OP_BF16> {
@@ -76,40 +84,159 @@ template <> struct OpTraits<OP_FP8> {
     }
 };
 
-// Largest candidate value that can still belong to a column whose exact key
-// is <= U (scaled units), for a row with accumulation slack eps and
-// quantisation slack eta (both already combined with the column maxima).
-// With E(t) = KFAC * (eps + eta * (2 sqrt(t + eps) + eta)) bounding |t - s|,
-// t - E(t) <= U  iff  sqrt(t + eps) <= W, W = KFAC eta + sqrt(...).
-__device__ __forceinline__ float thresh_from_U(double U, double eps, double eta, int exact)
-{
-    if (exact) return d2f_up(U);
-    const double kf = (double)KFAC;
-    double W = kf * eta + __builtin_sqrt(kf * kf * eta * eta + U + eps * (1.0 + kf) + kf * eta * eta);
-    double T = (W * W - eps) * (1.0 + 0x1p-40) + 0x1p-1000;
-    return d2f_up(T);
-}
-
-// Upper bound on the exact (scaled) key of a column whose candidate is t.
-__device__ __forceinline__ double upper_from_t(double t, double eps, double eta, int exact)
+// Upper bound on the exact (scaled) key of a column whose candidate is t,
+// t + E(t) with E(t) = KFAC (eps + eta (2 sqrt(t + eps) + eta)) bounding
+// |t - s| (eps: accumulation slack, eta: quantisation slack, both already
+// combined with the column's).  FP32 with a margin that covers its own
+// roundings (sqrt within 1 ulp, a dozen operations).
+__device__ __forceinline__ float upper_from_t(float t, float eps, float eta, int exact)
 {
     if (exact) return t;
-    const double kf = (double)KFAC;
-    double tp = t > 0.0 ? t : 0.0;
-    return (t + kf * (eps + eta * (2.0 * __builtin_sqrt(tp + eps) + eta))) * (1.0 + 0x1p-40);
+    const float e = KFAC * (eps + eta * (2.f * __builtin_sqrtf(fmaxf(t, 0.f) + eps) + eta));
+    return (t + e) + (__builtin_fabsf(t) + e) * 0x1p-18f;
 }
 
+// Largest candidate value that can still belong to a column whose exact key
+// is <= U (scaled units): t - E(t) <= U  iff  sqrt(t + eps) <= W with
+// W = KFAC eta + sqrt(KFAC^2 eta^2 + U + eps (1 + KFAC) + KFAC eta^2).
+// Never above FLT_MAX, so +inf candidates (masked columns) never pass.
+__device__ __forceinline__ float thresh_from_U(float U, float eps, float eta, int exact)
+{
+    float T;
+    if (exact) {
+        T = U;
+    } else {
+        const float ke = KFAC * eta;
+        const float W = ke + __builtin_sqrtf(ke * ke + U + eps * (1.f + KFAC) + ke * eta);
+        T = (W * W - eps) + (W * W + eps) * 0x1p-18f;
+    }
+    return fminf(T, 3.402823466e38f);
+}
+
+// Upper bound, in FP32, on the exact key of a pair whose FP32 direct-difference
+// sum of squares over d features is s (relative error below (d + 2) 2^-24,
+// plus subnormal flushes far below 2^-126).
+__device__ __forceinline__ float fp32_key_upper(float s, int d)
+{
+    return __builtin_fmaf(s, (float)(d + 6) * 0x1p-24f, s) + 0x1p-126f;
+}
+
+// Element e = b * 16 + rb * 4 + r of the pair of accumulator sets, by a tree
+// of selects (no dynamic register indexing).
+__device__ __forceinline__ float pick32(const f32x4_t (&a0)[RB], const f32x4_t (&a1)[RB], int e)
+{
+    f32x4_t q[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) q[rb] = (e & 16) ? a1[rb] : a0[rb];
+    const f32x4_t h0 = (e & 4) ? q[1] : q[0];
+    const f32x4_t h1 = (e & 4) ? q[3] : q[2];
+    const f32x4_t w = (e & 8) ? h1 : h0;
+    const float lo = (e & 1) ? w[1] : w[0];
+    const float hi = (e & 1) ? w[3] : w[2];
+    return (e & 2) ? hi : lo;
+}
+
+// Operand format helpers for the local frame (BF16 / FP16).
+template <int OP> struct LpFmt;
+template <> struct LpFmt<OP_BF16> {
+    __device__ static uint16_t to(float f) { return f32_to_bf16_rn(f); }
+    __device__ static float from(uint16_t h) { return bf16_to_f32(h); }
+    static constexpr double alpha = 0x1p-8 + 0x1p-22;
+    static constexpr double beta = 0x1p-125;
+    static constexpr uint32_t inf_bits = 0x7F80u;
+};
+template <> struct LpFmt<OP_FP16> {
+    __device__ static uint16_t to(float f) { return f32_to_f16_rn(f); }
+    __device__ static float from(uint16_t h) { return f16_to_f32(h); }
+    static constexpr double alpha = 0x1p-11 + 0x1p-22;
+    static constexpr double beta = 0x1p-25 + 0x1p-149;
+    static constexpr uint32_t inf_bits = 0x7C00u;
+};
+// Operands of one point in the frame centred at c (FP32) and scaled by the
+// power of two sigma: q = lowp(sigma (x - c)); row form [q, n1,n2,n3, 1,1,1],
+// column form [-2q, 1,1,1, n1,n2,n3] where n1+n2+n3 carries ||q||^2; plus
+// the inputs of the error bound (Q, P, rho, eta) rounded up.
 template <int OP>
-__global__ __launch_bounds__(256, 3) void k_cand_mfma(CandArgs a)
+__device__ __forceinline__ void local_operands(const float* x, const float* c, float sigma, int d,
+                                               uint4 (&row)[4], uint4 (&col)[4], PointConst& pc)
+{
+    typedef LpFmt<OP> F;
+    uint32_t rw[KSLOT / 2], cw[KSLOT / 2];
+    float nrm = 0.f, vn = 0.f;
+#pragma unroll
+    for (int f2 = 0; f2 < KSLOT / 2; ++f2) {
+        uint32_t rpk = 0, cpk = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int f = 2 * f2 + h;
+            if (f < DMAX_MFMA && f < d) {
+                const float u = (x[f] - c[f]) * sigma;
+                const uint16_t q = F::to(u);
+                const float qv = F::from(q);
+                nrm = __builtin_fmaf(qv, qv, nrm);
+                vn = __builtin_fmaf(u, u, vn);
+                rpk |= (uint32_t)q << (16 * h);
+                cpk |= (uint32_t)F::to(-2.0f * qv) << (16 * h);
+            }
+        }
+        rw[f2] = rpk;
+        cw[f2] = cpk;
+    }
+    // three-part split of ||q||^2; every residual is exact in FP32
+    float r = nrm, psum = 0.f;
+    uint16_t part[NORM_PARTS];
+#pragma unroll
+    for (int k = 0; k < NORM_PARTS; ++k) {
+        part[k] = F::to(r);
+        const float pv = F::from(part[k]);
+        psum += __builtin_fabsf(pv);
+        r -= pv;
+    }
+    const uint16_t one = F::to(1.0f);
+    // slots 26..28: parts (row) / ones (col); slots 29..31: ones (row) / parts (col)
+    rw[13] = (uint32_t)part[0] | ((uint32_t)part[1] << 16);
+    rw[14] = (uint32_t)part[2] | ((uint32_t)one << 16);
+    rw[15] = (uint32_t)one | ((uint32_t)one << 16);
+    cw[13] = (uint32_t)one | ((uint32_t)one << 16);
+    cw[14] = (uint32_t)one | ((uint32_t)part[0] << 16);
+    cw[15] = (uint32_t)part[1] | ((uint32_t)part[2] << 16);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        row[w] = make_uint4(rw[4 * w], rw[4 * w + 1], rw[4 * w + 2], rw[4 * w + 3]);
+        col[w] = make_uint4(cw[4 * w], cw[4 * w + 1], cw[4 * w + 2], cw[4 * w + 3]);
+    }
+    const double up = 1.0 + 0x1p-18;
+    pc.Q = d2f_up((double)__builtin_sqrtf(nrm) * up);
+    pc.P = d2f_up((double)psum * up);
+    pc.rho = d2f_up(((double)__builtin_fabsf(r) + (double)nrm * 27.0 * 0x1p-24) * up);
+    pc.eta = d2f_up((F::alpha * (double)__builtin_sqrtf(vn) * up + F::beta * __builtin_sqrt((double)d)) * up);
+}
+
+// LOCAL: BF16 operands are built in-kernel from the sorted FP32 copy of the
+// points, in a frame centred at the row tile's own centre, so their error
+// scales with the distance from the tile rather than from the data's centre.
+// Otherwise (FP16, exact integer data, FP8) the precomputed global operands
+// are used.
+//
+// Per-row state in LDS (thread t owns row t of the tile; the slow path of
+// the wave holding the row touches it one lane group at a time):
+//   rowU  bound on the row's k-th key (data units), rowT threshold on t,
+//   rowEps / rowEta the row's slack for the current chunk, rowCnt its
+//   survivor count, topk its k smallest candidates (t, or for LOCAL upper
+//   bounds on keys in data units, since the frame changes per chunk).
+template <int OP, bool LOCAL>
+__global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
 {
     typedef OpTraits<OP> Tr;
     typedef typename Tr::frag_t frag_t;
-    constexpr int LOADS = BN * Tr::BYTES / 16 / 256;       // uint4 loads per thread
+    constexpr int PF = Tr::BYTES / 16;                     // uint4s of one column's operand
 
-    __shared__ frag_t colbuf[BN / 16 * 4 * 16];
-    __shared__ __align__(16) int32_t colcomp[BN];
-    __shared__ float rowT[BM], rowU[BM];
-    __shared__ double rowEps[BM], rowEta[BM];
+    __shared__ frag_t colbuf[2][BN / 16 * 4 * 16];         // two chunks: one in use, one filling
+    __shared__ __align__(16) int32_t colcomp[2][BN];
+    __shared__ float cmax[2][4][4];                        // LOCAL: per-wave column maxima
+    __shared__ float rowT[BM], rowU[BM], rowEps[BM], rowEta[BM];
+    __shared__ int32_t rowCnt[BM];
+    __shared__ float wmx[2][4];                            // per-wave max of rowU, double-buffered
     __shared__ TileShared sh;
     extern __shared__ float topk[];                        // [BM][k]
 
@@ -122,43 +249,82 @@ __global__ __launch_bounds__(256, 3) void k_cand_mfma(CandArgs a)
     const int64_t row_base = tile.x;
     const int64_t row_end = tile.y;
     const int exact = a.bc.exact;
-    const double inv_s2 = 1.0 / (double)a.bc.sigma2;
+    const float s2 = a.bc.sigma2;                          // sigma^2, a power of two
+    const double inv_s2 = 1.0 / (double)s2;
+    const float sigma = __builtin_sqrtf(s2);               // exact
 
-    // ---- per-row state (thread t owns row t of the tile) -----------------
+    // ---- per-row state ---------------------------------------------------
     const int64_t my_slot = row_base + tid;
     const bool my_valid = my_slot < row_end;
     const int my_rp = my_valid ? (a.rows ? a.rows[my_slot] : a.row0 + (int)my_slot) : 0;
+    const int my_comp = my_valid ? a.compS[my_rp] : -2;
+    float x[DMAX];
     {
-        float T = -__builtin_huge_valf(), U = 0.f;
-        double eps = 0.0, eta = 0.0;
-        if (my_valid) {
-            const PointConst p = a.pc[my_rp];
-            eps = ((double)a.bc.gamma * (2.0 * (double)p.Q * (double)a.bc.colQ + (double)p.P +
-                                         (double)a.bc.colP) +
-                   (double)p.rho + (double)a.bc.colRho) * (1.0 + 0x1p-40);
-            eta = ((double)p.eta + (double)a.bc.colEta) * (1.0 + 0x1p-40);
-            T = 3.402823466e38f;                           // FLT_MAX: keep all
-            U = __builtin_huge_valf();
-            if (a.u0) {
-                const double u0 = a.u0[my_rp];
-                if (u0 >= 0.0) {
-                    T = fminf(T, thresh_from_U(u0 * (double)a.bc.sigma2 * (1.0 + 0x1p-50), eps, eta, exact));
-                    U = d2f_up(u0);
+        const float4* src = reinterpret_cast<const float4*>(a.xs + (int64_t)my_rp * DMAX);
+#pragma unroll
+        for (int q = 0; q < DMAX / 4; ++q) {
+            const float4 v = my_valid ? src[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+            x[4 * q + 0] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
+        }
+    }
+    float4 xq[NQR];                                        // kept for the per-row ball tests
+#pragma unroll
+    for (int q = 0; q < NQR; ++q) xq[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+    float* my_tk = topk + tid * k;
+    for (int e = 0; e < k; ++e) my_tk[e] = __builtin_huge_valf();
+    float U = 0.f;
+    if (my_valid) {
+        U = __builtin_huge_valf();
+        if (a.u0) {
+            const double u0 = a.u0[my_rp];
+            if (u0 >= 0.0) U = d2f_up(u0);
+        }
+        if (!(U < __builtin_huge_valf())) {
+            // no bound yet: seed one from the row's neighbours in the sorted
+            // order (distinct admissible columns, keys bounded from FP32)
+            for (int o = -k; o <= k; ++o) {
+                const int64_t q = (int64_t)my_rp + o;
+                if (o == 0 || q < tile.z || q >= tile.w || q >= a.np || a.compS[q] == my_comp) continue;
+                const float4* src = reinterpret_cast<const float4*>(a.xs + q * DMAX);
+                float sq = 0.f;
+#pragma unroll
+                for (int f4 = 0; f4 < NQR; ++f4) {
+                    const float4 y = src[f4];
+                    const float d0 = xq[f4].x - y.x, d1 = xq[f4].y - y.y;
+                    const float d2 = xq[f4].z - y.z, d3 = xq[f4].w - y.w;
+                    sq = __builtin_fmaf(d0, d0, sq);
+                    sq = __builtin_fmaf(d1, d1, sq);
+                    sq = __builtin_fmaf(d2, d2, sq);
+                    sq = __builtin_fmaf(d3, d3, sq);
+                }
+                const float ub = fp32_key_upper(sq, a.d);
+                if (ub < my_tk[k - 1]) {
+                    int p = k - 1;
+                    while (p > 0 && my_tk[p - 1] > ub) { my_tk[p] = my_tk[p - 1]; --p; }
+                    my_tk[p] = ub;
                 }
             }
+            U = my_tk[k - 1];
+            for (int e = 0; e < k; ++e) my_tk[e] = __builtin_huge_valf();
         }
-        rowT[tid] = T;
-        rowU[tid] = U;
-        rowEps[tid] = eps;
-        rowEta[tid] = eta;
-        for (int e = 0; e < k; ++e) topk[tid * k + e] = __builtin_huge_valf();
     }
-    if (a.prune) {
-        float x[DMAX];
-        const float* src = a.X + (int64_t)(my_valid ? a.perm[my_rp] : 0) * a.ld;
+    rowU[tid] = U;
+    rowCnt[tid] = 0;
+    if (a.prune || LOCAL) tile_ball<DMAX>(sh, x, my_valid, a.d);
+    // row operand and its bound inputs
+    PointConst mypc{0.f, 0.f, 0.f, 0.f};
+    if constexpr (LOCAL) {
+        uint4 rowop[4], colop[4];
+        local_operands<OP>(x, sh.cen, sigma, a.d, rowop, colop, mypc);
+        uint4* stage = reinterpret_cast<uint4*>(&colbuf[0][0]);   // free until the sweep
 #pragma unroll
-        for (int f = 0; f < DMAX; ++f) x[f] = (f < a.d && my_valid) ? src[f] : 0.f;
-        tile_ball<DMAX>(sh, x, my_valid, a.d);
+        for (int q = 0; q < 4; ++q) stage[tid * 4 + q] = rowop[q];
+    } else {
+        if (my_valid) mypc = a.pc[my_rp];
+        // one frame for every pair: the row's slack is fixed
+        rowEps[tid] = (a.bc.gamma * (2.f * mypc.Q * a.bc.colQ + mypc.P + a.bc.colP) + mypc.rho + a.bc.colRho) *
+                      (1.f + 0x1p-20f);
+        rowEta[tid] = (mypc.eta + a.bc.colEta) * (1.f + 0x1p-22f);
     }
     if (tid == 0) {
         const int64_t last = row_end - 1;
@@ -171,131 +337,241 @@ __global__ __launch_bounds__(256, 3) void k_cand_mfma(CandArgs a)
         sh.col_lo = tile.z;
         sh.col_hi = tile.w;
     }
+    // Max of rowU over the calling wave into wmx[b].  Sweep step i reads
+    // wmx[i & 1] after its barrier and writes wmx[(i + 1) & 1] at its end, so
+    // every wave reads the same values and takes the same chunk sequence.
+    auto wave_max = [&](int b) {
+        float v = my_valid ? rowU[tid] : 0.f;
+        for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+        if (lane == 0) wmx[b][wave] = v;
+    };
+    wave_max(0);
+    __syncthreads();
     // row fragments stay in registers for the whole sweep
     frag_t bfrag[RB];
     int32_t rcomp[RB];
-    bool rvalid[RB];
+    uint32_t rvmask = 0;                                   // hit bits of valid rows
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
         const int rl = wave * RB * 16 + rb * 16 + (lane & 15);
         const int64_t slot = row_base + rl;
-        rvalid[rb] = slot < row_end;
-        const int rp = rvalid[rb] ? (a.rows ? a.rows[slot] : a.row0 + (int)slot) : 0;
-        const frag_t* src = reinterpret_cast<const frag_t*>(a.opR) + (int64_t)rp * 4 + grp;
-        bfrag[rb] = *src;
-        rcomp[rb] = rvalid[rb] ? a.compS[rp] : -2;
-    }
-    __syncthreads();
-    float Treg[RB];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) Treg[rb] = rowT[wave * RB * 16 + rb * 16 + (lane & 15)];
-    const int lo_r = sh.lo, hi_r = sh.hi;
-
-    // ---- column sweep, nearest chunks first ------------------------------
-    unsigned long long pairs = 0;
-    wave_max_store(sh, my_valid ? rowU[tid] : 0.f);
-    __syncthreads();
-    const float umax0 = fmaxf(fmaxf(sh.wmax[0], sh.wmax[1]), fmaxf(sh.wmax[2], sh.wmax[3]));
-
-    sweep_chunks(sh, a, lo_r, hi_r, umax0, [&](int ci, int lo_c, int hi_c) {
-        const int64_t c0 = (int64_t)ci * BN;
-        const int ncols = (int)((a.np - c0) < BN ? (a.np - c0) : BN);
-        const int cl = sh.col_lo, ch = sh.col_hi;
-        if (a.share && my_valid) {
-            rowT[tid] = fminf(rowT[tid], __uint_as_float(a.gT[my_slot]));
-            rowU[tid] = fminf(rowU[tid], __uint_as_float(a.gU[my_slot]));
+        const bool ok = slot < row_end;
+        const int rp = ok ? (a.rows ? a.rows[slot] : a.row0 + (int)slot) : 0;
+        if constexpr (LOCAL) {
+            bfrag[rb] = reinterpret_cast<const frag_t*>(&colbuf[0][0])[rl * 4 + grp];
+        } else {
+            bfrag[rb] = reinterpret_cast<const frag_t*>(a.opR)[(int64_t)rp * 4 + grp];
         }
-        __syncthreads();
-        // stage the column chunk into LDS in fragment order
-        const uint4* gsrc = reinterpret_cast<const uint4*>(a.opC) + c0 * (Tr::BYTES / 16);
+        rcomp[rb] = ok ? a.compS[rp] : -2;
+        if (ok) rvmask |= 0x000F000Fu << (4 * rb);
+    }
+    float Treg[RB];
+    const int lo_r = sh.lo, hi_r = sh.hi;
+    const bool one_comp = lo_r == hi_r;
+    const int cl = sh.col_lo, ch = sh.col_hi;
+    float umax = fmaxf(fmaxf(wmx[0][0], wmx[0][1]), fmaxf(wmx[0][2], wmx[0][3]));
+    __syncthreads();                                       // the row stage in colbuf is consumed
+
+    // ---- column sweep: nearest chunks first, the next one in flight ---------
+    unsigned long long pairs = 0;                          // per wave
+    // Thread t carries column t of a chunk from global memory to LDS.
+    uint4 pf[LOCAL ? 1 : PF];
+    float4 pfx[LOCAL ? NQR : 1];
+    int pf_cc = -1;
+    auto fetch = [&](int ci) {
+        const int64_t c0 = (int64_t)ci * BN;
+        const bool in = c0 + tid < a.np;
+        if constexpr (LOCAL) {
+            const float4* src = reinterpret_cast<const float4*>(a.xs + (c0 + (in ? tid : 0)) * DMAX);
 #pragma unroll
-        for (int it = 0; it < LOADS; ++it) {
-            const int idx = it * 256 + tid;
-            if constexpr (Tr::BYTES == 64) {
-                const int c = idx >> 2, q = idx & 3;
-                uint4 v = make_uint4(0, 0, 0, 0);
-                if (c < ncols) v = gsrc[idx];
-                reinterpret_cast<uint4*>(colbuf)[((c >> 4) * 4 + q) * 16 + (c & 15)] = v;
+            for (int q = 0; q < NQR; ++q) pfx[q] = src[q];
+        } else {
+            const uint4* src = reinterpret_cast<const uint4*>(a.opC) + (c0 + (in ? tid : 0)) * PF;
+#pragma unroll
+            for (int q = 0; q < PF; ++q) pf[q] = src[q];
+        }
+        pf_cc = in ? a.compS[c0 + tid] : -1;
+    };
+    // registers -> LDS buffer b, in fragment order; columns this tile never
+    // pairs with (beyond the data, outside its column range, or in the
+    // component of a one-component tile) get t = +inf where the format has one
+    auto stash = [&](int ci, int b) {
+        const int64_t c0 = (int64_t)ci * BN;
+        const bool col_ok = c0 + tid < a.np && c0 + tid >= cl && c0 + tid < ch &&
+                            !(one_comp && pf_cc == lo_r);
+        colcomp[b][tid] = col_ok ? pf_cc : -1;
+        if constexpr (LOCAL) {
+            float y[DMAX];
+#pragma unroll
+            for (int q = 0; q < DMAX / 4; ++q) {
+                const float4 v = q < NQR ? pfx[q < NQR ? q : 0] : make_float4(0.f, 0.f, 0.f, 0.f);
+                y[4 * q + 0] = v.x; y[4 * q + 1] = v.y; y[4 * q + 2] = v.z; y[4 * q + 3] = v.w;
+            }
+            uint4 rowop[4], colop[4];
+            PointConst cp;
+            local_operands<OP>(y, sh.cen, sigma, a.d, rowop, colop, cp);
+            float cQ = 0.f, cP = 0.f, cR = 0.f, cE = 0.f;
+            if (col_ok) {
+                cQ = cp.Q; cP = cp.P; cR = cp.rho; cE = cp.eta;
             } else {
-                const int c = idx >> 1, h = idx & 1;
-                uint4 v = make_uint4(0, 0, 0, 0);
-                if (c < ncols) v = gsrc[idx];
-                uint2* cb2 = reinterpret_cast<uint2*>(colbuf);
-                cb2[((c >> 4) * 4 + 2 * h) * 16 + (c & 15)] = make_uint2(v.x, v.y);
-                cb2[((c >> 4) * 4 + 2 * h + 1) * 16 + (c & 15)] = make_uint2(v.z, v.w);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) colop[q] = make_uint4(0, 0, 0, 0);
+                colop[3].z = LpFmt<OP>::inf_bits << 16;   // K slot 29 (times the row's 1)
+            }
+            uint4* cb4 = reinterpret_cast<uint4*>(&colbuf[b][0]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cb4[((tid >> 4) * 4 + q) * 16 + (tid & 15)] = colop[q];
+            for (int off = 32; off > 0; off >>= 1) {
+                cQ = fmaxf(cQ, __shfl_xor(cQ, off));
+                cP = fmaxf(cP, __shfl_xor(cP, off));
+                cR = fmaxf(cR, __shfl_xor(cR, off));
+                cE = fmaxf(cE, __shfl_xor(cE, off));
+            }
+            if (lane == 0) {
+                cmax[b][wave][0] = cQ; cmax[b][wave][1] = cP; cmax[b][wave][2] = cR; cmax[b][wave][3] = cE;
+            }
+        } else if constexpr (Tr::BYTES == 64) {
+            uint4* cb4 = reinterpret_cast<uint4*>(&colbuf[b][0]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint4 v = pf[q];
+                if (!col_ok) {
+                    v = make_uint4(0, 0, 0, 0);
+                    if (q == 3) v.z = LpFmt<OP>::inf_bits << 16;   // K slot 29: t = +inf
+                }
+                cb4[((tid >> 4) * 4 + q) * 16 + (tid & 15)] = v;
+            }
+        } else {
+            // FP8 has no infinity: masked columns are zero and the slow path
+            // drops them by their component entry
+            uint2* cb2 = reinterpret_cast<uint2*>(&colbuf[b][0]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint4 v = col_ok ? pf[h] : make_uint4(0, 0, 0, 0);
+                cb2[((tid >> 4) * 4 + 2 * h) * 16 + (tid & 15)] = make_uint2(v.x, v.y);
+                cb2[((tid >> 4) * 4 + 2 * h + 1) * 16 + (tid & 15)] = make_uint2(v.z, v.w);
             }
         }
-        colcomp[tid] = (tid < ncols && c0 + tid >= cl && c0 + tid < ch) ? a.compS[c0 + tid] : -1;
-        __syncthreads();
+    };
+
+    auto process = [&](int ci, int b, int lo_c, int hi_c) {
+        const int64_t c0 = (int64_t)ci * BN;
+        const int ncols = (int)((a.np - c0) < BN ? (a.np - c0) : BN);
+        const bool pure = lo_c == hi_c;                    // the chunk is one component
+        if (a.share && my_valid) rowU[tid] = fminf(rowU[tid], __uint_as_float(a.gU[my_slot]));
+        // per-row tests: a row skips a chunk made only of its own component,
+        // or whose ball lies farther than its bound; a wave whose rows all
+        // skip does no work on the chunk
+        bool need = my_valid && !(pure && lo_c == my_comp);
+        if (a.prune && need)
+            need = point_ball_lb2(xq, a.balls + (int64_t)ci * BALL_STRIDE, a.d) <= rowU[tid];
+        if (!__ballot(need)) return;
+        // this chunk's threshold for the row; the wave's rows are read back
+        // by other lanes of the same wave only
+        {
+            float eps, eta;
+            if constexpr (LOCAL) {
+                const float colQ = fmaxf(fmaxf(cmax[b][0][0], cmax[b][1][0]), fmaxf(cmax[b][2][0], cmax[b][3][0]));
+                const float colP = fmaxf(fmaxf(cmax[b][0][1], cmax[b][1][1]), fmaxf(cmax[b][2][1], cmax[b][3][1]));
+                const float colR = fmaxf(fmaxf(cmax[b][0][2], cmax[b][1][2]), fmaxf(cmax[b][2][2], cmax[b][3][2]));
+                const float colE = fmaxf(fmaxf(cmax[b][0][3], cmax[b][1][3]), fmaxf(cmax[b][2][3], cmax[b][3][3]));
+                eps = (a.bc.gamma * (2.f * mypc.Q * colQ + mypc.P + colP) + mypc.rho + colR) * (1.f + 0x1p-20f);
+                eta = (mypc.eta + colE) * (1.f + 0x1p-22f);
+                rowEps[tid] = eps;
+                rowEta[tid] = eta;
+            } else {
+                eps = rowEps[tid];
+                eta = rowEta[tid];
+            }
+            rowT[tid] = my_valid ? thresh_from_U(rowU[tid] * s2, eps, eta, exact) : -__builtin_huge_valf();
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // rows of a one-component chunk's own component see no candidate
+        bool own[RB];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) Treg[rb] = rowT[wave * RB * 16 + rb * 16 + (lane & 15)];
+        for (int rb = 0; rb < RB; ++rb) own[rb] = pure && rcomp[rb] == lo_c;
+        auto reload_T = [&]() {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                Treg[rb] = own[rb] ? -__builtin_huge_valf() : rowT[wave * RB * 16 + rb * 16 + (lane & 15)];
+        };
+        reload_T();
         pairs += (unsigned long long)ncols;
 
+        const frag_t* cbuf = &colbuf[b][0];
+        const int32_t* ccomp = &colcomp[b][0];
         const int nblk = (ncols + 15) >> 4;
-        // slow path for one 16-column block: one lane group at a time so the
-        // 4 lanes of a row never touch its LDS state together
-        auto slow = [&](int cb, const f32x4_t (&acc)[RB]) {
+        // Slow path for the blocks cb (and cb + 1 if two): every lane first
+        // collects its candidates below its rows' thresholds as bits
+        // (b * 16 + rb * 4 + r), then walks only those.  The four lane groups
+        // holding columns of the same rows take turns, so a row's LDS state
+        // is never touched by two lanes at once.
+        auto slow = [&](int cb, const f32x4_t (&acc0)[RB], const f32x4_t (&acc1)[RB], bool two) {
+            uint32_t hm = 0;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    hm |= (uint32_t)(acc0[rb][r] <= Treg[rb]) << (rb * 4 + r);
+                    if (two) hm |= (uint32_t)(acc1[rb][r] <= Treg[rb]) << (16 + rb * 4 + r);
+                }
+            }
+            hm &= rvmask;
             for (int g = 0; g < 4; ++g) {
                 if (grp == g) {
-#pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) {
-                        if (!rvalid[rb]) continue;
+                    while (hm) {
+                        const int e = __builtin_ctz(hm);
+                        hm &= hm - 1;
+                        const float v = pick32(acc0, acc1, e);
+                        const int rb = (e >> 2) & 3, r = e & 3;
                         const int rl = wave * RB * 16 + rb * 16 + (lane & 15);
+                        if (!(v <= rowT[rl])) continue;
+                        // same component, or a column this tile must not pair with
+                        const int cj = (cb + (e >> 4)) * 16 + 4 * g + r;
+                        const int cc = ccomp[cj];
+                        const int rc = rb == 0 ? rcomp[0] : rb == 1 ? rcomp[1] : rb == 2 ? rcomp[2] : rcomp[3];
+                        if (cc < 0 || cc == rc) continue;
                         const int64_t slot = row_base + rl;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const float v = acc[rb][r];
-                            if (!(v <= rowT[rl])) continue;
-                            // same component, or a column this tile must not pair with
-                            const int cc = colcomp[cb * 16 + 4 * g + r];
-                            if (cc < 0 || cc == rcomp[rb]) continue;
-                            const int col = (int)(c0 + cb * 16 + 4 * g + r);
-                            const int pos = atomicAdd(&a.surv_cnt[slot], 1);
-                            if (pos < a.S) {
-                                a.surv_j[slot * a.S + pos] = col;
-                                a.surv_t[slot * a.S + pos] = v;
-                            }
-                            float* tk = topk + rl * k;
-                            if (v < tk[k - 1]) {
-                                int p = k - 1;
-                                while (p > 0 && tk[p - 1] > v) { tk[p] = tk[p - 1]; --p; }
-                                tk[p] = v;
-                                const float kth = tk[k - 1];
-                                if (kth < __builtin_huge_valf()) {
-                                    const double U = upper_from_t((double)kth, rowEps[rl], rowEta[rl], exact);
-                                    const float T = thresh_from_U(U, rowEps[rl], rowEta[rl], exact);
-                                    const float Us = d2f_up(exact ? U : U * inv_s2 * (1.0 + 0x1p-40));
-                                    if (T < rowT[rl]) {
-                                        rowT[rl] = T;
-                                        if (a.share) atomicMin(&a.gT[slot], __float_as_uint(T));
-                                    }
-                                    if (Us < rowU[rl]) {
-                                        rowU[rl] = Us;
-                                        if (a.share) atomicMin(&a.gU[slot], __float_as_uint(Us));
-                                    }
+                        const int pos = a.share ? atomicAdd(&a.surv_cnt[slot], 1) : rowCnt[rl]++;
+                        if (pos < a.S) {
+                            a.surv_j[slot * a.S + pos] = (int)(c0 + cj);
+                            a.surv_t[slot * a.S + pos] = v;
+                        }
+                        const float eps = rowEps[rl], eta = rowEta[rl];
+                        // LOCAL: a bound on the key (data units); else t itself
+                        const float key = LOCAL ? d2f_up((double)upper_from_t(v, eps, eta, exact) * inv_s2) : v;
+                        float* tk = topk + rl * k;
+                        if (key < tk[k - 1]) {
+                            int p = k - 1;
+                            while (p > 0 && tk[p - 1] > key) { tk[p] = tk[p - 1]; --p; }
+                            tk[p] = key;
+                            const float kth = tk[k - 1];
+                            if (kth < __builtin_huge_valf()) {
+                                const float Usc = LOCAL ? kth * s2 : upper_from_t(kth, eps, eta, exact);
+                                const float Us = LOCAL ? kth : d2f_up((double)Usc * inv_s2);
+                                if (Us < rowU[rl]) {
+                                    rowU[rl] = Us;
+                                    if (a.share) atomicMin(&a.gU[slot], __float_as_uint(Us));
                                 }
+                                const float T = thresh_from_U(Usc, eps, eta, exact);
+                                if (T < rowT[rl]) rowT[rl] = T;
                             }
                         }
                     }
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         };
-        auto reload_T = [&]() {
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) Treg[rb] = rowT[wave * RB * 16 + rb * 16 + (lane & 15)];
-        };
         // two 16-column blocks per step: 8 MFMAs, then one min3 chain and
-        // one compare per row block for 8 candidates.  The component mask is
-        // applied in the slow path only: masked columns (same component,
-        // outside the tile's column range) are rare and merely cause a
-        // detour there.
+        // one compare per row block for 8 candidates
         int cb = 0;
         for (; cb + 1 < nblk; cb += 2) {
-            const frag_t af0 = colbuf[(cb * 4 + grp) * 16 + (lane & 15)];
-            const frag_t af1 = colbuf[((cb + 1) * 4 + grp) * 16 + (lane & 15)];
+            const frag_t af0 = cbuf[(cb * 4 + grp) * 16 + (lane & 15)];
+            const frag_t af1 = cbuf[((cb + 1) * 4 + grp) * 16 + (lane & 15)];
             f32x4_t acc0[RB], acc1[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc0[rb] = Tr::mma(af0, bfrag[rb]);
@@ -311,13 +587,12 @@ __global__ __launch_bounds__(256, 3) void k_cand_mfma(CandArgs a)
                 hit |= (m <= Treg[rb]);
             }
             if (__ballot(hit)) {
-                slow(cb, acc0);
-                slow(cb + 1, acc1);
+                slow(cb, acc0, acc1, true);
                 reload_T();
             }
         }
         if (cb < nblk) {
-            const frag_t af = colbuf[(cb * 4 + grp) * 16 + (lane & 15)];
+            const frag_t af = cbuf[(cb * 4 + grp) * 16 + (lane & 15)];
             f32x4_t acc[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc[rb] = Tr::mma(af, bfrag[rb]);
@@ -328,13 +603,37 @@ __global__ __launch_bounds__(256, 3) void k_cand_mfma(CandArgs a)
                 hit |= (m <= Treg[rb]);
             }
             if (__ballot(hit)) {
-                slow(cb, acc);
+                slow(cb, acc, acc, false);
                 reload_T();
             }
         }
-        wave_max_store(sh, my_valid ? rowU[tid] : 0.f);
-    });
-    if (tid == 0 && a.pairs) atomicAdd(a.pairs, pairs * (unsigned long long)sh.rows);
+    };
+
+    ChunkIter itr;
+    itr.init(sh, a);
+    int cur_lo = 0, cur_hi = 0;
+    int cur = itr.next(sh, a, lo_r, hi_r, umax, &cur_lo, &cur_hi);
+    if (cur >= 0) fetch(cur);
+    int buf = 0;
+    while (cur >= 0) {
+        stash(cur, buf);
+        __syncthreads();        // chunk cur in LDS; every wave is done with buf ^ 1's last use
+        umax = fmaxf(fmaxf(wmx[buf][0], wmx[buf][1]), fmaxf(wmx[buf][2], wmx[buf][3]));
+        int nlo = 0, nhi = 0;
+        const int nxt = itr.next(sh, a, lo_r, hi_r, umax, &nlo, &nhi);
+        if (nxt >= 0) fetch(nxt);                      // in flight while cur is processed
+        process(cur, buf, cur_lo, cur_hi);
+        // this wave's bound for the pruning tests of later chunks
+        wave_max(buf ^ 1);
+        cur = nxt;
+        cur_lo = nlo;
+        cur_hi = nhi;
+        buf ^= 1;
+    }
+    if (!a.share && my_valid) a.surv_cnt[my_slot] = rowCnt[tid];
+    const int wrows = sh.rows - wave * 64;
+    if (lane == 0 && a.pairs && wrows > 0)
+        atomicAdd(a.pairs, pairs * (unsigned long long)(wrows < 64 ? wrows : 64));
 }
 
 }  // namespace
@@ -346,10 +645,20 @@ hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s)
     if (nt == 0) return hipSuccess;
     dim3 grid(nt, (unsigned)a.col_splits);
     size_t shm = (size_t)BM * a.k * sizeof(float);
+    const bool local = a.local != 0;
     switch (opkind) {
-    case OP_BF16: k_cand_mfma<OP_BF16><<<grid, 256, shm, s>>>(a); break;
-    case OP_FP16: k_cand_mfma<OP_FP16><<<grid, 256, shm, s>>>(a); break;
-    case OP_FP8: k_cand_mfma<OP_FP8><<<grid, 256, shm, s>>>(a); break;
+    case OP_BF16:
+        if (local) k_cand_mfma<OP_BF16, true><<<grid, 256, shm, s>>>(a);
+        else k_cand_mfma<OP_BF16, false><<<grid, 256, shm, s>>>(a);
+        break;
+    case OP_FP16:
+        if (local) k_cand_mfma<OP_FP16, true><<<grid, 256, shm, s>>>(a);
+        else k_cand_mfma<OP_FP16, false><<<grid, 256, shm, s>>>(a);
+        break;
+    case OP_FP8:
+        if (local) return hipErrorInvalidValue;   // FP8 is used on exact integer data only
+        k_cand_mfma<OP_FP8, false><<<grid, 256, shm, s>>>(a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -48,6 +48,7 @@ struct Plan {
     bool mst = true;
     int L1 = 1, L2 = 1;             // fine / coarse landmarks of the spatial order
     int ninst = 1;                  // instances in the point set (batched calls)
+    bool local = false;             // BF16 operands built per tile from FP32 (not exact data)
 };
 
 struct WS {
@@ -103,7 +104,7 @@ size_t carve(const Plan& p, void* base, WS* w)
     w->opRs = mfma ? c.take<char>(n * p.op_bytes) : nullptr;
     w->opCs = mfma ? c.take<char>(n * p.op_bytes) : nullptr;
     w->pcs = c.take<PointConst>(n);
-    w->xs = mfma ? nullptr : c.take<float>(n * DMAX);
+    w->xs = c.take<float>(n * DMAX);   // also the source of the per-tile BF16/FP16 operands
     w->compS = c.take<int32_t>(n);
     w->perm = c.take<int32_t>(n);
     w->comp = c.take<int32_t>(n);
@@ -292,6 +293,9 @@ nnm_status stage(Run& R, const float* X)
         break;
     }
     p.exact = (p.opkind != OP_FP32 && intgrid) ? 1 : 0;
+    // BF16 keeps 8 bits: relative to the data's centre its error would swamp
+    // nearest-neighbour distances, so its operands are built per tile
+    p.local = p.opkind == OP_BF16 && !p.exact;
     p.op_bytes = (p.opkind == OP_FP8) ? 32 : 64;
     R.bc = BoundConst{};
     R.sigma = 1.f;
@@ -317,21 +321,34 @@ nnm_status stage(Run& R, const float* X)
         if (span > 0.0) {
             int e = 0;
             frexp(span, &e);     // span = m * 2^e, m in [0.5, 1)
+            if (e < -60 || e > 60) {
+                // sigma^2 would leave the normal FP32 range: the matrix-core
+                // formats cannot carry such data faithfully
+                if (R.o.precision != NNM_PREC_AUTO) return NNM_EUNSUPPORTED;
+                p.opkind = OP_FP32;
+                p.exact = 0;
+                p.local = false;
+                R.bc.sigma2 = 1.f;
+                return NNM_OK;
+            }
             sigma = (float)ldexp(1.0, -e);
         }
     }
     R.sigma = sigma;
-    HIP_TRY(hipMemcpyAsync(w.centre, centre, sizeof(centre), hipMemcpyHostToDevice, R.s));
-    HIP_TRY(launch_stage_operands(X, p.n, p.d, p.ld, p.opkind, p.exact, w.centre, sigma, w.opR,
-                                  w.opC, w.pc, w.stats, R.s));
-    HIP_TRY(hipMemcpyAsync(&st, w.stats, sizeof(st), hipMemcpyDeviceToHost, R.s));
-    HIP_TRY(hipStreamSynchronize(R.s));
-    float cm[4];
-    memcpy(cm, st.colmax, sizeof(cm));
-    R.bc.colQ = cm[0];
-    R.bc.colP = cm[1];
-    R.bc.colRho = cm[2];
-    R.bc.colEta = cm[3];
+    if (!p.local) {
+        // global operands (exact integer data): one frame for every pair
+        HIP_TRY(hipMemcpyAsync(w.centre, centre, sizeof(centre), hipMemcpyHostToDevice, R.s));
+        HIP_TRY(launch_stage_operands(X, p.n, p.d, p.ld, p.opkind, p.exact, w.centre, sigma, w.opR,
+                                      w.opC, w.pc, w.stats, R.s));
+        HIP_TRY(hipMemcpyAsync(&st, w.stats, sizeof(st), hipMemcpyDeviceToHost, R.s));
+        HIP_TRY(hipStreamSynchronize(R.s));
+        float cm[4];
+        memcpy(cm, st.colmax, sizeof(cm));
+        R.bc.colQ = cm[0];
+        R.bc.colP = cm[1];
+        R.bc.colRho = cm[2];
+        R.bc.colEta = cm[3];
+    }
     R.bc.gamma = p.exact ? 0.f : (float)(33.0 * 0x1p-23);
     R.bc.sigma2 = sigma * sigma;
     R.bc.exact = p.exact;
@@ -375,8 +392,13 @@ nnm_status sort_points(Run& R, const float* X)
     WS& w = R.w;
     HIP_TRY(launch_component_order(w.comp, w.perm0, w.rank0, p.n, w.ckey, w.srtA, w.srtB, w.perm,
                                    w.compS, w.flag, w.excl, w.radix_temp, w.scan_temp, R.s));
-    HIP_TRY(launch_gather_points(p.n, p.opkind, w.perm, w.opR, w.opC, w.pc, X, p.d, p.ld, w.comp,
+    // the sorted FP32 copy (tile balls; the per-tile frame's operands) ...
+    HIP_TRY(launch_gather_points(p.n, OP_FP32, w.perm, w.opR, w.opC, w.pc, X, p.d, p.ld, w.comp,
                                  w.opRs, w.opCs, w.pcs, w.xs, w.compS, R.s));
+    // ... and the precomputed operands where one global frame is used
+    if (p.opkind != OP_FP32 && !p.local)
+        HIP_TRY(launch_gather_points(p.n, p.opkind, w.perm, w.opR, w.opC, w.pc, X, p.d, p.ld, w.comp,
+                                     w.opRs, w.opCs, w.pcs, w.xs, w.compS, R.s));
     HIP_TRY(launch_chunk_balls(X, p.n, p.d, p.ld, w.perm, CHUNK, w.balls, R.s));
     HIP_TRY(launch_chunk_balls(X, p.n, p.d, p.ld, w.perm, CHUNK * SUPER, w.sballs, R.s));
     return NNM_OK;
@@ -454,6 +476,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     a.balls = w.balls;
     a.sballs = w.sballs;
     a.prune = R.o.disable_prune ? 0 : 1;
+    a.local = p.local ? 1 : 0;
     a.share = a.col_splits > 1 ? 1 : 0;
     a.gT = w.gT;
     a.gU = w.gU;
@@ -462,9 +485,16 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
         HIP_TRY(launch_fill_i32((int32_t*)w.gU, 0x7F800000, nb, R.s));
     }
     {
-        Timer t(R.rep != nullptr, R.s, R.rep ? &R.rep->ms_candidates : nullptr);
-        if (p.opkind == OP_FP32) HIP_TRY(launch_cand_fp32(a, R.s));
-        else HIP_TRY(launch_cand_mfma(p.opkind, a, R.s));
+        double ms = 0.0;
+        {
+            Timer t(R.rep != nullptr, R.s, &ms);
+            if (p.opkind == OP_FP32) HIP_TRY(launch_cand_fp32(a, R.s));
+            else HIP_TRY(launch_cand_mfma(p.opkind, a, R.s));
+        }
+        if (R.rep) {
+            R.rep->ms_candidates += ms;
+            R.rep->cand_ms_per_round[R.round < 32 ? R.round : 31] += ms;
+        }
     }
     RescoreArgs r{};
     r.X = X;
@@ -586,12 +616,19 @@ nnm_status finish_report(Run& R, std::chrono::steady_clock::time_point t0)
     R.rep->knn_k = R.p.k;
     // largest bound applied at the typical scale (per unit of sigma^2 s)
     const BoundConst& b = R.bc;
-    R.rep->max_bound = R.p.opkind == OP_FP32
-                           ? (double)(R.p.d + 3) * 0x1p-24
-                           : (b.exact ? 0.0
-                                      : ((double)b.gamma * (2.0 * b.colQ * b.colQ + 2.0 * b.colP) +
-                                         2.0 * b.colRho + 2.0 * b.colEta * 2.0 * b.colEta) /
-                                            (double)b.sigma2);
+    if (R.p.opkind == OP_FP32) {
+        R.rep->max_bound = (double)(R.p.d + 3) * 0x1p-24;
+    } else if (b.exact) {
+        R.rep->max_bound = 0.0;
+    } else {
+        // per-tile frame: every scaled offset from a tile centre is below 2
+        // per feature, which caps Q, P, rho and eta
+        const double Qm = 2.0 * sqrt((double)R.p.d);
+        const double al = (R.p.opkind == OP_BF16 ? 0x1p-8 : 0x1p-11) + 0x1p-22;
+        const double eta = al * Qm + (R.p.opkind == OP_BF16 ? 0x1p-125 : 0x1p-25) * sqrt((double)R.p.d);
+        R.rep->max_bound = ((double)b.gamma * (2.0 * Qm * Qm + 2.0 * Qm * Qm) + 2.0 * Qm * Qm * 27.0 * 0x1p-24 +
+                            2.0 * eta * 2.0 * eta) / (double)b.sigma2;
+    }
     R.rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return NNM_OK;
 }

@@ -137,7 +137,7 @@ hipError_t launch_gather_points(int64_t n, int opkind, const int32_t* perm,
 struct CandArgs {
     const void* opR;          // row-form operands, sorted order
     const void* opC;          // column-form operands, sorted order
-    const float* xs;          // FP32 path: [np][DMAX] sorted order
+    const float* xs;          // [np][DMAX] FP32 coordinates in sorted order
     const PointConst* pc;     // per sorted position
     const int32_t* compS;     // component of each sorted position
     const int32_t* rows;      // row list (sorted positions), NULL = row0 + slot
@@ -166,6 +166,7 @@ struct CandArgs {
     const float* balls;       // [ceil(np / CHUNK)][DMAX + 1]
     const float* sballs;      // [ceil(np / (CHUNK * SUPER))][DMAX + 1]
     int32_t prune;
+    int32_t local;            // BF16/FP16: operands built per tile from xs
     // thresholds shared by the column splits of one row (float bits)
     int32_t share;
     uint32_t* gT;             // [n_rows] candidate-domain threshold
