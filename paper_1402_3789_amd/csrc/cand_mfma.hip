@@ -234,6 +234,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     __shared__ frag_t colbuf[2][BN / 16 * 4 * 16];         // two chunks: one in use, one filling
     __shared__ __align__(16) int32_t colcomp[2][BN];
     __shared__ float cmax[2][4][4];                        // LOCAL: per-wave column maxima
+    __shared__ float ballbuf[2][BALL_STRIDE];              // the chunk's bounding ball
     __shared__ float rowT[BM], rowU[BM], rowEps[BM], rowEta[BM];
     __shared__ int32_t rowCnt[BM];
     __shared__ float wmx[2][4];                            // per-wave max of rowU, double-buffered
@@ -378,8 +379,10 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     uint4 pf[LOCAL ? 1 : PF];
     float4 pfx[LOCAL ? NQR : 1];
     int pf_cc = -1;
+    float pf_ball = 0.f;
     auto fetch = [&](int ci) {
         const int64_t c0 = (int64_t)ci * BN;
+        if (tid < BALL_STRIDE) pf_ball = a.balls[(int64_t)ci * BALL_STRIDE + tid];
         const bool in = c0 + tid < a.np;
         if constexpr (LOCAL) {
             const float4* src = reinterpret_cast<const float4*>(a.xs + (c0 + (in ? tid : 0)) * DMAX);
@@ -400,6 +403,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         const bool col_ok = c0 + tid < a.np && c0 + tid >= cl && c0 + tid < ch &&
                             !(one_comp && pf_cc == lo_r);
         colcomp[b][tid] = col_ok ? pf_cc : -1;
+        if (tid < BALL_STRIDE) ballbuf[b][tid] = pf_ball;
         if constexpr (LOCAL) {
             float y[DMAX];
 #pragma unroll
@@ -464,7 +468,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         // skip does no work on the chunk
         bool need = my_valid && !(pure && lo_c == my_comp);
         if (a.prune && need)
-            need = point_ball_lb2(xq, a.balls + (int64_t)ci * BALL_STRIDE, a.d) <= rowU[tid];
+            need = point_ball_lb2(xq, &ballbuf[b][0], a.d) <= rowU[tid];
         if (!__ballot(need)) return;
         // this chunk's threshold for the row; the wave's rows are read back
         // by other lanes of the same wave only
@@ -569,9 +573,15 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         // two 16-column blocks per step: 8 MFMAs, then one min3 chain and
         // one compare per row block for 8 candidates
         int cb = 0;
+        // the next step's column fragments are read while this step's MFMAs run
+        frag_t nf0 = cbuf[(0 * 4 + grp) * 16 + (lane & 15)];
+        frag_t nf1 = cbuf[(1 * 4 + grp) * 16 + (lane & 15)];
         for (; cb + 1 < nblk; cb += 2) {
-            const frag_t af0 = cbuf[(cb * 4 + grp) * 16 + (lane & 15)];
-            const frag_t af1 = cbuf[((cb + 1) * 4 + grp) * 16 + (lane & 15)];
+            const frag_t af0 = nf0, af1 = nf1;
+            if (cb + 3 < nblk) {
+                nf0 = cbuf[((cb + 2) * 4 + grp) * 16 + (lane & 15)];
+                nf1 = cbuf[((cb + 3) * 4 + grp) * 16 + (lane & 15)];
+            }
             f32x4_t acc0[RB], acc1[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc0[rb] = Tr::mma(af0, bfrag[rb]);
