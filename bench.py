@@ -59,16 +59,17 @@ def cpu_baseline(X, seconds):
     env = os.environ.get("OMP_NUM_THREADS")
     if env and env.isdigit():
         cores = min(cores, int(env))
-    n0 = min(20000, X.shape[0])
-    t0 = time.perf_counter()
-    oracle.prim_mst(X[:n0], threads=cores)
-    t1 = time.perf_counter() - t0
-    ns = int(n0 * (seconds / max(t1, 1e-3)) ** 0.5)
-    ns = max(n0, min(ns, X.shape[0]))
-    if ns > n0:
+    # size the sample so that one run takes about `seconds` (O(n^2) work;
+    # small runs underestimate, so re-aim once more from a larger one)
+    ns = min(20000, X.shape[0])
+    t1 = 0.0
+    for _ in range(3):
         t0 = time.perf_counter()
         oracle.prim_mst(X[:ns], threads=cores)
         t1 = time.perf_counter() - t0
+        if t1 >= 0.5 * seconds or ns >= X.shape[0]:
+            break
+        ns = max(ns, min(int(ns * (seconds / max(t1, 1e-3)) ** 0.5), X.shape[0]))
     pairs = ns * (ns - 1) / 2.0
     return {"value": pairs / t1, "unit": "pair-distances/s", "cores": cores, "kind": "oracle",
             "sample": f"first {ns} of the {X.shape[0]} points (dense FP64 Prim, every pair "

@@ -41,7 +41,7 @@ struct Plan {
     int64_t ld = 0;
     int opkind = OP_FP32;
     int exact = 0;
-    int k = 16;
+    int k = 8;
     int S = 256;
     int64_t rmax = 0;               // rows per candidate launch
     int op_bytes = 64;
@@ -174,7 +174,7 @@ nnm_status plan_common(int64_t n, int32_t d, int32_t k, const nnm_options* opt, 
     p->n = n;
     p->d = d;
     p->mst = mst;
-    p->k = k > 0 ? k : (o.knn_k > 0 ? o.knn_k : 16);
+    p->k = k > 0 ? k : (o.knn_k > 0 ? o.knn_k : 8);
     if (p->k < 1 || p->k > KMAX) return NNM_EINVAL;
     // workspace is sized for the widest operand so the precision can be
     // settled after the data have been inspected
