@@ -119,8 +119,8 @@ def main():
 
     def step(precision):
         tree = nnm.mst_build(Xd, precision=precision)
-        u, v, s, w = tree.to_numpy()             # device -> host copy of the edges
-        labels, k = nnm.cluster_cut((u, v, s, w), n, kl1=500)
+        # the cut copies the n-1 edges to the host and cuts them there
+        labels, k = nnm.cluster_cut(tree, n, kl1=500)
         return tree, k
 
     for i in range(args.warmup):

@@ -28,11 +28,23 @@ struct TileShared {
     int wneed[4];            // per wave: does any of its rows need the current chunk
 };
 
+// Workgroups are dealt to the 8 XCDs round-robin; neighbouring tiles sweep
+// mostly the same column chunks, so give each XCD (and its L2) a contiguous
+// run of tiles: workgroup b -> tile (b mod 8) * q + min(b mod 8, r) + b / 8
+// for G = 8 q + r workgroups, a bijection onto [0, G).
+__device__ __forceinline__ int xcd_tile(int b, int G)
+{
+    if (gridDim.y != 1) return b;
+    const int x = b & 7, q = G >> 3, r = G & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // Row slots [rbeg, rend) and column range [cl, ch) of this workgroup's tile.
 __device__ __forceinline__ int4 tile_of(const CandArgs& a, int bm)
 {
-    if (a.tiles) return a.tiles[blockIdx.x];
-    const int rbeg = (int)blockIdx.x * bm;
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    if (a.tiles) return a.tiles[t];
+    const int rbeg = t * bm;
     const int rend = rbeg + bm < a.n_rows ? rbeg + bm : a.n_rows;
     return make_int4(rbeg, rend, 0, a.np);
 }

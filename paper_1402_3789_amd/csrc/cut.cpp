@@ -31,22 +31,20 @@
 namespace {
 
 struct Dsu {
-    std::vector<int64_t> up;
-    std::vector<int64_t> size;
+    std::vector<int32_t> up;
+    std::vector<int32_t> size;
     explicit Dsu(int64_t n) : up((size_t)n), size((size_t)n, 1)
     {
-        for (int64_t i = 0; i < n; ++i) up[(size_t)i] = i;
+        for (int64_t i = 0; i < n; ++i) up[(size_t)i] = (int32_t)i;
     }
-    int64_t root(int64_t x)
+    int32_t root(int32_t x)
     {
-        int64_t r = x;
-        while (up[(size_t)r] != r) r = up[(size_t)r];
-        while (up[(size_t)x] != r) {
-            int64_t nx = up[(size_t)x];
-            up[(size_t)x] = r;
-            x = nx;
+        while (up[(size_t)x] != x) {            // path halving
+            const int32_t g = up[(size_t)up[(size_t)x]];
+            up[(size_t)x] = g;
+            x = g;
         }
-        return r;
+        return x;
     }
 };
 
@@ -97,7 +95,7 @@ extern "C" nnm_status cluster_cut(const nnm_edge* edges, int64_t n, const nnm_cu
             it = Item(1, next_in_order++);
         }
         const nnm_edge& x = edges[it.second];
-        const int64_t ra = dsu.root(x.u), rb = dsu.root(x.v);
+        const int32_t ra = dsu.root(x.u), rb = dsu.root(x.v);
         const int64_t sa = dsu.size[(size_t)ra], sb = dsu.size[(size_t)rb];
         if (priority) {
             const int cls = ((sa < sb ? sa : sb) < kl4) ? 0 : 1;
@@ -111,17 +109,17 @@ extern "C" nnm_status cluster_cut(const nnm_edge* edges, int64_t n, const nnm_cu
         if (kl3 >= 0 && sa + sb > kl3) continue;
         if (sa >= sb) {
             dsu.up[(size_t)rb] = ra;
-            dsu.size[(size_t)ra] += sb;
+            dsu.size[(size_t)ra] += (int32_t)sb;
         } else {
             dsu.up[(size_t)ra] = rb;
-            dsu.size[(size_t)rb] += sa;
+            dsu.size[(size_t)rb] += (int32_t)sa;
         }
         --clusters;
     }
     std::vector<int32_t> name((size_t)n, -1);
     int32_t next = 0;
     for (int64_t i = 0; i < n; ++i) {
-        const int64_t r = dsu.root(i);
+        const int32_t r = dsu.root((int32_t)i);
         if (name[(size_t)r] < 0) name[(size_t)r] = next++;
         labels[i] = name[(size_t)r];
     }

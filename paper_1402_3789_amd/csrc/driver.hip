@@ -30,10 +30,19 @@ struct Counters {
     int32_t over;                   // overflowed rows in the last batch
     int32_t tcount;                 // tiles of the last batch
     int32_t pad_[5];
-    unsigned long long pairs;
-    unsigned long long survivors;
+    // totals spread over NSPREAD slots (slot = workgroup mod NSPREAD), so
+    // that no single address takes an atomic from every workgroup
+    unsigned long long pairs[NSPREAD];
+    unsigned long long survivors[NSPREAD];
     unsigned long long err_bits[2];
 };
+
+unsigned long long spread_sum(const unsigned long long* v)
+{
+    unsigned long long t = 0;
+    for (int i = 0; i < NSPREAD; ++i) t += v[i];
+    return t;
+}
 
 struct Plan {
     int64_t n = 0;
@@ -469,7 +478,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     a.surv_cnt = w.surv_cnt;
     a.surv_j = w.surv_j;
     a.surv_t = w.surv_t;
-    a.pairs = &w.ctr->pairs;
+    a.pairs = w.ctr->pairs;
     a.X = X;
     a.ld = p.ld;
     a.perm = w.perm;
@@ -498,6 +507,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     }
     RescoreArgs r{};
     r.X = X;
+    r.xs = w.xs;
     r.ld = p.ld;
     r.d = p.d;
     r.n_rows = (int32_t)nb;
@@ -528,7 +538,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     r.kb = p.mst ? std::min(p.k, 4) : p.k;
     r.u0b = w.u0b;
     r.oflag = w.oflag;
-    r.survivors = &w.ctr->survivors;
+    r.survivors = w.ctr->survivors;
     r.err_bits = w.ctr->err_bits;
     int32_t over = 0;
     {
@@ -602,8 +612,8 @@ nnm_status finish_report(Run& R, std::chrono::steady_clock::time_point t0)
     Counters c;
     HIP_TRY(hipMemcpyAsync(&c, R.w.ctr, sizeof(c), hipMemcpyDeviceToHost, R.s));
     HIP_TRY(hipStreamSynchronize(R.s));
-    R.rep->pairs_evaluated = (int64_t)c.pairs;
-    R.rep->survivors = (int64_t)c.survivors;
+    R.rep->pairs_evaluated = (int64_t)spread_sum(c.pairs);
+    R.rep->survivors = (int64_t)spread_sum(c.survivors);
     double e0, e1;
     memcpy(&e0, &c.err_bits[0], 8);
     memcpy(&e1, &c.err_bits[1], 8);
@@ -831,8 +841,9 @@ nnm_status mst_rounds(Run& R, const float* X)
         if (next >= ncomp) return NNM_EDEVICE;   // no progress: cannot happen
         ncomp = next;
         if (rep && round < 32) {
-            rep->pairs_per_round[round] = (int64_t)(hc.pairs - pairs_before);
-            pairs_before = hc.pairs;
+            const unsigned long long pairs_now = spread_sum(hc.pairs);
+            rep->pairs_per_round[round] = (int64_t)(pairs_now - pairs_before);
+            pairs_before = pairs_now;
         }
     }
     if (ncomp != p.ninst || (int64_t)hc.ctr[0] != n - p.ninst) return NNM_EDEVICE;

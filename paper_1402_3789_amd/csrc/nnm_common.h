@@ -17,6 +17,7 @@ constexpr int NORM_PARTS = 3;
 constexpr int DMAX = 32;                         // FP32 path
 constexpr int DMAX_MFMA = KSLOT - 2 * NORM_PARTS;  // 26
 constexpr int KMAX = 32;                         // neighbour-cache depth
+constexpr int NSPREAD = 64;           // slots of the spread event counters
 constexpr int SMAX = 2048;                       // survivor cap
 
 enum OpKind : int { OP_BF16 = 0, OP_FP16 = 1, OP_FP8 = 2, OP_FP32 = 3 };
@@ -99,6 +100,30 @@ __device__ __forceinline__ double sqdist_fp64(const float* a, const float* b, in
     return s;
 }
 
+// The same key for two rows of the padded sorted copy ([DMAX] floats each,
+// 16-byte aligned): vector loads, identical arithmetic and order.
+__device__ __forceinline__ double sqdist_fp64_rows(const float* a, const float* b, int d)
+{
+    const float4* a4 = reinterpret_cast<const float4*>(a);
+    const float4* b4 = reinterpret_cast<const float4*>(b);
+    double s = 0.0;
+    for (int q = 0; q * 4 < d; ++q) {
+        const float4 u = a4[q], v = b4[q];
+        const float au[4] = {u.x, u.y, u.z, u.w};
+        const float bv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int f = 4 * q + h;
+            if (f < d) {
+                const double diff = __dsub_rn((double)au[h], (double)bv[h]);
+                const double sq = __dmul_rn(diff, diff);
+                s = (f == 0) ? sq : __dadd_rn(s, sq);
+            }
+        }
+    }
+    return s;
+}
+
 // (s, j) order for one row: smaller s, then smaller j.
 __device__ __forceinline__ bool sj_less(double s1, int j1, double s2, int j2)
 {
@@ -158,7 +183,7 @@ struct CandArgs {
     int32_t* surv_cnt;        // [n_rows]
     int32_t* surv_j;          // [n_rows][S] sorted column positions
     float* surv_t;            // [n_rows][S] candidate values
-    unsigned long long* pairs;// accumulated count of evaluated pairs
+    unsigned long long* pairs;// [NSPREAD] accumulated count of evaluated pairs
     // chunk pruning and near-first order
     const float* X;           // original features (row-tile balls)
     int64_t ld;
@@ -179,6 +204,7 @@ hipError_t launch_cand_fp32(const CandArgs& a, hipStream_t s);
 // FP64 rescoring of survivors into exact top-k lists.
 struct RescoreArgs {
     const float* X;
+    const float* xs;          // [np][DMAX] sorted FP32 copy (same values as X)
     int64_t ld;
     int32_t d;
     int32_t n_rows;
@@ -208,7 +234,7 @@ struct RescoreArgs {
     int32_t kb;               // level 1 bound: the kb-th key of the first S survivors
     double* u0b;              // [n] by sorted position: bound for the re-scan (level 1)
     int32_t* oflag;           // [n] by sorted position: row overflowed (level 1)
-    unsigned long long* survivors; // counter
+    unsigned long long* survivors; // [NSPREAD] counter
     unsigned long long* err_bits;  // [2]: max abs err, max rel err (double bits)
 };
 

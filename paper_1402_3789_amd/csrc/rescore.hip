@@ -11,10 +11,15 @@
 namespace nnm {
 namespace {
 
+// Running maximum of positive doubles kept as their bits; the plain read
+// first skips the atomic whenever the value cannot raise the maximum (the
+// common case once a few rows are in), so rows do not queue on one address.
 __device__ __forceinline__ void atomic_max_pos_double(unsigned long long* p, double v)
 {
     if (!(v > 0.0)) return;
-    atomicMax(p, (unsigned long long)__double_as_longlong(v));
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b <= __atomic_load_n(p, __ATOMIC_RELAXED)) return;
+    atomicMax(p, b);
 }
 
 // A row whose survivor list overflowed keeps its first S survivors, all real
@@ -42,7 +47,7 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
     }
     const int m = over ? a.S : cnt;
     const double u0s = a.u0 ? a.u0[rp] : -1.0;
-    const float* xi = a.X + (int64_t)i * a.ld;
+    const float* xi = a.xs + (int64_t)rp * DMAX;
     double sv[E];
     int jv[E];
     double emax = 0.0, rmax = 0.0;
@@ -55,7 +60,7 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
         if (idx < m) {
             const int jp = a.surv_j[slot * a.S + idx];
             const int j = a.perm[jp];
-            const double s = sqdist_fp64(xi, a.X + (int64_t)j * a.ld, a.d);
+            const double s = sqdist_fp64_rows(xi, a.xs + (int64_t)jp * DMAX, a.d);
             const double t = (double)a.surv_t[slot * a.S + idx] * a.inv_sigma2;
             const double err = __builtin_fabs(t - s);
             emax = err > emax ? err : emax;
@@ -132,7 +137,7 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
         a.clb[i] = __builtin_huge_val();
         a.cflag[i] = 1;
     }
-    atomicAdd(a.survivors, (unsigned long long)nsurv);
+    atomicAdd(&a.survivors[slot & (NSPREAD - 1)], (unsigned long long)nsurv);
 }
 
 // Exact top-k of one row over every point outside its component, by a full

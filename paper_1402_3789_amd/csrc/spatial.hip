@@ -44,12 +44,18 @@ __global__ __launch_bounds__(256) void k_ckey_reset(int32_t* __restrict__ ckey, 
     if (i < n) ckey[i] = 0x7FFFFFFF;
 }
 
+// Visits the points in spatial order (rank q of point perm0[q] is q), so the
+// smallest rank of each run of equal components inside a wave is its first
+// lane's: one atomic per run instead of one per point.
 __global__ __launch_bounds__(256) void k_ckey_min(const int32_t* __restrict__ comp,
-                                                  const int32_t* __restrict__ rank0, int64_t n,
+                                                  const int32_t* __restrict__ perm0, int64_t n,
                                                   int32_t* __restrict__ ckey)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) atomicMin(&ckey[comp[i]], rank0[i]);
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int c = q < n ? comp[perm0[q]] : -1;
+    const int prev = __shfl_up(c, 1);
+    if (q < n && (lane == 0 || prev != c)) atomicMin(&ckey[c], (int32_t)q);
 }
 
 // records in spatial order: k1 = key of the point's component, k2 = point
@@ -226,30 +232,59 @@ __global__ __launch_bounds__(64) void k_cell_landmarks(const float* __restrict__
     if (lane < m) lm[c * FANOUT + lane] = ids[lane];
 }
 
+// Each point takes the nearest of its cell's landmarks (FP32; any choice is
+// a valid order).  Workgroups run over the cell-sorted order, so the few
+// cells one workgroup touches have their landmarks staged in LDS in turn.
 __global__ __launch_bounds__(256) void k_cell_assign(const float* __restrict__ X, int64_t n, int d,
-                                                     int64_t ld, int32_t* __restrict__ cell,
+                                                     int64_t ld, const SortRec* __restrict__ rec,
+                                                     int32_t* __restrict__ cell,
                                                      const int32_t* __restrict__ lm,
                                                      const int32_t* __restrict__ lrank,
                                                      const int32_t* __restrict__ lcount,
                                                      float* __restrict__ dist)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int c = cell[i];
-    const int m = lcount[c];
-    const float* xi = X + i * ld;
+    __shared__ float L[FANOUT][DMAX + 1];
+    __shared__ uint32_t next_c;
+    const int64_t q0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t q = q0 + threadIdx.x;
+    const bool valid = q < n;
+    const int64_t qe = (q0 + blockDim.x < n ? q0 + blockDim.x : n) - 1;
+    const uint32_t clast = rec[qe].k1;
+    const int i = valid ? (int)rec[q].k2 : 0;
+    const uint32_t myc = valid ? rec[q].k1 : 0xFFFFFFFFu;
+    float xi[DMAX];
+    for (int f = 0; f < DMAX; ++f) xi[f] = (valid && f < d) ? X[(int64_t)i * ld + f] : 0.f;
     float best = __builtin_huge_valf();
     int bj = 0;
-    for (int j = 0; j < m; ++j) {
-        const float* y = X + (int64_t)lm[c * FANOUT + j] * ld;
-        float t = 0.f;
-        for (int f = 0; f < d; ++f) {
-            const float df = xi[f] - y[f];
-            t = __builtin_fmaf(df, df, t);
+    uint32_t c = rec[q0].k1;
+    for (;;) {
+        const int m = lcount[c];
+        for (int idx = threadIdx.x; idx < m * d; idx += blockDim.x) {
+            const int j = idx / d, f = idx - j * d;
+            L[j][f] = X[(int64_t)lm[c * FANOUT + j] * ld + f];
         }
-        if (t < best) { best = t; bj = j; }
+        if (threadIdx.x == 0) next_c = 0xFFFFFFFFu;
+        __syncthreads();
+        if (myc == c) {
+            for (int j = 0; j < m; ++j) {
+                float t = 0.f;
+                for (int f = 0; f < d; ++f) {
+                    const float df = xi[f] - L[j][f];
+                    t = __builtin_fmaf(df, df, t);
+                }
+                if (t < best) { best = t; bj = j; }
+            }
+        } else if (valid && myc > c) {
+            atomicMin(&next_c, myc);
+        }
+        __syncthreads();
+        if (c == clast) break;
+        c = next_c;
+        __syncthreads();
     }
-    cell[i] = c * FANOUT + (m > 0 ? lrank[c * FANOUT + bj] : 0);
+    if (!valid) return;
+    const int m = lcount[myc];
+    cell[i] = (int)myc * FANOUT + (m > 0 ? lrank[myc * FANOUT + bj] : 0);
     dist[i] = m > 0 ? best : 0.f;
 }
 
@@ -322,7 +357,7 @@ hipError_t launch_spatial_order(const float* X, int64_t n, int d, int64_t ld, in
         k_cell_bounds<<<g256(n), 256, 0, s>>>(res, n, cstart, cend);
         k_cell_landmarks<<<(unsigned)ncells, 64, 0, s>>>(X, d, ld, res, cstart, cend, (int)ncells, lm,
                                                         lrank, lcount);
-        k_cell_assign<<<g256(n), 256, 0, s>>>(X, n, d, ld, cell, lm, lrank, lcount, dist);
+        k_cell_assign<<<g256(n), 256, 0, s>>>(X, n, d, ld, res, cell, lm, lrank, lcount, dist);
         e = launch_perm_from_records(res, n, order, s);
         if (e != hipSuccess) return e;
         prev = order;
@@ -349,7 +384,7 @@ hipError_t launch_component_order(const int32_t* comp, const int32_t* perm0, con
                                   void* radix_temp, void* scan_temp, hipStream_t s)
 {
     k_ckey_reset<<<g256(n), 256, 0, s>>>(ckey, n);
-    k_ckey_min<<<g256(n), 256, 0, s>>>(comp, rank0, n, ckey);
+    k_ckey_min<<<g256(n), 256, 0, s>>>(comp, perm0, n, ckey);
     k_comp_records_spatial<<<g256(n), 256, 0, s>>>(perm0, comp, ckey, n, recA);
     int lg = 1;
     while (((int64_t)1 << lg) < n) ++lg;
