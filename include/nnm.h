@@ -145,6 +145,7 @@ typedef struct {
     int64_t over_per_round[32]; /* survivor-list overflows in each round      */
     int64_t exact_per_round[32];/* rows needing the exact scan in each round  */
     double cand_ms_per_round[32];/* candidate-kernel time in each round, ms    */
+    int64_t surv_per_round[32]; /* survivors rescored in each round           */
 } nnm_report;
 
 /* Fill *opt with the defaults (AUTO precision, k = 8, automatic caps). */

@@ -52,7 +52,8 @@ class Report(ctypes.Structure):
                 ("pairs_per_round", ctypes.c_int64 * 32),
                 ("over_per_round", ctypes.c_int64 * 32),
                 ("exact_per_round", ctypes.c_int64 * 32),
-                ("cand_ms_per_round", ctypes.c_double * 32)]
+                ("cand_ms_per_round", ctypes.c_double * 32),
+                ("surv_per_round", ctypes.c_int64 * 32)]
 
     def as_dict(self):
         out = {}

@@ -224,7 +224,7 @@ __device__ __forceinline__ void local_operands(const float* x, const float* c, f
 //   rowEps / rowEta the row's slack for the current chunk, rowCnt its
 //   survivor count, topk its k smallest candidates (t, or for LOCAL upper
 //   bounds on keys in data units, since the frame changes per chunk).
-template <int OP, bool LOCAL>
+template <int OP, bool LOCAL, bool SHARE>
 __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
 {
     typedef OpTraits<OP> Tr;
@@ -237,6 +237,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     __shared__ float ballbuf[2][BALL_STRIDE];              // the chunk's bounding ball
     __shared__ float rowT[BM], rowU[BM], rowEps[BM], rowEta[BM];
     __shared__ int32_t rowCnt[BM];
+    __shared__ int32_t rowComp[BM];
     __shared__ float wmx[2][4];                            // per-wave max of rowU, double-buffered
     __shared__ TileShared sh;
     extern __shared__ float topk[];                        // [BM][k]
@@ -311,6 +312,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     }
     rowU[tid] = U;
     rowCnt[tid] = 0;
+    rowComp[tid] = my_comp;
     if (a.prune || LOCAL) tile_ball<DMAX>(sh, x, my_valid, a.d);
     // row operand and its bound inputs
     PointConst mypc{0.f, 0.f, 0.f, 0.f};
@@ -462,7 +464,6 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         const int64_t c0 = (int64_t)ci * BN;
         const int ncols = (int)((a.np - c0) < BN ? (a.np - c0) : BN);
         const bool pure = lo_c == hi_c;                    // the chunk is one component
-        if (a.share && my_valid) rowU[tid] = fminf(rowU[tid], __uint_as_float(a.gU[my_slot]));
         // per-row tests: a row skips a chunk made only of its own component,
         // or whose ball lies farther than its bound; a wave whose rows all
         // skip does no work on the chunk
@@ -535,10 +536,11 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                         // same component, or a column this tile must not pair with
                         const int cj = (cb + (e >> 4)) * 16 + 4 * g + r;
                         const int cc = ccomp[cj];
-                        const int rc = rb == 0 ? rcomp[0] : rb == 1 ? rcomp[1] : rb == 2 ? rcomp[2] : rcomp[3];
-                        if (cc < 0 || cc == rc) continue;
+                        // (from LDS: a select over the register array would
+                        // be lowered to a private-memory array)
+                        if (cc < 0 || cc == rowComp[rl]) continue;
                         const int64_t slot = row_base + rl;
-                        const int pos = a.share ? atomicAdd(&a.surv_cnt[slot], 1) : rowCnt[rl]++;
+                        const int pos = SHARE ? atomicAdd(&a.surv_cnt[slot], 1) : rowCnt[rl]++;
                         if (pos < a.S) {
                             a.surv_j[slot * a.S + pos] = (int)(c0 + cj);
                             a.surv_t[slot * a.S + pos] = v;
@@ -557,7 +559,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                                 const float Us = LOCAL ? kth : d2f_up((double)Usc * inv_s2);
                                 if (Us < rowU[rl]) {
                                     rowU[rl] = Us;
-                                    if (a.share) atomicMin(&a.gU[slot], __float_as_uint(Us));
+                                    if (SHARE) atomicMin(&a.gU[slot], __float_as_uint(Us));
                                 }
                                 const float T = thresh_from_U(Usc, eps, eta, exact);
                                 if (T < rowT[rl]) rowT[rl] = T;
@@ -629,6 +631,9 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         stash(cur, buf);
         __syncthreads();        // chunk cur in LDS; every wave is done with buf ^ 1's last use
         umax = fmaxf(fmaxf(wmx[buf][0], wmx[buf][1]), fmaxf(wmx[buf][2], wmx[buf][3]));
+        // bounds found by the other column splits of the row (read before the
+        // next chunk's loads are issued: process() must not wait on those)
+        if (SHARE && my_valid) rowU[tid] = fminf(rowU[tid], __uint_as_float(a.gU[my_slot]));
         int nlo = 0, nhi = 0;
         const int nxt = itr.next(sh, a, lo_r, hi_r, umax, &nlo, &nhi);
         if (nxt >= 0) fetch(nxt);                      // in flight while cur is processed
@@ -640,11 +645,18 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         cur_hi = nhi;
         buf ^= 1;
     }
-    if (!a.share && my_valid) a.surv_cnt[my_slot] = rowCnt[tid];
+    if (!SHARE && my_valid) a.surv_cnt[my_slot] = rowCnt[tid];
     const int wrows = sh.rows - wave * 64;
     if (lane == 0 && a.pairs && wrows > 0)
         atomicAdd(&a.pairs[(blockIdx.x * 4 + wave) & (NSPREAD - 1)],
                   pairs * (unsigned long long)(wrows < 64 ? wrows : 64));
+}
+
+template <int OP, bool LOCAL>
+void launch_one(const CandArgs& a, dim3 grid, size_t shm, hipStream_t s)
+{
+    if (a.share) k_cand_mfma<OP, LOCAL, true><<<grid, 256, shm, s>>>(a);
+    else k_cand_mfma<OP, LOCAL, false><<<grid, 256, shm, s>>>(a);
 }
 
 }  // namespace
@@ -659,16 +671,16 @@ hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s)
     const bool local = a.local != 0;
     switch (opkind) {
     case OP_BF16:
-        if (local) k_cand_mfma<OP_BF16, true><<<grid, 256, shm, s>>>(a);
-        else k_cand_mfma<OP_BF16, false><<<grid, 256, shm, s>>>(a);
+        if (local) launch_one<OP_BF16, true>(a, grid, shm, s);
+        else launch_one<OP_BF16, false>(a, grid, shm, s);
         break;
     case OP_FP16:
-        if (local) k_cand_mfma<OP_FP16, true><<<grid, 256, shm, s>>>(a);
-        else k_cand_mfma<OP_FP16, false><<<grid, 256, shm, s>>>(a);
+        if (local) launch_one<OP_FP16, true>(a, grid, shm, s);
+        else launch_one<OP_FP16, false>(a, grid, shm, s);
         break;
     case OP_FP8:
         if (local) return hipErrorInvalidValue;   // FP8 is used on exact integer data only
-        k_cand_mfma<OP_FP8, false><<<grid, 256, shm, s>>>(a);
+        launch_one<OP_FP8, false>(a, grid, shm, s);
         break;
     default: return hipErrorInvalidValue;
     }

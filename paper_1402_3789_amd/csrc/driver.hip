@@ -763,7 +763,7 @@ nnm_status mst_rounds(Run& R, const float* X)
     int round = 0;
     Counters hc;
     memset(&hc, 0, sizeof(hc));
-    unsigned long long pairs_before = 0;
+    unsigned long long pairs_before = 0, surv_before = 0;
     for (; ncomp > p.ninst; ++round) {
         if (round >= 64) return NNM_EDEVICE;   // cannot happen: components at least halve
         R.round = round;
@@ -842,8 +842,11 @@ nnm_status mst_rounds(Run& R, const float* X)
         ncomp = next;
         if (rep && round < 32) {
             const unsigned long long pairs_now = spread_sum(hc.pairs);
+            const unsigned long long surv_now = spread_sum(hc.survivors);
             rep->pairs_per_round[round] = (int64_t)(pairs_now - pairs_before);
+            rep->surv_per_round[round] = (int64_t)(surv_now - surv_before);
             pairs_before = pairs_now;
+            surv_before = surv_now;
         }
     }
     if (ncomp != p.ninst || (int64_t)hc.ctr[0] != n - p.ninst) return NNM_EDEVICE;
