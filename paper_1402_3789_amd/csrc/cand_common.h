@@ -11,13 +11,12 @@ namespace nnm {
 // super-chunks of SUPER consecutive chunks.
 constexpr int CHUNK = 256;
 constexpr int SUPER = 16;
-constexpr int BALL_STRIDE = DMAX + 1;   // centre[DMAX], radius
 
 // Shared-memory scratch for the per-workgroup tile ball and the per-chunk
 // pruning decision (one instance per workgroup).
 struct TileShared {
     double acc[4][DMAX];
-    float cen[DMAX];
+    alignas(16) float cen[DMAX];   // zero beyond the data's features
     double red[4];
     float wmax[4];
     float rball;
@@ -73,6 +72,8 @@ __device__ inline void tile_ball(TileShared& sh, const float (&x)[DM], bool vali
         const double m = (sh.acc[0][threadIdx.x] + sh.acc[1][threadIdx.x] + sh.acc[2][threadIdx.x] +
                           sh.acc[3][threadIdx.x]) / (tot > 0.0 ? tot : 1.0);
         sh.cen[threadIdx.x] = (float)m;
+    } else if (threadIdx.x < DMAX) {
+        sh.cen[threadIdx.x] = 0.f;
     }
     __syncthreads();
     double r2 = 0.0;
@@ -101,42 +102,56 @@ __device__ inline void tile_ball(TileShared& sh, const float (&x)[DM], bool vali
 }
 
 // Lower bound on the squared distance of any pair across the tile ball and
-// chunk ball `ball` (centre[DMAX], radius), rounded down.
-__device__ inline double ball_lb2(const TileShared& sh, const float* ball, int d)
+// the ball `ball` (BALL_STRIDE floats, 16-byte aligned), rounded down.  Both
+// centres are zero beyond the data's features, so all DMAX features are
+// summed: the loads carry no dependence on d and issue together.
+__device__ inline double ball_lb2(const TileShared& sh, const float* ball)
 {
+    const float4* b4 = reinterpret_cast<const float4*>(ball);
+    const float4* c4 = reinterpret_cast<const float4*>(sh.cen);
+    float4 bv[DMAX / 4];
+#pragma unroll
+    for (int q = 0; q < DMAX / 4; ++q) bv[q] = b4[q];
+    const float rad = ball[DMAX];
     double s = 0.0;
-    for (int f = 0; f < d; ++f) {
-        const double df = (double)sh.cen[f] - (double)ball[f];
-        s += df * df;
+#pragma unroll
+    for (int q = 0; q < DMAX / 4; ++q) {
+        const float4 c = c4[q];
+        const double d0 = (double)c.x - (double)bv[q].x, d1 = (double)c.y - (double)bv[q].y;
+        const double d2 = (double)c.z - (double)bv[q].z, d3 = (double)c.w - (double)bv[q].w;
+        s += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
     }
     const double dist = __builtin_sqrt(s) * (1.0 - 0x1p-40);
-    const double lb = dist - (double)sh.rball - (double)ball[DMAX];
+    const double lb = dist - (double)sh.rball - (double)rad;
     if (!(lb > 0.0)) return 0.0;
     return lb * lb * (1.0 - 0x1p-40);
 }
 
 // Lower bound, rounded down, on the squared distance between the point x
-// (FP32, NQ float4s, features >= d ignored) and every point of the ball
-// (centre[DMAX], radius ball[DMAX], radius rounded up).  Plain FP32: the
-// computed sum of squares is within (d + 2) 2^-24 of the exact one, which the
-// margins on the root and on the square cover.
+// (FP32, NQ float4s, zero beyond the data's features) and every point of the
+// ball `ball` (BALL_STRIDE floats, 16-byte aligned, radius rounded up).
+// Plain FP32 over all 4 NQ features (the padding adds exact zeros): the
+// computed sum of squares is within (4 NQ + 2) 2^-24 of the exact one, which
+// the margins on the root and on the square cover for NQ <= 8.
 template <int NQ>
-__device__ __forceinline__ float point_ball_lb2(const float4 (&x)[NQ], const float* ball, int d)
+__device__ __forceinline__ float point_ball_lb2(const float4 (&x)[NQ], const float* ball)
 {
+    const float4* b4 = reinterpret_cast<const float4*>(ball);
+    float4 bv[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) bv[q] = b4[q];
+    const float rad = ball[DMAX];
     float s = 0.f;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const float v[4] = {x[q].x, x[q].y, x[q].z, x[q].w};
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            const int f = 4 * q + h;
-            if (f < d) {
-                const float df = v[h] - ball[f];
-                s = __builtin_fmaf(df, df, s);
-            }
-        }
+        const float d0 = x[q].x - bv[q].x, d1 = x[q].y - bv[q].y;
+        const float d2 = x[q].z - bv[q].z, d3 = x[q].w - bv[q].w;
+        s = __builtin_fmaf(d0, d0, s);
+        s = __builtin_fmaf(d1, d1, s);
+        s = __builtin_fmaf(d2, d2, s);
+        s = __builtin_fmaf(d3, d3, s);
     }
-    const float lb = __builtin_sqrtf(s) * (1.0f - 0x1p-18f) - ball[DMAX];
+    const float lb = __builtin_sqrtf(s) * (1.0f - 0x1p-18f) - rad;
     if (!(lb > 0.f)) return 0.f;
     return lb * lb * (1.0f - 0x1p-20f);
 }
@@ -202,7 +217,7 @@ __device__ inline void sweep_chunks(TileShared& sh, const CandArgs& a, int lo_r,
                 umax = fmaxf(fmaxf(sh.wmax[0], sh.wmax[1]), fmaxf(sh.wmax[2], sh.wmax[3]));
                 stale = false;
             }
-            if (ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE, a.d) > (double)umax) continue;
+            if (ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE) > (double)umax) continue;
         }
         const int c_lo = sc * SUPER > ch_lo ? sc * SUPER : ch_lo;
         const int c_hi = sc * SUPER + SUPER < ch_hi ? sc * SUPER + SUPER : ch_hi;
@@ -219,7 +234,7 @@ __device__ inline void sweep_chunks(TileShared& sh, const CandArgs& a, int lo_r,
                     umax = fmaxf(fmaxf(sh.wmax[0], sh.wmax[1]), fmaxf(sh.wmax[2], sh.wmax[3]));
                     stale = false;
                 }
-                if (ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE, a.d) > (double)umax) continue;
+                if (ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE) > (double)umax) continue;
             }
             process(ci, lo_c, hi_c);
             stale = true;
@@ -288,7 +303,7 @@ struct ChunkIter {
                             my_hi = a.compS[c1];
                             pass = !(lo_r == hi_r && my_lo == my_hi && lo_r == my_lo);
                             if (pass && a.prune)
-                                pass = ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE, a.d) <= (double)umax;
+                                pass = ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE) <= (double)umax;
                         }
                         cmask = __ballot(pass);
                     }
@@ -315,7 +330,7 @@ struct ChunkIter {
                     pass = true;
                     if (a.prune) {
                         const int sc = zigzag(step, sc_start, sc_lo, sc_hi);
-                        pass = ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE, a.d) <= (double)umax;
+                        pass = ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE) <= (double)umax;
                     }
                 }
                 smask = __ballot(pass);

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
                 float4 x4[F4];
 #pragma unroll
                 for (int q = 0; q < F4; ++q) x4[q] = make_float4(xr[4 * q], xr[4 * q + 1], xr[4 * q + 2], xr[4 * q + 3]);
-                need = point_ball_lb2(x4, a.balls + (int64_t)ci * BALL_STRIDE, a.d) <= U;
+                need = point_ball_lb2(x4, a.balls + (int64_t)ci * BALL_STRIDE) <= U;
             }
             const unsigned long long b = __ballot(need);
             if ((tid & 63) == 0) sh.wneed[tid >> 6] = b != 0ull;

@@ -234,7 +234,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     __shared__ frag_t colbuf[2][BN / 16 * 4 * 16];         // two chunks: one in use, one filling
     __shared__ __align__(16) int32_t colcomp[2][BN];
     __shared__ float cmax[2][4][4];                        // LOCAL: per-wave column maxima
-    __shared__ float ballbuf[2][BALL_STRIDE];              // the chunk's bounding ball
+    __shared__ __align__(16) float ballbuf[2][BALL_STRIDE];  // the chunk's bounding ball
     __shared__ float rowT[BM], rowU[BM], rowEps[BM], rowEta[BM];
     __shared__ int32_t rowCnt[BM];
     __shared__ int32_t rowComp[BM];
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         // skip does no work on the chunk
         bool need = my_valid && !(pure && lo_c == my_comp);
         if (a.prune && need)
-            need = point_ball_lb2(xq, &ballbuf[b][0], a.d) <= rowU[tid];
+            need = point_ball_lb2(xq, &ballbuf[b][0]) <= rowU[tid];
         if (!__ballot(need)) return;
         // this chunk's threshold for the row; the wave's rows are read back
         // by other lanes of the same wave only

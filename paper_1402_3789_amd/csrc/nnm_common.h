@@ -17,6 +17,9 @@ constexpr int NORM_PARTS = 3;
 constexpr int DMAX = 32;                         // FP32 path
 constexpr int DMAX_MFMA = KSLOT - 2 * NORM_PARTS;  // 26
 constexpr int KMAX = 32;                         // neighbour-cache depth
+// A bounding ball: centre[DMAX] (zero beyond the data's features), radius
+// at [DMAX], zero padding to a 16-byte multiple.
+constexpr int BALL_STRIDE = DMAX + 4;
 constexpr int NSPREAD = 64;           // slots of the spread event counters
 constexpr int SMAX = 2048;                       // survivor cap
 
@@ -188,8 +191,8 @@ struct CandArgs {
     const float* X;           // original features (row-tile balls)
     int64_t ld;
     const int32_t* perm;      // sorted position -> point
-    const float* balls;       // [ceil(np / CHUNK)][DMAX + 1]
-    const float* sballs;      // [ceil(np / (CHUNK * SUPER))][DMAX + 1]
+    const float* balls;       // [ceil(np / CHUNK)][BALL_STRIDE]
+    const float* sballs;      // [ceil(np / (CHUNK * SUPER))][BALL_STRIDE]
     int32_t prune;
     int32_t local;            // BF16/FP16: operands built per tile from xs
     // thresholds shared by the column splits of one row (float bits)

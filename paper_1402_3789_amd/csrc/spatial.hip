@@ -141,10 +141,12 @@ __global__ __launch_bounds__(256) void k_chunk_balls(const float* __restrict__ X
     if (threadIdx.x == 0) {
         double m = rmax[0];
         for (int w = 1; w < 4; ++w) m = rmax[w] > m ? rmax[w] : m;
-        balls[(int64_t)blockIdx.x * (DMAX + 1) + DMAX] = d2f_up(__builtin_sqrt(m) * (1.0 + 0x1p-40));
+        balls[(int64_t)blockIdx.x * BALL_STRIDE + DMAX] = d2f_up(__builtin_sqrt(m) * (1.0 + 0x1p-40));
     }
     if (threadIdx.x < DMAX)
-        balls[(int64_t)blockIdx.x * (DMAX + 1) + threadIdx.x] = threadIdx.x < d ? cen[threadIdx.x] : 0.f;
+        balls[(int64_t)blockIdx.x * BALL_STRIDE + threadIdx.x] = threadIdx.x < d ? cen[threadIdx.x] : 0.f;
+    else if (threadIdx.x > DMAX && threadIdx.x < BALL_STRIDE)
+        balls[(int64_t)blockIdx.x * BALL_STRIDE + threadIdx.x] = 0.f;
 }
 
 constexpr int FANOUT = 32;
