@@ -327,11 +327,13 @@ struct ChunkIter {
                 const int step = ss + lane;
                 bool pass = false;
                 if (step < nsc) {
-                    pass = true;
-                    if (a.prune) {
-                        const int sc = zigzag(step, sc_start, sc_lo, sc_hi);
+                    const int sc = zigzag(step, sc_start, sc_lo, sc_hi);
+                    // a super-chunk entirely inside the tile's only component
+                    const int64_t s0 = (int64_t)sc * SUPER * CHUNK;
+                    const int64_t s1 = (a.np - s0) < SUPER * CHUNK ? a.np - 1 : s0 + SUPER * CHUNK - 1;
+                    pass = !(lo_r == hi_r && a.compS[s0] == lo_r && a.compS[s1] == lo_r);
+                    if (pass && a.prune)
                         pass = ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE) <= (double)umax;
-                    }
                 }
                 smask = __ballot(pass);
             }

@@ -343,10 +343,18 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     // Max of rowU over the calling wave into wmx[b].  Sweep step i reads
     // wmx[i & 1] after its barrier and writes wmx[(i + 1) & 1] at its end, so
     // every wave reads the same values and takes the same chunk sequence.
+    // The maximum is recomputed only after the wave's bounds may have moved
+    // (slow path, split sharing); otherwise the cached value is written.
+    float wm = 0.f;
+    bool wdirty = true;
     auto wave_max = [&](int b) {
-        float v = my_valid ? rowU[tid] : 0.f;
-        for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-        if (lane == 0) wmx[b][wave] = v;
+        if (wdirty) {
+            float v = my_valid ? rowU[tid] : 0.f;
+            for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+            wm = v;
+            wdirty = false;
+        }
+        if (lane == 0) wmx[b][wave] = wm;
     };
     wave_max(0);
     __syncthreads();
@@ -514,6 +522,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         // holding columns of the same rows take turns, so a row's LDS state
         // is never touched by two lanes at once.
         auto slow = [&](int cb, const f32x4_t (&acc0)[RB], const f32x4_t (&acc1)[RB], bool two) {
+            wdirty = true;
             uint32_t hm = 0;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
@@ -633,7 +642,10 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         umax = fmaxf(fmaxf(wmx[buf][0], wmx[buf][1]), fmaxf(wmx[buf][2], wmx[buf][3]));
         // bounds found by the other column splits of the row (read before the
         // next chunk's loads are issued: process() must not wait on those)
-        if (SHARE && my_valid) rowU[tid] = fminf(rowU[tid], __uint_as_float(a.gU[my_slot]));
+        if (SHARE) {
+            if (my_valid) rowU[tid] = fminf(rowU[tid], __uint_as_float(a.gU[my_slot]));
+            wdirty = true;
+        }
         int nlo = 0, nhi = 0;
         const int nxt = itr.next(sh, a, lo_r, hi_r, umax, &nlo, &nhi);
         if (nxt >= 0) fetch(nxt);                      // in flight while cur is processed
