@@ -83,7 +83,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--precision", default="fp16")
-    ap.add_argument("--fp32-steps", type=int, default=1)
+    ap.add_argument("--fp32-steps", type=int, default=1,
+                    help="timed steps of each comparison path (0 = none)")
+    ap.add_argument("--compare", default="fp32,bf16",
+                    help="other candidate precisions timed on the same data")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -154,20 +157,23 @@ def main():
             "pairs_evaluated_per_step": evaluated / args.steps,
             "flops_per_pair": 2 * d + 1}
 
-    # plain FP32 path on the same data
-    fp32 = None
+    # the plain FP32 path (and other precisions) on the same data
+    others = {}
     if args.fp32_steps > 0:
-        step("fp32")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.fp32_steps):
-            tr32, _ = step("fp32")
-        torch.cuda.synchronize()
-        ms32 = 1e3 * (time.perf_counter() - t0) / args.fp32_steps
-        same = np.array_equal(tr32.host_bytes(), tree.host_bytes())
-        fp32 = {"ms_per_step": round(ms32, 3), "value": pairs / (ms32 * 1e-3),
-                "mixed_speedup": round(ms32 / ms, 3), "identical_tree": bool(same)}
-        log(f"[bench] fp32: {ms32:.1f} ms/step, identical tree: {same}")
+        for prec in [p for p in args.compare.split(",") if p and p != args.precision]:
+            step(prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.fp32_steps):
+                tr2, _ = step(prec)
+            torch.cuda.synchronize()
+            ms2 = 1e3 * (time.perf_counter() - t0) / args.fp32_steps
+            same = np.array_equal(tr2.host_bytes(), tree.host_bytes())
+            others[prec] = {"ms_per_step": round(ms2, 3), "value": pairs / (ms2 * 1e-3),
+                            "speedup_of_" + args.precision: round(ms2 / ms, 3),
+                            "identical_tree": bool(same),
+                            "ms_candidates": round(tr2.report["ms_candidates"], 3)}
+            log(f"[bench] {prec}: {ms2:.1f} ms/step, identical tree: {same}")
 
     cpu = None
     if not args.no_cpu:
@@ -192,7 +198,8 @@ def main():
                    "precision": args.precision, "cut": "kl1=500", "seed": 0},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "fp32_path": fp32,
+        "fp32_path": others.get("fp32"),
+        "other_paths": {k2: v2 for k2, v2 in others.items() if k2 != "fp32"},
         "report": {k2: last[k2] for k2 in ("rounds", "rows_scanned", "pairs_evaluated",
                                             "survivors", "overflow_rows", "max_abs_err",
                                             "max_rel_err", "ms_candidates", "ms_rescore",

@@ -70,6 +70,9 @@ typedef enum {
  *   FP16  as BF16 with FP16 operands (D <= 26);
  *   FP8   e4m3 operands; only for integer features in [-16, 16] (D <= 26);
  *   AUTO  FP8 for such integer data, else FP16 when D <= 26, else FP32.
+ * BF16 / FP16 / FP8 also return NNM_EUNSUPPORTED for data whose feature
+ * ranges would need a scale factor outside 2^-60 .. 2^60 (AUTO then uses
+ * FP32).
  */
 typedef enum {
     NNM_PREC_FP32 = 0,

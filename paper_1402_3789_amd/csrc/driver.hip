@@ -305,6 +305,14 @@ nnm_status stage(Run& R, const float* X)
     // BF16 keeps 8 bits: relative to the data's centre its error would swamp
     // nearest-neighbour distances, so its operands are built per tile
     p.local = p.opkind == OP_BF16 && !p.exact;
+    if (p.local && R.o.survivor_cap <= 0) {
+        // BF16's margin is wider: keep 4x the survivors per row (the
+        // survivor buffers hold 2^28 entries whatever the split into rows)
+        const int S4 = p.S * 4 < SMAX ? p.S * 4 : SMAX;
+        p.rmax = p.rmax * p.S / S4;
+        if (p.rmax < 1) p.rmax = 1;
+        p.S = S4;
+    }
     p.op_bytes = (p.opkind == OP_FP8) ? 32 : 64;
     R.bc = BoundConst{};
     R.sigma = 1.f;
