@@ -184,10 +184,31 @@ def mst_build_batched(Xs, precision="auto", knn_k=8, stream=None, workspace=None
     return [Tree(e[: n - 1], n, reps[b].as_dict()) for b, (e, n) in enumerate(outs)]
 
 
+_PINNED = {}
+
+
+def _pinned(nbytes):
+    """A reusable page-locked host buffer of at least nbytes (uint8 tensor)."""
+    torch = _torch()
+    b = _PINNED.get("edges")
+    if b is None or b.numel() < nbytes:
+        b = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, pin_memory=True)
+        _PINNED["edges"] = b
+    return b
+
+
 def _edges_host(tree_or_edges, n):
     if isinstance(tree_or_edges, Tree):
-        buf = np.ascontiguousarray(tree_or_edges.raw.cpu().numpy())
-        return buf, tree_or_edges.n
+        raw = tree_or_edges.raw
+        if raw.is_cuda:
+            # device -> page-locked host copy on the current stream
+            torch = _torch()
+            nb = raw.numel() * raw.element_size()
+            h = _pinned(nb)[:nb].view(torch.float64).view(raw.shape)
+            h.copy_(raw, non_blocking=True)
+            torch.cuda.current_stream(raw.device).synchronize()
+            return h.numpy(), tree_or_edges.n
+        return np.ascontiguousarray(raw.numpy()), tree_or_edges.n
     u, v, s, w = tree_or_edges
     m = len(u)
     buf = np.zeros((max(m, 1), 3), np.float64)
@@ -205,7 +226,7 @@ def cluster_cut(tree, n=None, kl1=0, kl2=-1, kl3=-1, kl4=0, dmax=math.inf):
     """Constrained cut of a sorted tree (host): (labels int32 [n], K)."""
     buf, n = _edges_host(tree, n)
     p = N.CutParams(int(kl1), int(kl2), int(kl3), int(kl4), float(dmax))
-    labels = np.zeros(max(n, 1), np.int32)
+    labels = np.empty(max(n, 1), np.int32)     # every entry is written
     k = ctypes.c_int64(0)
     code = N.lib().cluster_cut(ctypes.c_void_p(buf.ctypes.data), int(n), ctypes.byref(p),
                                ctypes.c_void_p(labels.ctypes.data), ctypes.byref(k))

@@ -314,8 +314,9 @@ struct ChunkIter {
                     }
                     const int off = cs - cbase + (int)__builtin_ctzll(m);
                     cs = cbase + off + 1;
-                    *lo_c = __shfl(my_lo, off);
-                    *hi_c = __shfl(my_hi, off);
+                    // off is wave-uniform: a lane read, not an LDS permute
+                    *lo_c = __builtin_amdgcn_readlane(my_lo, off);
+                    *hi_c = __builtin_amdgcn_readlane(my_hi, off);
                     return zigzag(cbase + off, cstart, c_lo, c_hi);
                 }
                 in_super = false;

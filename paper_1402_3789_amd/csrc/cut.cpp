@@ -21,8 +21,12 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <atomic>
 #include <functional>
+#include <memory>
 #include <queue>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -48,6 +52,80 @@ struct Dsu {
     }
 };
 
+// Without KL2, KL3 and KL4 every admissible tree edge unites two clusters,
+// the admissible edges (w <= dmax) form a prefix of the key order, and the
+// process takes the first m = min(prefix, n - KL1) of them: the result is the
+// forest of those m edges, whatever the order they are united in.  Threads
+// unite them concurrently (lock-free union-find, the larger root index is
+// linked under the smaller, so each root is its component's smallest point);
+// labels follow from the roots in increasing order, i.e. by first appearance.
+void forest_labels(const nnm_edge* edges, int64_t n, int64_t m, int32_t* labels, int64_t* n_clusters)
+{
+    unsigned nt = std::thread::hardware_concurrency();
+    if (nt < 1) nt = 1;
+    if (nt > 16) nt = 16;
+    std::unique_ptr<std::atomic<int32_t>[]> up(new std::atomic<int32_t>[(size_t)n]);
+    std::unique_ptr<int32_t[]> root(new int32_t[(size_t)n]);
+    auto parallel = [&](int64_t count, auto&& body) {
+        std::vector<std::thread> th;
+        const int64_t per = (count + nt - 1) / nt;
+        for (unsigned t = 0; t < nt; ++t) {
+            const int64_t a = (int64_t)t * per, b = std::min<int64_t>(count, a + per);
+            if (a >= b) break;
+            th.emplace_back([=, &body] { body((int)t, a, b); });
+        }
+        for (auto& x : th) x.join();
+    };
+    auto find = [&](int32_t x) {
+        int32_t p = up[(size_t)x].load(std::memory_order_relaxed);
+        while (p != x) {
+            const int32_t g = up[(size_t)p].load(std::memory_order_relaxed);
+            if (g != p) up[(size_t)x].compare_exchange_weak(p, g, std::memory_order_relaxed);
+            x = g;
+            p = up[(size_t)x].load(std::memory_order_relaxed);
+        }
+        return x;
+    };
+    parallel(n, [&](int, int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) up[(size_t)i].store((int32_t)i, std::memory_order_relaxed);
+    });
+    parallel(m, [&](int, int64_t a, int64_t b) {
+        for (int64_t e = a; e < b; ++e) {
+            int32_t x = edges[e].u, y = edges[e].v;
+            for (;;) {
+                x = find(x);
+                y = find(y);
+                if (x == y) break;
+                if (x > y) std::swap(x, y);          // link y (larger) under x
+                int32_t expect = y;
+                if (up[(size_t)y].compare_exchange_strong(expect, x, std::memory_order_acq_rel)) break;
+            }
+        }
+    });
+    std::vector<int64_t> count(nt + 1, 0);
+    parallel(n, [&](int t, int64_t a, int64_t b) {
+        int64_t c = 0;
+        for (int64_t i = a; i < b; ++i) {
+            root[(size_t)i] = find((int32_t)i);
+            c += root[(size_t)i] == (int32_t)i;
+        }
+        count[(size_t)t + 1] = c;
+    });
+    for (unsigned t = 0; t < nt; ++t) count[t + 1] += count[t];
+    // names of the roots (a root is the smallest index of its component, so
+    // every root precedes its members): rank among roots
+    parallel(n, [&](int t, int64_t a, int64_t b) {
+        int64_t c = count[(size_t)t];
+        for (int64_t i = a; i < b; ++i)
+            if (root[(size_t)i] == (int32_t)i) labels[i] = (int32_t)c++;
+    });
+    parallel(n, [&](int, int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i)
+            if (root[(size_t)i] != (int32_t)i) labels[i] = labels[root[(size_t)i]];
+    });
+    *n_clusters = count[nt];
+}
+
 bool key_before(const nnm_edge& a, const nnm_edge& b)
 {
     if (a.s != b.s) return a.s < b.s;
@@ -63,10 +141,30 @@ extern "C" nnm_status cluster_cut(const nnm_edge* edges, int64_t n, const nnm_cu
     if (n < 1 || !prm || !labels || !n_clusters) return NNM_EINVAL;
     if (n > 1 && !edges) return NNM_EINVAL;
     const int64_t ne = n - 1;
-    for (int64_t e = 0; e < ne; ++e) {
-        const nnm_edge& x = edges[e];
-        if (x.u < 0 || x.u >= x.v || x.v >= n || !(x.s >= 0.0)) return NNM_EINVAL;
-        if (e > 0 && !key_before(edges[e - 1], x)) return NNM_EINVAL;
+    {
+        // every edge well formed and the keys strictly increasing
+        auto check = [&](int64_t a, int64_t b) {
+            for (int64_t e = a; e < b; ++e) {
+                const nnm_edge& x = edges[e];
+                if (x.u < 0 || x.u >= x.v || x.v >= n || !(x.s >= 0.0)) return false;
+                if (e > 0 && !key_before(edges[e - 1], x)) return false;
+            }
+            return true;
+        };
+        unsigned nt = ne >= 65536 ? std::thread::hardware_concurrency() : 1;
+        if (nt < 1) nt = 1;
+        if (nt > 16) nt = 16;
+        std::vector<char> ok(nt, 1);
+        std::vector<std::thread> th;
+        const int64_t per = (ne + nt - 1) / nt;
+        for (unsigned t = 1; t < nt; ++t) {
+            const int64_t a = (int64_t)t * per, b = std::min<int64_t>(ne, a + per);
+            if (a < b) th.emplace_back([&, t, a, b] { ok[t] = check(a, b); });
+        }
+        ok[0] = check(0, std::min<int64_t>(ne, per));
+        for (auto& x : th) x.join();
+        for (char c : ok)
+            if (!c) return NNM_EINVAL;
     }
     const int64_t kl1 = prm->kl1_max_clusters;
     const int64_t kl2 = prm->kl2_max_size;
@@ -74,6 +172,19 @@ extern "C" nnm_status cluster_cut(const nnm_edge* edges, int64_t n, const nnm_cu
     const int64_t kl4 = prm->kl4_min_size;
     const double dmax = prm->dmax;
     const bool priority = kl4 > 1;
+
+    if (kl2 < 0 && kl3 < 0 && !priority && n >= 65536) {
+        int64_t lo = 0, hi = ne;                // admissible prefix (w <= dmax)
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (!(edges[mid].w > dmax)) lo = mid + 1;   // the discard test below
+            else hi = mid;
+        }
+        int64_t m = lo;
+        if (kl1 > 0) m = std::min<int64_t>(m, std::max<int64_t>(0, n - kl1));
+        forest_labels(edges, n, m, labels, n_clusters);
+        return NNM_OK;
+    }
 
     Dsu dsu(n);
     int64_t clusters = n;

@@ -144,3 +144,31 @@ def test_cut_rejects_bad_edges():
                          np.array([1.0, 1.5])), 3)                      # v out of range
     lab, k = nnm.cluster_cut((u[:0], v[:0], s[:0], s[:0]), 1)
     assert k == 1 and lab.tolist() == [0]
+
+
+def _big_sorted_tree(rng, n):
+    """A random spanning tree with key-sorted edges (ties included)."""
+    i = np.arange(1, n, dtype=np.int64)
+    par = (rng.random(n - 1) * i).astype(np.int64)
+    u = np.minimum(par, i).astype(np.int32)
+    v = np.maximum(par, i).astype(np.int32)
+    s = np.round(rng.random(n - 1) * 1000.0) / 1000.0      # many equal keys
+    o = np.lexsort((v, u, s))
+    u, v, s = u[o], v[o], s[o]
+    return u, v, s, np.sqrt(s)
+
+
+def test_cut_large_forest_path_matches_oracle():
+    """n >= 65536 without KL2/KL3/KL4 takes the threaded forest path."""
+    rng = np.random.default_rng(7)
+    n = 200_003
+    u, v, s, w = _big_sorted_tree(rng, n)
+    for kl1, dmax in [(0, math.inf), (500, math.inf), (1, math.inf), (n + 5, math.inf),
+                      (0, float(np.median(w))), (64, 0.2), (500, 0.0), (0, math.nan)]:
+        got, k = nnm.cluster_cut((u, v, s, w), n, kl1=kl1, dmax=dmax)
+        exp, ke = oracle.cut(u, v, s, w, n, kl1, -1, -1, 0, dmax)
+        assert k == ke and np.array_equal(got, exp), (kl1, dmax)
+    # and the general path at the same size
+    got, k = nnm.cluster_cut((u, v, s, w), n, kl1=100, kl4=3)
+    exp, ke = oracle.cut(u, v, s, w, n, 100, -1, -1, 3, math.inf)
+    assert k == ke and np.array_equal(got, exp)
