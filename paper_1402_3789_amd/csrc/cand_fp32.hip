@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
     if (!a.share && valid) a.surv_cnt[slot] = cnt;
     const int wrows = sh.rows - (tid >> 6) * 64;
     if ((tid & 63) == 0 && a.pairs && wrows > 0)
-        atomicAdd(&a.pairs[(blockIdx.x * 4 + (tid >> 6)) & (NSPREAD - 1)],
+        atomicAdd(&a.pairs[((blockIdx.x * 4 + (tid >> 6)) & (NSPREAD - 1)) * SPREAD_STRIDE],
                   pairs * (unsigned long long)(wrows < 64 ? wrows : 64));
 }
 

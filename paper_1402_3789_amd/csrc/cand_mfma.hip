@@ -660,7 +660,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     if (!SHARE && my_valid) a.surv_cnt[my_slot] = rowCnt[tid];
     const int wrows = sh.rows - wave * 64;
     if (lane == 0 && a.pairs && wrows > 0)
-        atomicAdd(&a.pairs[(blockIdx.x * 4 + wave) & (NSPREAD - 1)],
+        atomicAdd(&a.pairs[((blockIdx.x * 4 + wave) & (NSPREAD - 1)) * SPREAD_STRIDE],
                   pairs * (unsigned long long)(wrows < 64 ? wrows : 64));
 }
 

@@ -30,17 +30,18 @@ struct Counters {
     int32_t over;                   // overflowed rows in the last batch
     int32_t tcount;                 // tiles of the last batch
     int32_t pad_[5];
-    // totals spread over NSPREAD slots (slot = workgroup mod NSPREAD), so
-    // that no single address takes an atomic from every workgroup
-    unsigned long long pairs[NSPREAD];
-    unsigned long long survivors[NSPREAD];
+    // totals spread over NSPREAD slots on separate cache lines (slot =
+    // workgroup mod NSPREAD), so that no address or line takes an atomic
+    // from every workgroup
+    unsigned long long pairs[NSPREAD * SPREAD_STRIDE];
+    unsigned long long survivors[NSPREAD * SPREAD_STRIDE];
     unsigned long long err_bits[2];
 };
 
 unsigned long long spread_sum(const unsigned long long* v)
 {
     unsigned long long t = 0;
-    for (int i = 0; i < NSPREAD; ++i) t += v[i];
+    for (int i = 0; i < NSPREAD; ++i) t += v[i * SPREAD_STRIDE];
     return t;
 }
 

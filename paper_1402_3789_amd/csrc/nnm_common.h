@@ -21,6 +21,7 @@ constexpr int KMAX = 32;                         // neighbour-cache depth
 // at [DMAX], zero padding to a 16-byte multiple.
 constexpr int BALL_STRIDE = DMAX + 4;
 constexpr int NSPREAD = 64;           // slots of the spread event counters
+constexpr int SPREAD_STRIDE = 16;     // u64 per slot: one 128-byte cache line each
 constexpr int SMAX = 2048;                       // survivor cap
 
 enum OpKind : int { OP_BF16 = 0, OP_FP16 = 1, OP_FP8 = 2, OP_FP32 = 3 };
@@ -186,7 +187,7 @@ struct CandArgs {
     int32_t* surv_cnt;        // [n_rows]
     int32_t* surv_j;          // [n_rows][S] sorted column positions
     float* surv_t;            // [n_rows][S] candidate values
-    unsigned long long* pairs;// [NSPREAD] accumulated count of evaluated pairs
+    unsigned long long* pairs;// [NSPREAD * SPREAD_STRIDE] count of evaluated pairs
     // chunk pruning and near-first order
     const float* X;           // original features (row-tile balls)
     int64_t ld;
@@ -237,7 +238,7 @@ struct RescoreArgs {
     int32_t kb;               // level 1 bound: the kb-th key of the first S survivors
     double* u0b;              // [n] by sorted position: bound for the re-scan (level 1)
     int32_t* oflag;           // [n] by sorted position: row overflowed (level 1)
-    unsigned long long* survivors; // [NSPREAD] counter
+    unsigned long long* survivors; // [NSPREAD * SPREAD_STRIDE] counter
     unsigned long long* err_bits;  // [2]: max abs err, max rel err (double bits)
 };
 

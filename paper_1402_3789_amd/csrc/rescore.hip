@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
         a.clb[i] = __builtin_huge_val();
         a.cflag[i] = 1;
     }
-    atomicAdd(&a.survivors[slot & (NSPREAD - 1)], (unsigned long long)nsurv);
+    atomicAdd(&a.survivors[(slot & (NSPREAD - 1)) * SPREAD_STRIDE], (unsigned long long)nsurv);
 }
 
 // Exact top-k of one row over every point outside its component, by a full
