@@ -156,12 +156,20 @@ __global__ __launch_bounds__(256) void k_break(MergeArgs a)
 
 __global__ __launch_bounds__(256) void k_emit(MergeArgs a)
 {
-    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= a.n) return;
-    if (a.comp[c] != c || a.parent[c] == c) return;
-    const unsigned long long p = a.cbest_p[c];
-    const int e = atomicAdd(&a.counters[0], 1);
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool emit = c < a.n && a.comp[c] == c && a.parent[c] != c;
+    // one counter atomic per wave; lanes take consecutive slots
+    const unsigned long long m = __ballot(emit);
+    if (!m) return;
+    const int leader = (int)__builtin_ctzll(m);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&a.counters[0], (int)__popcll(m));
+    base = __shfl(base, leader);
+    if (!emit) return;
+    const int e = base + (int)__popcll(m & ((1ull << lane) - 1ull));
     if (e >= a.n) return;   // cannot happen: a tree has n - 1 edges
+    const unsigned long long p = a.cbest_p[c];
     SortRec r;
     r.k0 = a.cbest_s[c];
     r.k1 = (uint32_t)(p >> 32);

@@ -104,8 +104,12 @@ __global__ __launch_bounds__(256) void k_stage_operands_16(
     const float* __restrict__ centre, float sigma, uint16_t* __restrict__ opR,
     uint16_t* __restrict__ opC, PointConst* __restrict__ pc, StageStats* st)
 {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    // lanes past the end repeat the last point (for the wave maxima) and
+    // store nothing
+    const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (blockIdx.x * (int64_t)blockDim.x >= n) return;
+    const bool valid = gi < n;
+    const int64_t i = valid ? gi : n - 1;
     uint16_t q[KSLOT];
     double nrm = 0.0, vn = 0.0;
 #pragma unroll
@@ -145,21 +149,23 @@ __global__ __launch_bounds__(256) void k_stage_operands_16(
         col[DMAX_MFMA + k] = one;
         col[DMAX_MFMA + NORM_PARTS + k] = part[k];
     }
-    uint4* dR = reinterpret_cast<uint4*>(opR + i * KSLOT);
-    uint4* dC = reinterpret_cast<uint4*>(opC + i * KSLOT);
+    if (valid) {
+        uint4* dR = reinterpret_cast<uint4*>(opR + i * KSLOT);
+        uint4* dC = reinterpret_cast<uint4*>(opC + i * KSLOT);
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        uint4 a, b;
-        a.x = row[8 * w + 0] | ((uint32_t)row[8 * w + 1] << 16);
-        a.y = row[8 * w + 2] | ((uint32_t)row[8 * w + 3] << 16);
-        a.z = row[8 * w + 4] | ((uint32_t)row[8 * w + 5] << 16);
-        a.w = row[8 * w + 6] | ((uint32_t)row[8 * w + 7] << 16);
-        b.x = col[8 * w + 0] | ((uint32_t)col[8 * w + 1] << 16);
-        b.y = col[8 * w + 2] | ((uint32_t)col[8 * w + 3] << 16);
-        b.z = col[8 * w + 4] | ((uint32_t)col[8 * w + 5] << 16);
-        b.w = col[8 * w + 6] | ((uint32_t)col[8 * w + 7] << 16);
-        dR[w] = a;
-        dC[w] = b;
+        for (int w = 0; w < 4; ++w) {
+            uint4 a, b;
+            a.x = row[8 * w + 0] | ((uint32_t)row[8 * w + 1] << 16);
+            a.y = row[8 * w + 2] | ((uint32_t)row[8 * w + 3] << 16);
+            a.z = row[8 * w + 4] | ((uint32_t)row[8 * w + 5] << 16);
+            a.w = row[8 * w + 6] | ((uint32_t)row[8 * w + 7] << 16);
+            b.x = col[8 * w + 0] | ((uint32_t)col[8 * w + 1] << 16);
+            b.y = col[8 * w + 2] | ((uint32_t)col[8 * w + 3] << 16);
+            b.z = col[8 * w + 4] | ((uint32_t)col[8 * w + 5] << 16);
+            b.w = col[8 * w + 6] | ((uint32_t)col[8 * w + 7] << 16);
+            dR[w] = a;
+            dC[w] = b;
+        }
     }
     PointConst p;
     if (exact) {
@@ -171,11 +177,15 @@ __global__ __launch_bounds__(256) void k_stage_operands_16(
         p.eta = d2f_up((LpBound<OP>::alpha * __builtin_sqrt(vn) * (1.0 + 0x1p-40) +
                         LpBound<OP>::beta * __builtin_sqrt((double)d)) * (1.0 + 0x1p-40));
     }
-    pc[i] = p;
-    atomicMax(&st->colmax[0], __float_as_uint(p.Q));
-    atomicMax(&st->colmax[1], __float_as_uint(p.P));
-    atomicMax(&st->colmax[2], __float_as_uint(p.rho));
-    atomicMax(&st->colmax[3], __float_as_uint(p.eta));
+    if (valid) pc[i] = p;
+    // column maxima: one atomic per wave and quantity (non-negative floats
+    // order as their bits)
+    float m4[4] = {p.Q, p.P, p.rho, p.eta};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        for (int off = 32; off > 0; off >>= 1) m4[q] = fmaxf(m4[q], __shfl_xor(m4[q], off));
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 4; ++q) atomicMax(&st->colmax[q], __float_as_uint(m4[q]));
 }
 
 __device__ __forceinline__ uint8_t to_fp8(float f)
