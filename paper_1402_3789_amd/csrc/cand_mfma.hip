@@ -583,16 +583,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         };
         // two 16-column blocks per step: 8 MFMAs, then one min3 chain and
         // one compare per row block for 8 candidates
-        int cb = 0;
-        // the next step's column fragments are read while this step's MFMAs run
-        frag_t nf0 = cbuf[(0 * 4 + grp) * 16 + (lane & 15)];
-        frag_t nf1 = cbuf[(1 * 4 + grp) * 16 + (lane & 15)];
-        for (; cb + 1 < nblk; cb += 2) {
-            const frag_t af0 = nf0, af1 = nf1;
-            if (cb + 3 < nblk) {
-                nf0 = cbuf[((cb + 2) * 4 + grp) * 16 + (lane & 15)];
-                nf1 = cbuf[((cb + 3) * 4 + grp) * 16 + (lane & 15)];
-            }
+        auto step2 = [&](int cb, const frag_t& af0, const frag_t& af1) {
             f32x4_t acc0[RB], acc1[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc0[rb] = Tr::mma(af0, bfrag[rb]);
@@ -610,6 +601,26 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
             if (__ballot(hit)) {
                 slow(cb, acc0, acc1, true);
                 reload_T();
+            }
+        };
+        auto frag = [&](int blk) { return cbuf[(blk * 4 + grp) * 16 + (lane & 15)]; };
+        // unrolled by two steps with two fragment sets, so the fragments of
+        // the next step are read while this step's MFMAs run, without copies
+        int cb = 0;
+        if (nblk >= 2) {
+            frag_t fa0 = frag(0), fa1 = frag(1);
+            for (; cb + 3 < nblk; cb += 4) {
+                const frag_t fb0 = frag(cb + 2), fb1 = frag(cb + 3);
+                step2(cb, fa0, fa1);
+                if (cb + 5 < nblk) {
+                    fa0 = frag(cb + 4);
+                    fa1 = frag(cb + 5);
+                }
+                step2(cb + 2, fb0, fb1);
+            }
+            if (cb + 1 < nblk) {
+                step2(cb, fa0, fa1);
+                cb += 2;
             }
         }
         if (cb < nblk) {
