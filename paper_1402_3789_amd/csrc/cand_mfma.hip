@@ -219,12 +219,15 @@ __device__ __forceinline__ void local_operands(const float* x, const float* c, f
 // are used.
 //
 // Per-row state in LDS (thread t owns row t of the tile; the slow path of
-// the wave holding the row touches it one lane group at a time):
-//   rowU  bound on the row's k-th key (data units), rowT threshold on t,
-//   rowEps / rowEta the row's slack for the current chunk, rowCnt its
-//   survivor count, topk its k smallest candidates (t, or for LOCAL upper
-//   bounds on keys in data units, since the frame changes per chunk).
-template <int OP, bool LOCAL, bool SHARE>
+// the wave holding the row touches it one lane group at a time), packed so
+// that the slow path reads it with two vector loads:
+//   rs[r][0] = (T, U, eps, eta): threshold on t, bound on the row's k-th key
+//              (data units), the row's slack for the current chunk;
+//   rs[r][1] = (survivor count, component) as integer bits;
+//   topk[r][0..KP): the k smallest candidates, +inf padded (t, or for LOCAL
+//              upper bounds on keys in data units, since the frame changes
+//              per chunk).  KP is k rounded up to 8 or 32.
+template <int OP, bool LOCAL, bool SHARE, int KP>
 __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
 {
     typedef OpTraits<OP> Tr;
@@ -235,12 +238,11 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     __shared__ __align__(16) int32_t colcomp[2][BN];
     __shared__ float cmax[2][4][4];                        // LOCAL: per-wave column maxima
     __shared__ __align__(16) float ballbuf[2][BALL_STRIDE];  // the chunk's bounding ball
-    __shared__ float rowT[BM], rowU[BM], rowEps[BM], rowEta[BM];
-    __shared__ int32_t rowCnt[BM];
-    __shared__ int32_t rowComp[BM];
-    __shared__ float wmx[2][4];                            // per-wave max of rowU, double-buffered
+    __shared__ float4 rs[BM][2];                           // per-row state, see above
+    __shared__ float wmx[2][4];                            // per-wave max of U, double-buffered
     __shared__ TileShared sh;
-    extern __shared__ float topk[];                        // [BM][k]
+    extern __shared__ float4 topk4[];                      // [BM][KP / 4]
+    float* topk = reinterpret_cast<float*>(topk4);
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -272,8 +274,8 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     float4 xq[NQR];                                        // kept for the per-row ball tests
 #pragma unroll
     for (int q = 0; q < NQR; ++q) xq[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
-    float* my_tk = topk + tid * k;
-    for (int e = 0; e < k; ++e) my_tk[e] = __builtin_huge_valf();
+    float* my_tk = topk + tid * KP;
+    for (int e = 0; e < KP; ++e) my_tk[e] = __builtin_huge_valf();
     float U = 0.f;
     if (my_valid) {
         U = __builtin_huge_valf();
@@ -307,12 +309,11 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                 }
             }
             U = my_tk[k - 1];
-            for (int e = 0; e < k; ++e) my_tk[e] = __builtin_huge_valf();
+            for (int e = 0; e < KP; ++e) my_tk[e] = __builtin_huge_valf();
         }
     }
-    rowU[tid] = U;
-    rowCnt[tid] = 0;
-    rowComp[tid] = my_comp;
+    rs[tid][0] = make_float4(-__builtin_huge_valf(), U, 0.f, 0.f);
+    rs[tid][1] = make_float4(__int_as_float(0), __int_as_float(my_comp), 0.f, 0.f);
     if (a.prune || LOCAL) tile_ball<DMAX>(sh, x, my_valid, a.d);
     // row operand and its bound inputs
     PointConst mypc{0.f, 0.f, 0.f, 0.f};
@@ -325,9 +326,9 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     } else {
         if (my_valid) mypc = a.pc[my_rp];
         // one frame for every pair: the row's slack is fixed
-        rowEps[tid] = (a.bc.gamma * (2.f * mypc.Q * a.bc.colQ + mypc.P + a.bc.colP) + mypc.rho + a.bc.colRho) *
-                      (1.f + 0x1p-20f);
-        rowEta[tid] = (mypc.eta + a.bc.colEta) * (1.f + 0x1p-22f);
+        rs[tid][0].z = (a.bc.gamma * (2.f * mypc.Q * a.bc.colQ + mypc.P + a.bc.colP) + mypc.rho + a.bc.colRho) *
+                       (1.f + 0x1p-20f);
+        rs[tid][0].w = (mypc.eta + a.bc.colEta) * (1.f + 0x1p-22f);
     }
     if (tid == 0) {
         const int64_t last = row_end - 1;
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     bool wdirty = true;
     auto wave_max = [&](int b) {
         if (wdirty) {
-            float v = my_valid ? rowU[tid] : 0.f;
+            float v = my_valid ? rs[tid][0].y : 0.f;
             for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
             wm = v;
             wdirty = false;
@@ -477,7 +478,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         // skip does no work on the chunk
         bool need = my_valid && !(pure && lo_c == my_comp);
         if (a.prune && need)
-            need = point_ball_lb2(xq, &ballbuf[b][0]) <= rowU[tid];
+            need = point_ball_lb2(xq, &ballbuf[b][0]) <= rs[tid][0].y;
         if (!__ballot(need)) return;
         // this chunk's threshold for the row; the wave's rows are read back
         // by other lanes of the same wave only
@@ -490,13 +491,13 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                 const float colE = fmaxf(fmaxf(cmax[b][0][3], cmax[b][1][3]), fmaxf(cmax[b][2][3], cmax[b][3][3]));
                 eps = (a.bc.gamma * (2.f * mypc.Q * colQ + mypc.P + colP) + mypc.rho + colR) * (1.f + 0x1p-20f);
                 eta = (mypc.eta + colE) * (1.f + 0x1p-22f);
-                rowEps[tid] = eps;
-                rowEta[tid] = eta;
+                rs[tid][0].z = eps;
+                rs[tid][0].w = eta;
             } else {
-                eps = rowEps[tid];
-                eta = rowEta[tid];
+                eps = rs[tid][0].z;
+                eta = rs[tid][0].w;
             }
-            rowT[tid] = my_valid ? thresh_from_U(rowU[tid] * s2, eps, eta, exact) : -__builtin_huge_valf();
+            rs[tid][0].x = my_valid ? thresh_from_U(rs[tid][0].y * s2, eps, eta, exact) : -__builtin_huge_valf();
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -508,7 +509,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         auto reload_T = [&]() {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
-                Treg[rb] = own[rb] ? -__builtin_huge_valf() : rowT[wave * RB * 16 + rb * 16 + (lane & 15)];
+                Treg[rb] = own[rb] ? -__builtin_huge_valf() : rs[wave * RB * 16 + rb * 16 + (lane & 15)][0].x;
         };
         reload_T();
         pairs += (unsigned long long)ncols;
@@ -541,37 +542,65 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                         const float v = pick32(acc0, acc1, e);
                         const int rb = (e >> 2) & 3, r = e & 3;
                         const int rl = wave * RB * 16 + rb * 16 + (lane & 15);
-                        if (!(v <= rowT[rl])) continue;
+                        const float4 st = rs[rl][0];              // T, U, eps, eta
+                        if (!(v <= st.x)) continue;
                         // same component, or a column this tile must not pair with
                         const int cj = (cb + (e >> 4)) * 16 + 4 * g + r;
                         const int cc = ccomp[cj];
-                        // (from LDS: a select over the register array would
-                        // be lowered to a private-memory array)
-                        if (cc < 0 || cc == rowComp[rl]) continue;
+                        const float4 s1 = rs[rl][1];              // count, component
+                        if (cc < 0 || cc == __float_as_int(s1.y)) continue;
                         const int64_t slot = row_base + rl;
-                        const int pos = SHARE ? atomicAdd(&a.surv_cnt[slot], 1) : rowCnt[rl]++;
+                        int pos;
+                        if (SHARE) {
+                            pos = atomicAdd(&a.surv_cnt[slot], 1);
+                        } else {
+                            pos = __float_as_int(s1.x);
+                            rs[rl][1].x = __int_as_float(pos + 1);
+                        }
                         if (pos < a.S) {
                             a.surv_j[slot * a.S + pos] = (int)(c0 + cj);
                             a.surv_t[slot * a.S + pos] = v;
                         }
-                        const float eps = rowEps[rl], eta = rowEta[rl];
+                        const float eps = st.z, eta = st.w;
                         // LOCAL: a bound on the key (data units); else t itself
                         const float key = LOCAL ? d2f_up((double)upper_from_t(v, eps, eta, exact) * inv_s2) : v;
-                        float* tk = topk + rl * k;
-                        if (key < tk[k - 1]) {
-                            int p = k - 1;
-                            while (p > 0 && tk[p - 1] > key) { tk[p] = tk[p - 1]; --p; }
-                            tk[p] = key;
-                            const float kth = tk[k - 1];
+                        // the row's list, read and rewritten with vector accesses
+                        float4* tk4 = topk4 + rl * (KP / 4);
+                        float4 tq[KP / 4];
+#pragma unroll
+                        for (int q = 0; q < KP / 4; ++q) tq[q] = tk4[q];
+                        float kth_old = __builtin_huge_valf();
+#pragma unroll
+                        for (int q = 0; q < KP / 4; ++q) {
+                            const float x4[4] = {tq[q].x, tq[q].y, tq[q].z, tq[q].w};
+#pragma unroll
+                            for (int h = 0; h < 4; ++h)
+                                if (4 * q + h == k - 1) kth_old = x4[h];
+                        }
+                        if (key < kth_old) {
+                            // insert into the sorted first k entries
+                            float prev = -__builtin_huge_valf(), kth = 0.f;
+#pragma unroll
+                            for (int q = 0; q < KP / 4; ++q) {
+                                float x4[4] = {tq[q].x, tq[q].y, tq[q].z, tq[q].w};
+#pragma unroll
+                                for (int h = 0; h < 4; ++h) {
+                                    const int e2 = 4 * q + h;
+                                    const float old = x4[h];
+                                    if (e2 < k) x4[h] = old <= key ? old : (prev <= key ? key : prev);
+                                    if (e2 == k - 1) kth = x4[h];
+                                    prev = old;
+                                }
+                                tk4[q] = make_float4(x4[0], x4[1], x4[2], x4[3]);
+                            }
                             if (kth < __builtin_huge_valf()) {
                                 const float Usc = LOCAL ? kth * s2 : upper_from_t(kth, eps, eta, exact);
                                 const float Us = LOCAL ? kth : d2f_up((double)Usc * inv_s2);
-                                if (Us < rowU[rl]) {
-                                    rowU[rl] = Us;
-                                    if (SHARE) atomicMin(&a.gU[slot], __float_as_uint(Us));
-                                }
                                 const float T = thresh_from_U(Usc, eps, eta, exact);
-                                if (T < rowT[rl]) rowT[rl] = T;
+                                if (Us < st.y || T < st.x) {
+                                    if (SHARE && Us < st.y) atomicMin(&a.gU[slot], __float_as_uint(Us));
+                                    rs[rl][0] = make_float4(fminf(st.x, T), fminf(st.y, Us), eps, eta);
+                                }
                             }
                         }
                     }
@@ -654,7 +683,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         // bounds found by the other column splits of the row (read before the
         // next chunk's loads are issued: process() must not wait on those)
         if (SHARE) {
-            if (my_valid) rowU[tid] = fminf(rowU[tid], __uint_as_float(a.gU[my_slot]));
+            if (my_valid) rs[tid][0].y = fminf(rs[tid][0].y, __uint_as_float(a.gU[my_slot]));
             wdirty = true;
         }
         int nlo = 0, nhi = 0;
@@ -668,7 +697,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         cur_hi = nhi;
         buf ^= 1;
     }
-    if (!SHARE && my_valid) a.surv_cnt[my_slot] = rowCnt[tid];
+    if (!SHARE && my_valid) a.surv_cnt[my_slot] = __float_as_int(rs[tid][1].x);
     const int wrows = sh.rows - wave * 64;
     if (lane == 0 && a.pairs && wrows > 0)
         atomicAdd(&a.pairs[((blockIdx.x * 4 + wave) & (NSPREAD - 1)) * SPREAD_STRIDE],
@@ -676,10 +705,17 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
 }
 
 template <int OP, bool LOCAL>
-void launch_one(const CandArgs& a, dim3 grid, size_t shm, hipStream_t s)
+void launch_one(const CandArgs& a, dim3 grid, size_t, hipStream_t s)
 {
-    if (a.share) k_cand_mfma<OP, LOCAL, true><<<grid, 256, shm, s>>>(a);
-    else k_cand_mfma<OP, LOCAL, false><<<grid, 256, shm, s>>>(a);
+    if (a.k <= 8) {
+        const size_t shm = (size_t)BM * 8 * sizeof(float);
+        if (a.share) k_cand_mfma<OP, LOCAL, true, 8><<<grid, 256, shm, s>>>(a);
+        else k_cand_mfma<OP, LOCAL, false, 8><<<grid, 256, shm, s>>>(a);
+    } else {
+        const size_t shm = (size_t)BM * KMAX * sizeof(float);
+        if (a.share) k_cand_mfma<OP, LOCAL, true, KMAX><<<grid, 256, shm, s>>>(a);
+        else k_cand_mfma<OP, LOCAL, false, KMAX><<<grid, 256, shm, s>>>(a);
+    }
 }
 
 }  // namespace
