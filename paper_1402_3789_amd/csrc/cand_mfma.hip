@@ -329,6 +329,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         rs[tid][0].z = (a.bc.gamma * (2.f * mypc.Q * a.bc.colQ + mypc.P + a.bc.colP) + mypc.rho + a.bc.colRho) *
                        (1.f + 0x1p-20f);
         rs[tid][0].w = (mypc.eta + a.bc.colEta) * (1.f + 0x1p-22f);
+        rs[tid][0].x = my_valid ? thresh_from_U(U * s2, rs[tid][0].z, rs[tid][0].w, exact) : -__builtin_huge_valf();
     }
     if (tid == 0) {
         const int64_t last = row_end - 1;
@@ -480,11 +481,13 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         if (a.prune && need)
             need = point_ball_lb2(xq, &ballbuf[b][0]) <= rs[tid][0].y;
         if (!__ballot(need)) return;
-        // this chunk's threshold for the row; the wave's rows are read back
-        // by other lanes of the same wave only
-        {
+        // per-tile frame: this chunk's slack and threshold for the row (the
+        // wave's rows are read back by other lanes of the same wave only).
+        // In the global frame the slack is fixed and T follows U wherever U
+        // moves, so nothing is recomputed per chunk.
+        if constexpr (LOCAL) {
             float eps, eta;
-            if constexpr (LOCAL) {
+            {
                 const float colQ = fmaxf(fmaxf(cmax[b][0][0], cmax[b][1][0]), fmaxf(cmax[b][2][0], cmax[b][3][0]));
                 const float colP = fmaxf(fmaxf(cmax[b][0][1], cmax[b][1][1]), fmaxf(cmax[b][2][1], cmax[b][3][1]));
                 const float colR = fmaxf(fmaxf(cmax[b][0][2], cmax[b][1][2]), fmaxf(cmax[b][2][2], cmax[b][3][2]));
@@ -493,15 +496,12 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                 eta = (mypc.eta + colE) * (1.f + 0x1p-22f);
                 rs[tid][0].z = eps;
                 rs[tid][0].w = eta;
-            } else {
-                eps = rs[tid][0].z;
-                eta = rs[tid][0].w;
             }
             rs[tid][0].x = my_valid ? thresh_from_U(rs[tid][0].y * s2, eps, eta, exact) : -__builtin_huge_valf();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // rows of a one-component chunk's own component see no candidate
         bool own[RB];
 #pragma unroll
@@ -683,7 +683,14 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         // bounds found by the other column splits of the row (read before the
         // next chunk's loads are issued: process() must not wait on those)
         if (SHARE) {
-            if (my_valid) rs[tid][0].y = fminf(rs[tid][0].y, __uint_as_float(a.gU[my_slot]));
+            if (my_valid) {
+                const float g = __uint_as_float(a.gU[my_slot]);
+                if (g < rs[tid][0].y) {
+                    rs[tid][0].y = g;
+                    if (!LOCAL)
+                        rs[tid][0].x = fminf(rs[tid][0].x, thresh_from_U(g * s2, rs[tid][0].z, rs[tid][0].w, exact));
+                }
+            }
             wdirty = true;
         }
         int nlo = 0, nhi = 0;
