@@ -53,6 +53,7 @@ constexpr int RB = 4;                 // 16-row blocks per wave
 constexpr int BM = WAVES * RB * 16;   // rows per workgroup (= threads)
 constexpr int BN = CHUNK;             // columns per LDS chunk
 constexpr float KFAC = 1.0f + 0x1p-20f;
+constexpr int SEEDW = 32;             // seeding window: sweep-order neighbours on each side
 constexpr int NQR = (DMAX_MFMA + 3) / 4;   // float4s of a row's coordinates
 
 template <int OP> struct OpTraits;
@@ -284,9 +285,9 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
             if (u0 >= 0.0) U = d2f_up(u0);
         }
         if (!(U < __builtin_huge_valf())) {
-            // no bound yet: seed one from the row's neighbours in the sorted
-            // order (distinct admissible columns, keys bounded from FP32)
-            for (int o = -k; o <= k; ++o) {
+            // no bound yet: seed one from the row's 2 SEEDW neighbours in the
+            // sorted order (distinct admissible columns, keys bounded from FP32)
+            for (int o = -SEEDW; o <= SEEDW; ++o) {
                 const int64_t q = (int64_t)my_rp + o;
                 if (o == 0 || q < tile.z || q >= tile.w || q >= a.np || a.compS[q] == my_comp) continue;
                 const float4* src = reinterpret_cast<const float4*>(a.xs + q * DMAX);
@@ -542,12 +543,17 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                         const float v = pick32(acc0, acc1, e);
                         const int rb = (e >> 2) & 3, r = e & 3;
                         const int rl = wave * RB * 16 + rb * 16 + (lane & 15);
+                        // every LDS read this hit may need, issued together
+                        const int cj = (cb + (e >> 4)) * 16 + 4 * g + r;
                         const float4 st = rs[rl][0];              // T, U, eps, eta
+                        const float4 s1 = rs[rl][1];              // count, component
+                        const int cc = ccomp[cj];
+                        float4* tk4 = topk4 + rl * (KP / 4);
+                        float4 tq[KP / 4];
+#pragma unroll
+                        for (int q = 0; q < KP / 4; ++q) tq[q] = tk4[q];
                         if (!(v <= st.x)) continue;
                         // same component, or a column this tile must not pair with
-                        const int cj = (cb + (e >> 4)) * 16 + 4 * g + r;
-                        const int cc = ccomp[cj];
-                        const float4 s1 = rs[rl][1];              // count, component
                         if (cc < 0 || cc == __float_as_int(s1.y)) continue;
                         const int64_t slot = row_base + rl;
                         int pos;
@@ -564,11 +570,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                         const float eps = st.z, eta = st.w;
                         // LOCAL: a bound on the key (data units); else t itself
                         const float key = LOCAL ? d2f_up((double)upper_from_t(v, eps, eta, exact) * inv_s2) : v;
-                        // the row's list, read and rewritten with vector accesses
-                        float4* tk4 = topk4 + rl * (KP / 4);
-                        float4 tq[KP / 4];
-#pragma unroll
-                        for (int q = 0; q < KP / 4; ++q) tq[q] = tk4[q];
+                        // the row's list (read above), rewritten with vector stores
                         float kth_old = __builtin_huge_valf();
 #pragma unroll
                         for (int q = 0; q < KP / 4; ++q) {
