@@ -260,6 +260,7 @@ struct Run {
     float sigma = 1.f;
     int splits_opt = 0;
     int round = 0;          // current merge round (per-round report entries)
+    int kk = 0;             // neighbours sought by the current scan (0 = the cache depth)
 };
 
 int ceil_log2(int64_t v)
@@ -417,8 +418,9 @@ nnm_status sort_points(Run& R, const float* X)
     if (p.opkind != OP_FP32 && !p.local)
         HIP_TRY(launch_gather_points(p.n, p.opkind, w.perm, w.opR, w.opC, w.pc, X, p.d, p.ld, w.comp,
                                      w.opRs, w.opCs, w.pcs, w.xs, w.compS, R.s));
-    HIP_TRY(launch_chunk_balls(X, p.n, p.d, p.ld, w.perm, CHUNK, w.balls, R.s));
-    HIP_TRY(launch_chunk_balls(X, p.n, p.d, p.ld, w.perm, CHUNK * SUPER, w.sballs, R.s));
+    // balls from the sorted FP32 copy (the same values, contiguous rows)
+    HIP_TRY(launch_chunk_balls(w.xs, p.n, p.d, DMAX, nullptr, CHUNK, w.balls, R.s));
+    HIP_TRY(launch_chunk_balls(w.xs, p.n, p.d, DMAX, nullptr, CHUNK * SUPER, w.sballs, R.s));
     return NNM_OK;
 }
 
@@ -468,7 +470,8 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     a.n_rows = (int32_t)nb;
     a.np = (int32_t)p.n;
     a.d = p.d;
-    a.k = p.k;
+    const int kk = R.kk > 0 ? R.kk : p.k;
+    a.k = kk;
     a.S = p.S;
     a.col_splits = pick_splits(R, nb);
     if (p.ninst > 1) {
@@ -520,7 +523,8 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     r.ld = p.ld;
     r.d = p.d;
     r.n_rows = (int32_t)nb;
-    r.k = p.k;
+    r.k = kk;
+    r.kstride = p.k;
     r.S = p.S;
     r.rows = rows;
     r.row0 = row0;
@@ -544,7 +548,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     r.level = final_pass ? 2 : 1;
     // the tree only needs exact prefixes, so an overflowed row is re-scanned
     // below its 4th key; knn_build needs all k
-    r.kb = p.mst ? std::min(p.k, 4) : p.k;
+    r.kb = p.mst ? std::min(kk, 4) : kk;
     r.u0b = w.u0b;
     r.oflag = w.oflag;
     r.survivors = w.ctr->survivors;
@@ -808,7 +812,11 @@ nnm_status mst_rounds(Run& R, const float* X)
             if (nrep > 0 && nrep < rcount) {
                 HIP_TRY(hipMemcpyAsync(w.rlist, w.olist, sizeof(int32_t) * (size_t)nrep,
                                        hipMemcpyDeviceToDevice, R.s));
+                // a representative only has to bound its component's
+                // smallest outgoing key: its nearest outside point will do
+                R.kk = 1;
                 st = scan_rows(R, X, w.rlist, nrep, false);
+                R.kk = 0;
                 if (st != NNM_OK) return st;
                 if (rep && round < 32) rep->rows_per_round[round] += nrep;
                 Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);

@@ -212,7 +212,8 @@ struct RescoreArgs {
     int64_t ld;
     int32_t d;
     int32_t n_rows;
-    int32_t k;
+    int32_t k;                // neighbours sought (<= kstride)
+    int32_t kstride;          // row stride of the neighbour cache
     int32_t S;
     const int32_t* rows;      // row list (sorted positions), NULL = row0 + slot
     int32_t row0;

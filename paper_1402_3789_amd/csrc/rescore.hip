@@ -100,8 +100,8 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
         for (int e = 0; e < E; ++e)
             if (sv[e] == ws && jv[e] == wj) { sv[e] = __builtin_huge_val(); jv[e] = 0x7FFFFFFF; }
         if (!over && lane == 0) {
-            a.cidx[(int64_t)i * a.k + r] = wj;
-            a.cs[(int64_t)i * a.k + r] = ws;
+            a.cidx[(int64_t)i * a.kstride + r] = wj;
+            a.cs[(int64_t)i * a.kstride + r] = ws;
         }
         last = ws;
         ++kept;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
     a.clen[i] = kept;
     a.ccur[i] = 0;
     if (kept == a.k) {
-        a.clb[i] = a.cs[(int64_t)i * a.k + a.k - 1];
+        a.clb[i] = a.cs[(int64_t)i * a.kstride + a.k - 1];
         a.cflag[i] = 0;
     } else if (u0s >= 0.0) {
         a.clb[i] = u0s;
@@ -194,8 +194,8 @@ __global__ __launch_bounds__(256) void k_fallback(RescoreArgs a, const int32_t* 
                 if (sj_less(ws_s[w], ws_j[w], s0, j0)) { s0 = ws_s[w]; j0 = ws_j[w]; t0 = ws_t[w]; }
             winner = (s0 < __builtin_huge_val()) ? t0 : -1;
             if (winner >= 0) {
-                a.cidx[(int64_t)i * k + r] = j0;
-                a.cs[(int64_t)i * k + r] = s0;
+                a.cidx[(int64_t)i * a.kstride + r] = j0;
+                a.cs[(int64_t)i * a.kstride + r] = s0;
             }
         }
         __syncthreads();
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void k_fallback(RescoreArgs a, const int32_t* 
         a.clen[i] = kept;
         a.ccur[i] = 0;
         if (kept == k) {
-            a.clb[i] = a.cs[(int64_t)i * k + k - 1];
+            a.clb[i] = a.cs[(int64_t)i * a.kstride + k - 1];
             a.cflag[i] = 0;
         } else {
             a.clb[i] = __builtin_huge_val();

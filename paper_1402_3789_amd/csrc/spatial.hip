@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_chunk_balls(const float* __restrict__ X
     double sum[DMAX];
     for (int f = 0; f < DMAX; ++f) sum[f] = 0.0;
     for (int64_t p = c0 + threadIdx.x; p < c1; p += blockDim.x) {
-        const float* x = X + (int64_t)perm[p] * ld;
+        const float* x = X + (int64_t)(perm ? perm[p] : p) * ld;
         for (int f = 0; f < d; ++f) sum[f] += (double)x[f];
     }
     for (int f = 0; f < d; ++f) {
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_chunk_balls(const float* __restrict__ X
     __syncthreads();
     double r2 = 0.0;
     for (int64_t p = c0 + threadIdx.x; p < c1; p += blockDim.x) {
-        const float* x = X + (int64_t)perm[p] * ld;
+        const float* x = X + (int64_t)(perm ? perm[p] : p) * ld;
         double s = 0.0;
         for (int f = 0; f < d; ++f) {
             const double df = (double)x[f] - (double)cen[f];
