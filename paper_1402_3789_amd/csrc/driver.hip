@@ -441,7 +441,7 @@ int pick_splits(const Run& R, int64_t rows)
     if (R.o.col_splits > 0) return R.o.col_splits;
     const int64_t bm = 256;
     const int64_t tiles = (rows + bm - 1) / bm;
-    int64_t want = (2048 + tiles - 1) / tiles;
+    int64_t want = (4096 + tiles - 1) / tiles;
     int64_t cap = R.p.n / 65536;
     if (want > cap) want = cap;
     if (want < 1) want = 1;
