@@ -104,8 +104,12 @@ __device__ inline void tile_ball(TileShared& sh, const float (&x)[DM], bool vali
 // Lower bound on the squared distance of any pair across the tile ball and
 // the ball `ball` (BALL_STRIDE floats, 16-byte aligned), rounded down.  Both
 // centres are zero beyond the data's features, so all DMAX features are
-// summed: the loads carry no dependence on d and issue together.
-__device__ inline double ball_lb2(const TileShared& sh, const float* ball)
+// summed: the loads carry no dependence on d and issue together.  FP32: the
+// computed sum of squares is within (DMAX + 2) 2^-24 of the exact one and the
+// root within half that plus one rounding, which the factor 1 - 2^-18 on the
+// root covers; the two subtractions of the radii (rounded up) round by at
+// most 2^-24 of the root each, and the square by 2^-24, covered by 1 - 2^-20.
+__device__ inline float ball_lb2(const TileShared& sh, const float* ball)
 {
     const float4* b4 = reinterpret_cast<const float4*>(ball);
     const float4* c4 = reinterpret_cast<const float4*>(sh.cen);
@@ -113,18 +117,20 @@ __device__ inline double ball_lb2(const TileShared& sh, const float* ball)
 #pragma unroll
     for (int q = 0; q < DMAX / 4; ++q) bv[q] = b4[q];
     const float rad = ball[DMAX];
-    double s = 0.0;
+    float s = 0.f;
 #pragma unroll
     for (int q = 0; q < DMAX / 4; ++q) {
         const float4 c = c4[q];
-        const double d0 = (double)c.x - (double)bv[q].x, d1 = (double)c.y - (double)bv[q].y;
-        const double d2 = (double)c.z - (double)bv[q].z, d3 = (double)c.w - (double)bv[q].w;
-        s += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+        const float d0 = c.x - bv[q].x, d1 = c.y - bv[q].y;
+        const float d2 = c.z - bv[q].z, d3 = c.w - bv[q].w;
+        s = __builtin_fmaf(d0, d0, s);
+        s = __builtin_fmaf(d1, d1, s);
+        s = __builtin_fmaf(d2, d2, s);
+        s = __builtin_fmaf(d3, d3, s);
     }
-    const double dist = __builtin_sqrt(s) * (1.0 - 0x1p-40);
-    const double lb = dist - (double)sh.rball - (double)rad;
-    if (!(lb > 0.0)) return 0.0;
-    return lb * lb * (1.0 - 0x1p-40);
+    const float lb = __builtin_sqrtf(s) * (1.0f - 0x1p-18f) - sh.rball - rad;
+    if (!(lb > 0.f)) return 0.f;
+    return lb * lb * (1.0f - 0x1p-20f);
 }
 
 // Lower bound, rounded down, on the squared distance between the point x
@@ -154,6 +160,41 @@ __device__ __forceinline__ float point_ball_lb2(const float4 (&x)[NQ], const flo
     const float lb = __builtin_sqrtf(s) * (1.0f - 0x1p-18f) - rad;
     if (!(lb > 0.f)) return 0.f;
     return lb * lb * (1.0f - 0x1p-20f);
+}
+
+// Upper bound on sqrt(U) for the per-row ball test below (U >= 0 or +inf):
+// the correctly rounded root times 1 + 2^-20, rounded, stays above it.
+__device__ __forceinline__ float reach_of(float U)
+{
+    return __builtin_sqrtf(U) * (1.0f + 0x1p-20f);
+}
+
+// Whether the point x (as for point_ball_lb2) may hold a pair with the ball
+// `ball` whose key is at most U, given reach >= sqrt(U): such a pair needs
+// |x - centre| <= radius + sqrt(U).  No root per test: the computed sum of
+// squares s is within (4 NQ + 2) 2^-24 of the exact one (NQ <= 8), and the
+// sum radius + reach and its square round by 2^-24 each, so comparing s with
+// the square times 1 + 2^-16 never drops a ball that holds such a pair.
+template <int NQ>
+__device__ __forceinline__ bool point_ball_reach(const float4 (&x)[NQ], const float* ball, float reach)
+{
+    const float4* b4 = reinterpret_cast<const float4*>(ball);
+    float4 bv[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) bv[q] = b4[q];
+    const float rad = ball[DMAX];
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const float d0 = x[q].x - bv[q].x, d1 = x[q].y - bv[q].y;
+        const float d2 = x[q].z - bv[q].z, d3 = x[q].w - bv[q].w;
+        s = __builtin_fmaf(d0, d0, s);
+        s = __builtin_fmaf(d1, d1, s);
+        s = __builtin_fmaf(d2, d2, s);
+        s = __builtin_fmaf(d3, d3, s);
+    }
+    const float r = rad + reach;
+    return s <= r * r * (1.0f + 0x1p-16f);
 }
 
 // Workgroup-wide max of one float per thread (all 256 threads call it).
@@ -217,7 +258,7 @@ __device__ inline void sweep_chunks(TileShared& sh, const CandArgs& a, int lo_r,
                 umax = fmaxf(fmaxf(sh.wmax[0], sh.wmax[1]), fmaxf(sh.wmax[2], sh.wmax[3]));
                 stale = false;
             }
-            if (ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE) > (double)umax) continue;
+            if (ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE) > umax) continue;
         }
         const int c_lo = sc * SUPER > ch_lo ? sc * SUPER : ch_lo;
         const int c_hi = sc * SUPER + SUPER < ch_hi ? sc * SUPER + SUPER : ch_hi;
@@ -234,7 +275,7 @@ __device__ inline void sweep_chunks(TileShared& sh, const CandArgs& a, int lo_r,
                     umax = fmaxf(fmaxf(sh.wmax[0], sh.wmax[1]), fmaxf(sh.wmax[2], sh.wmax[3]));
                     stale = false;
                 }
-                if (ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE) > (double)umax) continue;
+                if (ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE) > umax) continue;
             }
             process(ci, lo_c, hi_c);
             stale = true;
@@ -303,7 +344,7 @@ struct ChunkIter {
                             my_hi = a.compS[c1];
                             pass = !(lo_r == hi_r && my_lo == my_hi && lo_r == my_lo);
                             if (pass && a.prune)
-                                pass = ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE) <= (double)umax;
+                                pass = ball_lb2(sh, a.balls + (int64_t)ci * BALL_STRIDE) <= umax;
                         }
                         cmask = __ballot(pass);
                     }
@@ -334,7 +375,7 @@ struct ChunkIter {
                     const int64_t s1 = (a.np - s0) < SUPER * CHUNK ? a.np - 1 : s0 + SUPER * CHUNK - 1;
                     pass = !(lo_r == hi_r && a.compS[s0] == lo_r && a.compS[s1] == lo_r);
                     if (pass && a.prune)
-                        pass = ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE) <= (double)umax;
+                        pass = ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE) <= umax;
                 }
                 smask = __ballot(pass);
             }

@@ -275,6 +275,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     float4 xq[NQR];                                        // kept for the per-row ball tests
 #pragma unroll
     for (int q = 0; q < NQR; ++q) xq[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+    float reach = __builtin_huge_valf(), reachU = __builtin_huge_valf();   // sqrt bound of U
     float* my_tk = topk + tid * KP;
     for (int e = 0; e < KP; ++e) my_tk[e] = __builtin_huge_valf();
     float U = 0.f;
@@ -393,8 +394,13 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     float4 pfx[LOCAL ? NQR : 1];
     int pf_cc = -1;
     float pf_ball = 0.f;
+    // the bound the other column splits have found for this row, read with
+    // each chunk's loads and used behind the next barrier (any older value is
+    // still a valid bound)
+    float pf_gU = __builtin_huge_valf();
     auto fetch = [&](int ci) {
         const int64_t c0 = (int64_t)ci * BN;
+        if (SHARE && my_valid) pf_gU = __uint_as_float(a.gU[my_slot]);
         if (tid < BALL_STRIDE) pf_ball = a.balls[(int64_t)ci * BALL_STRIDE + tid];
         const bool in = c0 + tid < a.np;
         if constexpr (LOCAL) {
@@ -449,14 +455,19 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
             }
         } else if constexpr (Tr::BYTES == 64) {
             uint4* cb4 = reinterpret_cast<uint4*>(&colbuf[b][0]);
+            if (__ballot(!col_ok) == 0ull) {               // the usual case: copies only
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint4 v = pf[q];
-                if (!col_ok) {
-                    v = make_uint4(0, 0, 0, 0);
-                    if (q == 3) v.z = LpFmt<OP>::inf_bits << 16;   // K slot 29: t = +inf
+                for (int q = 0; q < 4; ++q) cb4[((tid >> 4) * 4 + q) * 16 + (tid & 15)] = pf[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint4 v = pf[q];
+                    if (!col_ok) {
+                        v = make_uint4(0, 0, 0, 0);
+                        if (q == 3) v.z = LpFmt<OP>::inf_bits << 16;   // K slot 29: t = +inf
+                    }
+                    cb4[((tid >> 4) * 4 + q) * 16 + (tid & 15)] = v;
                 }
-                cb4[((tid >> 4) * 4 + q) * 16 + (tid & 15)] = v;
             }
         } else {
             // FP8 has no infinity: masked columns are zero and the slow path
@@ -479,8 +490,14 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         // or whose ball lies farther than its bound; a wave whose rows all
         // skip does no work on the chunk
         bool need = my_valid && !(pure && lo_c == my_comp);
-        if (a.prune && need)
-            need = point_ball_lb2(xq, &ballbuf[b][0]) <= rs[tid][0].y;
+        if (a.prune && need) {
+            const float Ucur = rs[tid][0].y;
+            if (Ucur != reachU) {                          // the root only when U moved
+                reachU = Ucur;
+                reach = reach_of(Ucur);
+            }
+            need = point_ball_reach(xq, &ballbuf[b][0], reach);
+        }
         if (!__ballot(need)) return;
         // per-tile frame: this chunk's slack and threshold for the row (the
         // wave's rows are read back by other lanes of the same wave only).
@@ -682,11 +699,11 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         stash(cur, buf);
         __syncthreads();        // chunk cur in LDS; every wave is done with buf ^ 1's last use
         umax = fmaxf(fmaxf(wmx[buf][0], wmx[buf][1]), fmaxf(wmx[buf][2], wmx[buf][3]));
-        // bounds found by the other column splits of the row (read before the
-        // next chunk's loads are issued: process() must not wait on those)
+        // bounds found by the other column splits of the row (loaded with the
+        // chunk now in LDS, so nothing waits here)
         if (SHARE) {
             if (my_valid) {
-                const float g = __uint_as_float(a.gU[my_slot]);
+                const float g = pf_gU;
                 if (g < rs[tid][0].y) {
                     rs[tid][0].y = g;
                     if (!LOCAL)
