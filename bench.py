@@ -155,6 +155,7 @@ def main():
             "kernel": f"k_cand_mfma<{args.precision}>", "launches_per_step": launches / args.steps,
             "avg_launch_ms": cand_ms / max(launches, 1),
             "pairs_evaluated_per_step": evaluated / args.steps,
+            "executed_pairs_per_s": evaluated / (cand_ms * 1e-3) if cand_ms > 0 else 0.0,
             "flops_per_pair": 2 * d + 1}
 
     # the plain FP32 path (and other precisions) on the same data
@@ -202,7 +203,7 @@ def main():
         "other_paths": {k2: v2 for k2, v2 in others.items() if k2 != "fp32"},
         "report": {k2: last[k2] for k2 in ("rounds", "rows_scanned", "pairs_evaluated",
                                             "survivors", "overflow_rows", "max_abs_err",
-                                            "max_rel_err", "ms_candidates", "ms_rescore",
+                                            "max_rel_err", "max_bound", "ms_candidates", "ms_rescore",
                                             "ms_merge", "ms_sort", "rows_per_round",
                                             "comps_per_round")},
     }

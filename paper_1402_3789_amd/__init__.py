@@ -156,11 +156,12 @@ def knn_build(X, k=16, precision="auto", survivor_cap=0, force_fallback=False,
     return idx, s, ln
 
 
-def mst_build_batched(Xs, precision="auto", knn_k=8, stream=None, workspace=None):
+def mst_build_batched(Xs, precision="auto", knn_k=8, survivor_cap=0, force_fallback=False,
+                      stream=None, workspace=None):
     """Independent trees of many instances in one call; list of Tree."""
     torch = _torch()
     L = N.lib()
-    o = options(precision, knn_k)
+    o = options(precision, knn_k, survivor_cap, False, force_fallback)
     inst = (N.Instance * len(Xs))()
     outs = []
     for b, X in enumerate(Xs):

@@ -538,6 +538,8 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     r.sigma2 = R.bc.sigma2;
     r.force_fallback = R.o.force_fallback;
     r.np = p.n;
+    r.inst_off = w.inst_off;
+    r.ninst = (int32_t)p.ninst;
     r.cidx = w.cidx;
     r.cs = w.cs;
     r.clen = w.clen;

@@ -227,6 +227,8 @@ struct RescoreArgs {
     float sigma2;
     int32_t force_fallback;
     int64_t np;
+    const int32_t* inst_off;  // [ninst + 1] instance offsets in point order (ninst > 1)
+    int32_t ninst;            // instances; the exact scan stays inside the row's own
     // outputs, indexed by point id
     int32_t* cidx;            // [n][k]
     double* cs;               // [n][k]

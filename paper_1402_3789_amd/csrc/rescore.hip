@@ -140,8 +140,8 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
     atomicAdd(&a.survivors[(slot & (NSPREAD - 1)) * SPREAD_STRIDE], (unsigned long long)nsurv);
 }
 
-// Exact top-k of one row over every point outside its component, by a full
-// FP64 scan (one workgroup per overflowed row).
+// Exact top-k of one row over every point of its instance outside its
+// component, by a full FP64 scan (one workgroup per overflowed row).
 __global__ __launch_bounds__(256) void k_fallback(RescoreArgs a, const int32_t* overflow_list,
                                                   int n_over)
 {
@@ -160,7 +160,19 @@ __global__ __launch_bounds__(256) void k_fallback(RescoreArgs a, const int32_t* 
     int lj[KMAX];
     for (int e = 0; e < KMAX; ++e) { ls[e] = __builtin_huge_val(); lj[e] = 0x7FFFFFFF; }
     const int k = a.k;
-    for (int64_t j = tid; j < a.np; j += 256) {
+    // the row's instance: the last b with inst_off[b] <= i
+    int64_t jlo = 0, jhi = a.np;
+    if (a.ninst > 1) {
+        int lo = 0, hi = a.ninst;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.inst_off[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        jlo = a.inst_off[lo];
+        jhi = a.inst_off[lo + 1];
+    }
+    for (int64_t j = jlo + tid; j < jhi; j += 256) {
         if (j == i || a.comp[j] == ci) continue;
         const double s = sqdist_fp64(xi, a.X + j * a.ld, a.d);
         if (!sj_less(s, (int)j, ls[k - 1], lj[k - 1])) continue;

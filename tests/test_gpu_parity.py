@@ -222,3 +222,18 @@ def test_batched_matches_single(nnm):
             ou, ov, os_, ow = oracle.prim_mst(X)
             assert np.array_equal(u, ou) and np.array_equal(v, ov) and np.array_equal(s, os_)
             assert np.array_equal(w, ow)
+
+
+@pytest.mark.parametrize("knob", ["force_fallback", "tiny_cap"])
+def test_batched_exact_scan_stays_in_instance(nnm, knob):
+    # Rows that reach the exact full scan (forced, or after repeated survivor
+    # overflows with the smallest cap) must only pair inside their instance.
+    Xs = W.batch256(1, count=6, n_lo=200, n_hi=1500)
+    _say("batched exact scan", knob, [x.shape for x in Xs])
+    kw = {"force_fallback": True} if knob == "force_fallback" else {"survivor_cap": 16}
+    trees = nnm.mst_build_batched([_dev(x) for x in Xs], precision="fp16", **kw)
+    torch.cuda.synchronize()
+    for X, t in zip(Xs, trees):
+        got = t.to_numpy()
+        for g, r in zip(got, oracle.prim_mst(X)):
+            assert np.array_equal(g, r)
