@@ -537,9 +537,12 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         const int nblk = (ncols + 15) >> 4;
         // Slow path for the blocks cb (and cb + 1 if two): every lane first
         // collects its candidates below its rows' thresholds as bits
-        // (b * 16 + rb * 4 + r), then walks only those.  The four lane groups
-        // holding columns of the same rows take turns, so a row's LDS state
-        // is never touched by two lanes at once.
+        // (b * 16 + rb * 4 + r), then walks only those, one per step.  The
+        // four lanes lane & 15 + 16 g hold columns of the same rows: in a
+        // step, a lane whose next candidate is in the same row block as that
+        // of a lane of a lower group waits, so a row's LDS state is never
+        // touched by two lanes at once, and lanes of different rows proceed
+        // together.
         auto slow = [&](int cb, const f32x4_t (&acc0)[RB], const f32x4_t (&acc1)[RB], bool two) {
             wdirty = true;
             uint32_t hm = 0;
@@ -552,11 +555,16 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                 }
             }
             hm &= rvmask;
-            for (int g = 0; g < 4; ++g) {
-                if (grp == g) {
-                    while (hm) {
-                        const int e = __builtin_ctz(hm);
-                        hm &= hm - 1;
+            while (__ballot(hm != 0u)) {
+                const int e = hm ? (int)__builtin_ctz(hm) : 0;
+                const int rbs = hm ? ((e >> 2) & 3) : -1;     // row block of the next candidate
+                const int o1 = __shfl_xor(rbs, 16), o2 = __shfl_xor(rbs, 32), o3 = __shfl_xor(rbs, 48);
+                const int g = grp;
+                const bool wait = ((g ^ 1) < g && o1 == rbs) || ((g ^ 2) < g && o2 == rbs) ||
+                                  ((g ^ 3) < g && o3 == rbs);
+                if (rbs >= 0 && !wait) {
+                    hm &= hm - 1;
+                    do {
                         const float v = pick32(acc0, acc1, e);
                         const int rb = (e >> 2) & 3, r = e & 3;
                         const int rl = wave * RB * 16 + rb * 16 + (lane & 15);
@@ -622,8 +630,9 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                                 }
                             }
                         }
-                    }
+                    } while (false);
                 }
+                // this step's row-state writes before the next step's reads
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
