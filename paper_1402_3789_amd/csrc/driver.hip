@@ -419,8 +419,8 @@ nnm_status sort_points(Run& R, const float* X)
         HIP_TRY(launch_gather_points(p.n, p.opkind, w.perm, w.opR, w.opC, w.pc, X, p.d, p.ld, w.comp,
                                      w.opRs, w.opCs, w.pcs, w.xs, w.compS, R.s));
     // balls from the sorted FP32 copy (the same values, contiguous rows)
-    HIP_TRY(launch_chunk_balls(w.xs, p.n, p.d, DMAX, nullptr, CHUNK, w.balls, R.s));
-    HIP_TRY(launch_chunk_balls(w.xs, p.n, p.d, DMAX, nullptr, CHUNK * SUPER, w.sballs, R.s));
+    HIP_TRY(launch_chunk_balls(w.xs, p.n, CHUNK, w.balls, R.s));
+    HIP_TRY(launch_chunk_balls(w.xs, p.n, CHUNK * SUPER, w.sballs, R.s));
     return NNM_OK;
 }
 

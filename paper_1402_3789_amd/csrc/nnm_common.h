@@ -320,8 +320,9 @@ hipError_t launch_component_order(const int32_t* comp, const int32_t* perm0, con
                                   int64_t n, int32_t* ckey, SortRec* recA, SortRec* recB,
                                   int32_t* perm, int32_t* seg, int32_t* flag, int32_t* excl,
                                   void* radix_temp, void* scan_temp, hipStream_t s);
-hipError_t launch_chunk_balls(const float* X, int64_t n, int d, int64_t ld, const int32_t* perm,
-                              int bn, float* balls, hipStream_t s);
+// balls of the chunks of bn rows of the sorted FP32 copy xs ([n][DMAX], zero
+// beyond the data's features)
+hipError_t launch_chunk_balls(const float* xs, int64_t n, int bn, float* balls, hipStream_t s);
 
 // Many instances in one point set (spatial.hip).
 struct InstDev {

@@ -91,46 +91,61 @@ __global__ __launch_bounds__(256) void k_segment_ids(const int32_t* __restrict__
     if (p < n) seg[p] = excl[p] + flag[p] - 1;
 }
 
-// One block per chunk of `bn` sorted positions: centre = FP64 mean rounded
-// to FP32, radius = FP64 max distance to that centre, rounded up.
-__global__ __launch_bounds__(256) void k_chunk_balls(const float* __restrict__ X, int64_t n, int d,
-                                                     int64_t ld, const int32_t* __restrict__ perm,
-                                                     int bn, float* __restrict__ balls)
+// One block per chunk of `bn` consecutive rows of the sorted FP32 copy
+// (DMAX floats a row, zero beyond the data's features): centre = FP64 mean
+// rounded to FP32, radius = FP64 max distance to that centre, rounded up.
+// Eight lanes per row, one float4 each, so every read is a whole row.
+__global__ __launch_bounds__(256) void k_chunk_balls(const float* __restrict__ xs, int64_t n, int bn,
+                                                     float* __restrict__ balls)
 {
     __shared__ double acc[4][DMAX];
-    __shared__ float cen[DMAX];
+    __shared__ alignas(16) float cen[DMAX];
     __shared__ double rmax[4];
     const int64_t c0 = (int64_t)blockIdx.x * bn;
-    int64_t c1 = c0 + bn;
-    if (c1 > n) c1 = n;
+    const int64_t c1 = c0 + bn < n ? c0 + bn : n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double sum[DMAX];
-    for (int f = 0; f < DMAX; ++f) sum[f] = 0.0;
-    for (int64_t p = c0 + threadIdx.x; p < c1; p += blockDim.x) {
-        const float* x = X + (int64_t)(perm ? perm[p] : p) * ld;
-        for (int f = 0; f < d; ++f) sum[f] += (double)x[f];
+    const int q = threadIdx.x & 7;               // float4 of the row
+    const int r = threadIdx.x >> 3;              // row of a pass of 32
+    const float4* x4 = reinterpret_cast<const float4*>(xs);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int64_t p = c0 + r; p < c1; p += 32) {
+        const float4 v = x4[p * (DMAX / 4) + q];
+        s0 += (double)v.x;
+        s1 += (double)v.y;
+        s2 += (double)v.z;
+        s3 += (double)v.w;
     }
-    for (int f = 0; f < d; ++f) {
-        double v = sum[f];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) acc[wave][f] = v;
+    // over the eight rows of the wave that share q
+    for (int off = 8; off < 64; off <<= 1) {
+        s0 += __shfl_xor(s0, off);
+        s1 += __shfl_xor(s1, off);
+        s2 += __shfl_xor(s2, off);
+        s3 += __shfl_xor(s3, off);
+    }
+    if (lane < 8) {
+        acc[wave][4 * q + 0] = s0;
+        acc[wave][4 * q + 1] = s1;
+        acc[wave][4 * q + 2] = s2;
+        acc[wave][4 * q + 3] = s3;
     }
     __syncthreads();
-    if (threadIdx.x < d) {
-        const double m = (acc[0][threadIdx.x] + acc[1][threadIdx.x] + acc[2][threadIdx.x] +
-                          acc[3][threadIdx.x]) / (double)(c1 - c0);
-        cen[threadIdx.x] = (float)m;
+    if (threadIdx.x < DMAX) {
+        const int f = threadIdx.x;
+        cen[f] = (float)((acc[0][f] + acc[1][f] + acc[2][f] + acc[3][f]) / (double)(c1 - c0));
     }
     __syncthreads();
+    const float4 c = reinterpret_cast<const float4*>(cen)[q];
     double r2 = 0.0;
-    for (int64_t p = c0 + threadIdx.x; p < c1; p += blockDim.x) {
-        const float* x = X + (int64_t)(perm ? perm[p] : p) * ld;
-        double s = 0.0;
-        for (int f = 0; f < d; ++f) {
-            const double df = (double)x[f] - (double)cen[f];
-            s += df * df;
-        }
-        r2 = s > r2 ? s : r2;
+    for (int64_t p = c0 + r; p < c1; p += 32) {
+        const float4 v = x4[p * (DMAX / 4) + q];
+        const double d0 = (double)v.x - (double)c.x, d1 = (double)v.y - (double)c.y;
+        const double d2 = (double)v.z - (double)c.z, d3 = (double)v.w - (double)c.w;
+        double part = d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+        // the row's eight lanes run the same trips: its full squared distance
+        part += __shfl_xor(part, 1);
+        part += __shfl_xor(part, 2);
+        part += __shfl_xor(part, 4);
+        r2 = part > r2 ? part : r2;
     }
     for (int off = 32; off > 0; off >>= 1) {
         const double o = __shfl_xor(r2, off);
@@ -138,15 +153,14 @@ __global__ __launch_bounds__(256) void k_chunk_balls(const float* __restrict__ X
     }
     if (lane == 0) rmax[wave] = r2;
     __syncthreads();
+    float* out = balls + (int64_t)blockIdx.x * BALL_STRIDE;
     if (threadIdx.x == 0) {
         double m = rmax[0];
         for (int w = 1; w < 4; ++w) m = rmax[w] > m ? rmax[w] : m;
-        balls[(int64_t)blockIdx.x * BALL_STRIDE + DMAX] = d2f_up(__builtin_sqrt(m) * (1.0 + 0x1p-40));
+        out[DMAX] = d2f_up(__builtin_sqrt(m) * (1.0 + 0x1p-40));
     }
-    if (threadIdx.x < DMAX)
-        balls[(int64_t)blockIdx.x * BALL_STRIDE + threadIdx.x] = threadIdx.x < d ? cen[threadIdx.x] : 0.f;
-    else if (threadIdx.x > DMAX && threadIdx.x < BALL_STRIDE)
-        balls[(int64_t)blockIdx.x * BALL_STRIDE + threadIdx.x] = 0.f;
+    if (threadIdx.x < DMAX) out[threadIdx.x] = cen[threadIdx.x];
+    else if (threadIdx.x > DMAX && threadIdx.x < BALL_STRIDE) out[threadIdx.x] = 0.f;
 }
 
 constexpr int FANOUT = 32;
@@ -404,11 +418,12 @@ hipError_t launch_component_order(const int32_t* comp, const int32_t* perm0, con
     return hipGetLastError();
 }
 
-hipError_t launch_chunk_balls(const float* X, int64_t n, int d, int64_t ld, const int32_t* perm,
-                              int bn, float* balls, hipStream_t s)
+hipError_t launch_chunk_balls(const float* xs, int64_t n, int bn, float* balls, hipStream_t s)
 {
+    static_assert(DMAX == 32, "eight float4 per padded row");
     const int64_t nc = (n + bn - 1) / bn;
-    k_chunk_balls<<<(unsigned)nc, 256, 0, s>>>(X, n, d, ld, perm, bn, balls);
+    if (nc <= 0) return hipSuccess;
+    k_chunk_balls<<<(unsigned)nc, 256, 0, s>>>(xs, n, bn, balls);
     return hipGetLastError();
 }
 

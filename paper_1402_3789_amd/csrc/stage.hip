@@ -273,24 +273,21 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, const int32_t* __rest
 
 __global__ __launch_bounds__(256) void k_gather_fp32(int64_t n, const int32_t* __restrict__ perm,
                                                      const float* __restrict__ X, int d,
-                                                     int64_t ld,
-                                                     const int32_t* __restrict__ comp,
-                                                     float* __restrict__ xs,
-                                                     int32_t* __restrict__ compS)
+                                                     int64_t ld, float* __restrict__ xs)
 {
-    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    // eight lanes per point, one float4 of the padded row each: the reads of
+    // a row and the 128-byte write are contiguous across its lanes
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t p = t >> 3;
+    const int q = (int)(t & 7);
     if (p >= n) return;
-    int64_t i = perm[p];
-    float4* dst = reinterpret_cast<float4*>(xs + p * DMAX);
-#pragma unroll
-    for (int w = 0; w < DMAX / 4; ++w) {
-        float4 v;
-        v.x = (4 * w + 0 < d) ? X[i * ld + 4 * w + 0] : 0.f;
-        v.y = (4 * w + 1 < d) ? X[i * ld + 4 * w + 1] : 0.f;
-        v.z = (4 * w + 2 < d) ? X[i * ld + 4 * w + 2] : 0.f;
-        v.w = (4 * w + 3 < d) ? X[i * ld + 4 * w + 3] : 0.f;
-        dst[w] = v;
-    }
+    const float* src = X + (int64_t)perm[p] * ld + 4 * q;
+    float4 v;
+    v.x = (4 * q + 0 < d) ? src[0] : 0.f;
+    v.y = (4 * q + 1 < d) ? src[1] : 0.f;
+    v.z = (4 * q + 2 < d) ? src[2] : 0.f;
+    v.w = (4 * q + 3 < d) ? src[3] : 0.f;
+    reinterpret_cast<float4*>(xs + p * DMAX)[q] = v;
 }
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
@@ -340,7 +337,8 @@ hipError_t launch_gather_points(int64_t n, int opkind, const int32_t* perm,
 {
     unsigned g = grid_for(n, 256);
     if (opkind == OP_FP32) {
-        k_gather_fp32<<<g, 256, 0, s>>>(n, perm, X, d, ld, comp, xs, compS);
+        static_assert(DMAX == 32, "eight float4 per padded row");
+        k_gather_fp32<<<grid_for(n * 8, 256), 256, 0, s>>>(n, perm, X, d, ld, xs);
     } else if (opkind == OP_FP8) {
         k_gather<32><<<g, 256, 0, s>>>(n, perm, (const uint4*)opR, (const uint4*)opC, pc, comp,
                                        (uint4*)opRs, (uint4*)opCs, pcs, compS);
