@@ -261,6 +261,7 @@ struct Run {
     int splits_opt = 0;
     int round = 0;          // current merge round (per-round report entries)
     int kk = 0;             // neighbours sought by the current scan (0 = the cache depth)
+    bool fp32_scan = false; // the current scan uses the FP32 kernel whatever the precision
 };
 
 int ceil_log2(int64_t v)
@@ -458,6 +459,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     Plan& p = R.p;
     WS& w = R.w;
     HIP_TRY(hipMemsetAsync(w.surv_cnt, 0, sizeof(int32_t) * (size_t)nb, R.s));
+    const bool use32 = p.opkind == OP_FP32 || R.fp32_scan;
     CandArgs a{};
     a.opR = w.opRs;
     a.opC = w.opCs;
@@ -497,7 +499,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     a.balls = w.balls;
     a.sballs = w.sballs;
     a.prune = R.o.disable_prune ? 0 : 1;
-    a.local = p.local ? 1 : 0;
+    a.local = (p.local && !use32) ? 1 : 0;
     a.share = a.col_splits > 1 ? 1 : 0;
     a.gT = w.gT;
     a.gU = w.gU;
@@ -509,7 +511,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
         double ms = 0.0;
         {
             Timer t(R.rep != nullptr, R.s, &ms);
-            if (p.opkind == OP_FP32) HIP_TRY(launch_cand_fp32(a, R.s));
+            if (use32) HIP_TRY(launch_cand_fp32(a, R.s));
             else HIP_TRY(launch_cand_mfma(p.opkind, a, R.s));
         }
         if (R.rep) {
@@ -534,8 +536,9 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     r.surv_j = w.surv_j;
     r.surv_t = w.surv_t;
     r.u0 = u0;
-    r.inv_sigma2 = 1.0 / (double)R.bc.sigma2;
-    r.sigma2 = R.bc.sigma2;
+    // FP32 candidates are in data units
+    r.inv_sigma2 = use32 ? 1.0 : 1.0 / (double)R.bc.sigma2;
+    r.sigma2 = use32 ? 1.f : R.bc.sigma2;
     r.force_fallback = R.o.force_fallback;
     r.np = p.n;
     r.inst_off = w.inst_off;
@@ -608,15 +611,22 @@ nnm_status scan_rows(Run& R, const float* X, const int32_t* rows, int64_t count,
             HIP_TRY(launch_fill_i32(w.oflag, 0, p.n, R.s));
             if (R.rep) R.rep->rescanned_bounded += on;
             const bool final_pass = pass >= OVER_PASSES;
+            // rows whose matrix-core survivors overflowed are rescanned with
+            // the FP32 kernel: its margin is a few units in the last place,
+            // where the low-precision margin may hold thousands of columns
+            // (points clustered far tighter than the data's extent).  Exact
+            // integer data has no margin; there only ties overflow.
+            R.fp32_scan = p.opkind != OP_FP32 && !p.exact;
             over = 0;
             for (int64_t c0 = 0; c0 < on; c0 += p.rmax) {
                 const int64_t nc = std::min<int64_t>(p.rmax, on - c0);
                 int32_t o2 = 0;
                 st = scan_batch(R, X, w.olist + c0, 0, nc, w.u0b, final_pass, &o2);
-                if (st != NNM_OK) return st;
+                if (st != NNM_OK) { R.fp32_scan = false; return st; }
                 if (!final_pass) over += o2;
             }
         }
+        R.fp32_scan = false;
     }
     return NNM_OK;
 }
