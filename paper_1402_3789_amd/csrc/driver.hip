@@ -611,14 +611,16 @@ nnm_status scan_rows(Run& R, const float* X, const int32_t* rows, int64_t count,
             HIP_TRY(launch_fill_i32(w.oflag, 0, p.n, R.s));
             if (R.rep) R.rep->rescanned_bounded += on;
             const bool final_pass = pass >= OVER_PASSES;
-            // rows whose matrix-core survivors overflow again are rescanned
-            // with the FP32 kernel: its margin is a few units in the last
-            // place, where the low-precision margin may hold thousands of
-            // columns (points clustered far tighter than the data's extent).
-            // The first rescan stays on the matrix cores, which settle
-            // milder overflows faster.  Exact integer data has no margin;
-            // there only ties overflow.
-            R.fp32_scan = pass >= 2 && p.opkind != OP_FP32 && !p.exact;
+            // rows whose matrix-core survivors keep overflowing are
+            // rescanned with the FP32 kernel: its margin is a few units in
+            // the last place, where the low-precision margin may hold
+            // thousands of columns (points clustered far tighter than the
+            // data's extent).  The first rescan stays on the matrix cores,
+            // which settle milder overflows faster, and so does a second one
+            // of a few rows (too few tiles to hide the slower kernel's
+            // sweep).  Exact integer data has no margin; there only ties
+            // overflow.
+            R.fp32_scan = p.opkind != OP_FP32 && !p.exact && (pass >= 3 || (pass == 2 && on >= 4096));
             over = 0;
             for (int64_t c0 = 0; c0 < on; c0 += p.rmax) {
                 const int64_t nc = std::min<int64_t>(p.rmax, on - c0);
