@@ -61,11 +61,31 @@ __global__ __launch_bounds__(256) void k_cursor(MergeArgs a)
     }
 }
 
+// By sorted position: a component's points are contiguous there, so a wave
+// mostly serves one component and issues one atomic for it.
 __global__ __launch_bounds__(256) void k_compmin1(MergeArgs a)
 {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    if (a.rstat[i] == 1) atomicMin(&a.cbest_s[a.comp[i]], sbits(a.rbest_s[i]));
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool in = p < a.n;
+    int c = -1;
+    unsigned long long key = NONE;
+    if (in) {
+        const int i = a.perm[p];
+        c = a.comp[i];
+        if (a.rstat[i] == 1) key = sbits(a.rbest_s[i]);
+    }
+    const int c0 = __shfl(c, 0);      // lane 0 is in range whenever any lane is
+    if (__ballot(in && c != c0) == 0ull) {
+        unsigned long long m = key;
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(m, off);
+            m = o < m ? o : m;
+        }
+        if ((threadIdx.x & 63) == 0 && m != NONE && m < __atomic_load_n(&a.cbest_s[c0], __ATOMIC_RELAXED))
+            atomicMin(&a.cbest_s[c0], m);
+    } else if (key != NONE && key < __atomic_load_n(&a.cbest_s[c], __ATOMIC_RELAXED)) {
+        atomicMin(&a.cbest_s[c], key);
+    }
 }
 
 // By sorted position, so the rescan list comes out in component order.

@@ -21,10 +21,13 @@ __device__ __forceinline__ uint32_t ord_enc(float f)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// One pass over X: eight lanes per point, lane q covering features
+// 4q..4q+3, so the reads of a row are contiguous across its lanes.
 __global__ __launch_bounds__(256) void k_stage_stats(const float* __restrict__ X,
                                                      int64_t n, int d, int64_t ld,
                                                      StageStats* st)
 {
+    static_assert(DMAX == 32, "eight lanes of four features");
     __shared__ uint32_t smin[DMAX], smax[DMAX];
     __shared__ int sbad, snonint;
     if (threadIdx.x < DMAX) {
@@ -33,28 +36,36 @@ __global__ __launch_bounds__(256) void k_stage_stats(const float* __restrict__ X
     }
     if (threadIdx.x == 0) { sbad = 0; snonint = 0; }
     __syncthreads();
+    const int q = threadIdx.x & 7;
     int bad = 0, nonint = 0;
-    for (int f = 0; f < d; ++f) {
-        uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-             i += (int64_t)gridDim.x * blockDim.x) {
-            float v = X[i * ld + f];
+    uint32_t lo[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    uint32_t hi[4] = {0u, 0u, 0u, 0u};
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 3);
+    for (int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 3) + (threadIdx.x >> 3); i < n; i += stride) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int f = 4 * q + h;
+            if (f >= d) continue;
+            const float v = X[i * ld + f];
             if (!__builtin_isfinite(v)) { bad = 1; continue; }
             if (v != __builtin_rintf(v) || __builtin_fabsf(v) > 16.0f) nonint = 1;
-            uint32_t e = ord_enc(v);
-            lo = lo < e ? lo : e;
-            hi = hi > e ? hi : e;
+            const uint32_t e = ord_enc(v);
+            lo[h] = lo[h] < e ? lo[h] : e;
+            hi[h] = hi[h] > e ? hi[h] : e;
         }
-        // wave reduction then one LDS atomic per wave
-        for (int off = 32; off > 0; off >>= 1) {
-            uint32_t olo = __shfl_xor(lo, off);
-            uint32_t ohi = __shfl_xor(hi, off);
-            lo = lo < olo ? lo : olo;
-            hi = hi > ohi ? hi : ohi;
+    }
+    // over the eight points of the wave that share q, then one LDS atomic
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        for (int off = 8; off < 64; off <<= 1) {
+            const uint32_t olo = __shfl_xor(lo[h], off);
+            const uint32_t ohi = __shfl_xor(hi[h], off);
+            lo[h] = lo[h] < olo ? lo[h] : olo;
+            hi[h] = hi[h] > ohi ? hi[h] : ohi;
         }
-        if ((threadIdx.x & 63) == 0) {
-            atomicMin(&smin[f], lo);
-            atomicMax(&smax[f], hi);
+        if ((threadIdx.x & 63) < 8 && 4 * q + h < d) {
+            atomicMin(&smin[4 * q + h], lo[h]);
+            atomicMax(&smax[4 * q + h], hi[h]);
         }
     }
     if (bad) atomicOr(&sbad, 1);
@@ -297,7 +308,7 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 hipError_t launch_stage_stats(const float* X, int64_t n, int d, int64_t ld,
                               StageStats* st, hipStream_t s)
 {
-    int64_t blocks = (n + 255) / 256;
+    int64_t blocks = (n + 31) / 32;          // 32 points per pass of a block
     if (blocks > 2048) blocks = 2048;
     if (blocks < 1) blocks = 1;
     k_stage_stats<<<(unsigned)blocks, 256, 0, s>>>(X, n, d, ld, st);
