@@ -202,7 +202,9 @@ nnm_status plan_common(int64_t n, int32_t d, int32_t k, const nnm_options* opt, 
     if (S > SMAX) S = SMAX;
     S = pow2_at_least(S);
     p->S = S;
-    int64_t rmax = ((int64_t)1 << 28) / S;
+    // survivor buffers of 2^29 entries (4 GB): 2M rows at S = 256 in one
+    // launch (a split launch pays two tails and narrower column splits)
+    int64_t rmax = ((int64_t)1 << 29) / S;
     if (rmax > n) rmax = n;
     if (rmax < 1) rmax = 1;
     p->rmax = rmax;
@@ -310,7 +312,7 @@ nnm_status stage(Run& R, const float* X)
     p.local = p.opkind == OP_BF16 && !p.exact;
     if (p.local && R.o.survivor_cap <= 0) {
         // BF16's margin is wider: keep 4x the survivors per row (the
-        // survivor buffers hold 2^28 entries whatever the split into rows)
+        // survivor buffers hold 2^29 entries whatever the split into rows)
         const int S4 = p.S * 4 < SMAX ? p.S * 4 : SMAX;
         p.rmax = p.rmax * p.S / S4;
         if (p.rmax < 1) p.rmax = 1;
