@@ -28,7 +28,7 @@ def _torch():
     return torch
 
 
-def options(precision="auto", knn_k=8, survivor_cap=0, disable_prune=False,
+def options(precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
             force_fallback=False, col_splits=0) -> N.Options:
     o = N.Options()
     N.lib().nnm_default_options(ctypes.byref(o))
@@ -112,7 +112,7 @@ class Tree:
         return (iv[:, 0].copy(), iv[:, 1].copy(), h[:, 1].copy(), h[:, 2].copy())
 
 
-def mst_build(X, precision="auto", knn_k=8, survivor_cap=0, disable_prune=False,
+def mst_build(X, precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
               force_fallback=False, col_splits=0, stream=None, workspace=None) -> Tree:
     """Exact key-ordered minimum spanning tree of the rows of X (device)."""
     torch = _torch()
@@ -156,7 +156,7 @@ def knn_build(X, k=16, precision="auto", survivor_cap=0, force_fallback=False,
     return idx, s, ln
 
 
-def mst_build_batched(Xs, precision="auto", knn_k=8, survivor_cap=0, force_fallback=False,
+def mst_build_batched(Xs, precision="auto", knn_k=0, survivor_cap=0, force_fallback=False,
                       stream=None, workspace=None):
     """Independent trees of many instances in one call; list of Tree."""
     torch = _torch()

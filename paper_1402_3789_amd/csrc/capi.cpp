@@ -8,7 +8,7 @@ extern "C" void nnm_default_options(nnm_options* opt)
     if (!opt) return;
     memset(opt, 0, sizeof(*opt));
     opt->precision = NNM_PREC_AUTO;
-    opt->knn_k = 8;
+    opt->knn_k = 0;
 }
 
 extern "C" const char* nnm_strerror(int32_t status)

@@ -51,7 +51,7 @@ struct Plan {
     int64_t ld = 0;
     int opkind = OP_FP32;
     int exact = 0;
-    int k = 8;
+    int k = 6;
     int S = 256;
     int64_t rmax = 0;               // rows per candidate launch
     int op_bytes = 64;
@@ -184,12 +184,15 @@ nnm_status plan_common(int64_t n, int32_t d, int32_t k, const nnm_options* opt, 
     p->n = n;
     p->d = d;
     p->mst = mst;
-    p->k = k > 0 ? k : (o.knn_k > 0 ? o.knn_k : 8);
-    if (p->k < 1 || p->k > KMAX) return NNM_EINVAL;
     // workspace is sized for the widest operand so the precision can be
     // settled after the data have been inspected
     p->opkind = (o.precision == NNM_PREC_FP32) ? OP_FP32 : OP_FP16;
     if (o.precision == NNM_PREC_AUTO && d > DMAX_MFMA) p->opkind = OP_FP32;
+    // cache depth: the matrix-core paths' survivor band grows with k, so
+    // they keep fewer neighbours than the plain FP32 path (measured best:
+    // 6 and 8 on the 2M workload)
+    p->k = k > 0 ? k : (o.knn_k > 0 ? o.knn_k : (p->opkind == OP_FP32 ? 8 : 6));
+    if (p->k < 1 || p->k > KMAX) return NNM_EINVAL;
     if (o.precision != NNM_PREC_FP32 && o.precision != NNM_PREC_AUTO && d > DMAX_MFMA)
         return NNM_EUNSUPPORTED;
     p->op_bytes = 64;

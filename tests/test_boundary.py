@@ -47,7 +47,7 @@ def test_strerror_and_defaults():
     assert N.strerror(-99) == "unknown status"
     o = N.Options()
     N.lib().nnm_default_options(ctypes.byref(o))
-    assert o.precision == N.PREC["auto"] and o.knn_k == 8
+    assert o.precision == N.PREC["auto"] and o.knn_k == 0
 
 
 def _ws(n, d, **kw):
