@@ -188,10 +188,11 @@ nnm_status plan_common(int64_t n, int32_t d, int32_t k, const nnm_options* opt, 
     // settled after the data have been inspected
     p->opkind = (o.precision == NNM_PREC_FP32) ? OP_FP32 : OP_FP16;
     if (o.precision == NNM_PREC_AUTO && d > DMAX_MFMA) p->opkind = OP_FP32;
-    // cache depth: the matrix-core paths' survivor band grows with k, so
-    // they keep fewer neighbours than the plain FP32 path (measured best:
-    // 6 and 8 on the 2M workload)
-    p->k = k > 0 ? k : (o.knn_k > 0 ? o.knn_k : (p->opkind == OP_FP32 ? 8 : 6));
+    // cache depth: the global-frame matrix-core paths' survivor band grows
+    // with k, so they keep fewer neighbours than the FP32 and the per-tile
+    // BF16 paths (measured best on the 2M workload: 6, and 8)
+    const bool deep = p->opkind == OP_FP32 || o.precision == NNM_PREC_BF16;
+    p->k = k > 0 ? k : (o.knn_k > 0 ? o.knn_k : (deep ? 8 : 6));
     if (p->k < 1 || p->k > KMAX) return NNM_EINVAL;
     if (o.precision != NNM_PREC_FP32 && o.precision != NNM_PREC_AUTO && d > DMAX_MFMA)
         return NNM_EUNSUPPORTED;
@@ -442,12 +443,17 @@ nnm_status spatial_order(Run& R, const float* X)
     return NNM_OK;
 }
 
-int pick_splits(const Run& R, int64_t rows)
+// Column splits per row tile: enough workgroups to fill the chip twice
+// over for the bounded scans of the merge rounds; the first round (every
+// row's k nearest, hit-heavy) does better with half as many (measured on the
+// 2M workload).
+int pick_splits(const Run& R, int64_t rows, bool bounded)
 {
     if (R.o.col_splits > 0) return R.o.col_splits;
     const int64_t bm = 256;
     const int64_t tiles = (rows + bm - 1) / bm;
-    int64_t want = (4096 + tiles - 1) / tiles;
+    const int64_t target = bounded ? 8192 : 4096;
+    int64_t want = (target + tiles - 1) / tiles;
     int64_t cap = R.p.n / 65536;
     if (want > cap) want = cap;
     if (want < 1) want = 1;
@@ -480,7 +486,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     const int kk = R.kk > 0 ? R.kk : p.k;
     a.k = kk;
     a.S = p.S;
-    a.col_splits = pick_splits(R, nb);
+    a.col_splits = pick_splits(R, nb, u0 != nullptr && R.round > 0);
     if (p.ninst > 1) {
         // tiles never mix instances; each pairs only with its own instance
         int32_t nt = 0;
@@ -491,7 +497,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
         HIP_TRY(launch_tile_desc(w.tstart, nt, rows, row0, nb, w.inst_off, p.ninst, 256, w.tiles, R.s));
         a.tiles = w.tiles;
         a.n_tiles = nt;
-        a.col_splits = pick_splits(R, (int64_t)nt * 256);
+        a.col_splits = pick_splits(R, (int64_t)nt * 256, u0 != nullptr && R.round > 0);
     }
     a.bc = R.bc;
     a.surv_cnt = w.surv_cnt;
