@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_flag_rescan(MergeArgs a)
 // Flagged rows of components that have no bound yet (every row of such a
 // component is flagged): up to REPS rows evenly spaced along the component's
 // segment of the sorted order (which is spatially ordered) represent it.
-constexpr int REPS = 16;
+constexpr int REPS = 8;
 
 __global__ __launch_bounds__(256) void k_rep_flags(MergeArgs a, const int32_t* seg,
                                                    const int32_t* segstart, int64_t nseg,
