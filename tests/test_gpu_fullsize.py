@@ -1,5 +1,6 @@
 """Full-size parity (N = 2,000,000, D = 25) on properties the oracle can
-check one row at a time, in the launch configuration the benchmark times.
+check one row at a time, in the launch configuration the benchmark times
+(and the exact kNN of sampled rows for knn_build at full size).
 
 A spanning tree is the key-ordered minimum spanning tree iff every tree
 edge is the smallest pair across the cut it defines.  At full size the
@@ -107,9 +108,15 @@ def _check_full(nnm, X, precision, rng):
     return tree
 
 
-def test_aniso500_full_size_fp16(nnm):
-    rng = np.random.default_rng(2024)
+@pytest.fixture(scope="module")
+def aniso():
     X, _ = W.aniso500(0, n=N_FULL)
+    return X
+
+
+def test_aniso500_full_size_fp16(nnm, aniso):
+    rng = np.random.default_rng(2024)
+    X = aniso
     _say("aniso500 full", X.shape)
     tree = _check_full(nnm, X, "fp16", rng)
     labels, k = nnm.cluster_cut(tree, kl1=500)
@@ -122,3 +129,20 @@ def test_int16grid_full_size_fp8(nnm):
     _say("int16grid full", X.shape)
     tree = _check_full(nnm, X, "fp8", rng)
     assert tree.report["integer_mode"] == 1 and tree.report["max_abs_err"] == 0.0
+
+
+@pytest.mark.parametrize("k", [16, 32])
+def test_aniso500_full_size_knn(nnm, aniso, k):
+    # exact k nearest neighbours of every point at full size: sampled rows
+    # against the oracle's exact kNN of those rows
+    X = aniso
+    rng = np.random.default_rng(2026 + k)
+    rows = rng.choice(X.shape[0], size=96, replace=False)
+    _say("aniso500 full knn", k)
+    idx, s, ln = nnm.knn_build(torch.from_numpy(X).to("cuda:0"), k=k, precision="fp16")
+    torch.cuda.synchronize()
+    oi, os_, ol = oracle.knn(X, k, rows=rows)
+    assert np.array_equal(idx.cpu().numpy()[rows], oi)
+    assert np.array_equal(s.cpu().numpy()[rows], os_)
+    assert np.array_equal(ln.cpu().numpy()[rows], ol)
+    _say("knn rows identical", k)
