@@ -733,6 +733,10 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         buf ^= 1;
     }
     if (!SHARE && my_valid) a.surv_cnt[my_slot] = __float_as_int(rs[tid][1].x);
+    // the row's final threshold (one frame for every pair): a survivor above
+    // it has key > U >= the row's k-th key, so rescoring may drop it
+    if (!LOCAL && a.tfin && my_valid)
+        atomicMin(&a.tfin[my_slot], __float_as_uint(fmaxf(rs[tid][0].x, 0.f)));
     const int wrows = sh.rows - wave * 64;
     if (lane == 0 && a.pairs && wrows > 0)
         atomicAdd(&a.pairs[((blockIdx.x * 4 + wave) & (NSPREAD - 1)) * SPREAD_STRIDE],

@@ -81,6 +81,7 @@ struct WS {
     float* balls;
     float* sballs;
     uint32_t* gT; uint32_t* gU;
+    uint32_t* tfin;
     void* spatial_temp;
     double* u0b; int32_t* oflag; int32_t* olist; int32_t* rep_pos; int32_t* rflag2;
     int4* tiles; int32_t* tflag; int32_t* tstart;
@@ -151,6 +152,7 @@ size_t carve(const Plan& p, void* base, WS* w)
     w->sballs = c.take<float>((n + CHUNK * SUPER - 1) / (CHUNK * SUPER) * BALL_STRIDE);
     w->gT = c.take<uint32_t>((size_t)p.rmax);
     w->gU = c.take<uint32_t>((size_t)p.rmax);
+    w->tfin = c.take<uint32_t>((size_t)p.rmax);
     w->spatial_temp = c.take<char>(spatial_temp_bytes((int64_t)n, p.L1, p.L2));
     w->u0b = c.take<double>(n);
     w->oflag = c.take<int32_t>(n);
@@ -513,6 +515,10 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     a.local = (p.local && !use32) ? 1 : 0;
     a.share = a.col_splits > 1 ? 1 : 0;
     a.gT = w.gT;
+    // final thresholds: one frame for every pair (not the per-tile frame)
+    const bool use_tfin = !use32 && !p.local;
+    a.tfin = use_tfin ? w.tfin : nullptr;
+    if (use_tfin) HIP_TRY(launch_fill_i32((int32_t*)w.tfin, 0x7F800000, nb, R.s));
     a.gU = w.gU;
     if (a.share) {
         HIP_TRY(launch_fill_i32((int32_t*)w.gT, 0x7F800000, nb, R.s));
@@ -542,6 +548,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     r.rows = rows;
     r.row0 = row0;
     r.perm = w.perm;
+    r.tfin = a.tfin;
     r.comp = w.comp;
     r.surv_cnt = w.surv_cnt;
     r.surv_j = w.surv_j;

@@ -199,6 +199,8 @@ struct CandArgs {
     // thresholds shared by the column splits of one row (float bits)
     int32_t share;
     uint32_t* gT;             // [n_rows] candidate-domain threshold
+    uint32_t* tfin;           // [n_rows] or NULL: each row's final threshold (FP32
+                              // bits, clamped at 0; min over column splits)
     uint32_t* gU;             // [n_rows] bound on the key of the k-th neighbour
 };
 
@@ -218,6 +220,7 @@ struct RescoreArgs {
     const int32_t* rows;      // row list (sorted positions), NULL = row0 + slot
     int32_t row0;
     const int32_t* perm;      // sorted position -> point
+    const uint32_t* tfin;     // NULL or the candidate pass's final threshold per row
     const int32_t* comp;      // component of each point
     const int32_t* surv_cnt;
     const int32_t* surv_j;

@@ -48,6 +48,10 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
     const int m = over ? a.S : cnt;
     const double u0s = a.u0 ? a.u0[rp] : -1.0;
     const float* xi = a.xs + (int64_t)rp * DMAX;
+    // survivors above the row's final threshold cannot be among its k
+    // nearest (their key exceeds the final bound U); an overflowed row keeps
+    // all of its first S for the bound it passes on
+    const float tf = (a.tfin && !over) ? __uint_as_float(a.tfin[slot]) : __builtin_huge_valf();
     double sv[E];
     int jv[E];
     double emax = 0.0, rmax = 0.0;
@@ -57,11 +61,12 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
         sv[e] = __builtin_huge_val();
         jv[e] = 0x7FFFFFFF;
         const int idx = e * 64 + lane;
-        if (idx < m) {
+        const float tv = idx < m ? a.surv_t[slot * a.S + idx] : 0.f;
+        if (idx < m && !(tv > tf)) {
             const int jp = a.surv_j[slot * a.S + idx];
             const int j = a.perm[jp];
             const double s = sqdist_fp64_rows(xi, a.xs + (int64_t)jp * DMAX, a.d);
-            const double t = (double)a.surv_t[slot * a.S + idx] * a.inv_sigma2;
+            const double t = (double)tv * a.inv_sigma2;
             const double err = __builtin_fabs(t - s);
             emax = err > emax ? err : emax;
             if (s > 0.0) {
