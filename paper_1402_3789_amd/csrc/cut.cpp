@@ -89,8 +89,15 @@ void forest_labels(const nnm_edge* edges, int64_t n, int64_t m, int32_t* labels,
     parallel(n, [&](int, int64_t a, int64_t b) {
         for (int64_t i = a; i < b; ++i) up[(size_t)i].store((int32_t)i, std::memory_order_relaxed);
     });
+    // the union-find walks are memory-latency bound: the parent words of the
+    // edges (and points) a few iterations ahead are prefetched
+    constexpr int64_t AHEAD = 16;
     parallel(m, [&](int, int64_t a, int64_t b) {
         for (int64_t e = a; e < b; ++e) {
+            if (e + AHEAD < b) {
+                __builtin_prefetch(&up[(size_t)edges[e + AHEAD].u]);
+                __builtin_prefetch(&up[(size_t)edges[e + AHEAD].v]);
+            }
             int32_t x = edges[e].u, y = edges[e].v;
             for (;;) {
                 x = find(x);
@@ -106,6 +113,8 @@ void forest_labels(const nnm_edge* edges, int64_t n, int64_t m, int32_t* labels,
     parallel(n, [&](int t, int64_t a, int64_t b) {
         int64_t c = 0;
         for (int64_t i = a; i < b; ++i) {
+            if (i + AHEAD < b)
+                __builtin_prefetch(&up[(size_t)up[(size_t)(i + AHEAD)].load(std::memory_order_relaxed)]);
             root[(size_t)i] = find((int32_t)i);
             c += root[(size_t)i] == (int32_t)i;
         }
