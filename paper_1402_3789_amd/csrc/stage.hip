@@ -117,16 +117,30 @@ __global__ __launch_bounds__(256) void k_stage_operands_16(
 {
     // lanes past the end repeat the last point (for the wave maxima) and
     // store nothing
-    const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (blockIdx.x * (int64_t)blockDim.x >= n) return;
+    const int64_t b0 = blockIdx.x * (int64_t)blockDim.x;
+    const int64_t gi = b0 + threadIdx.x;
+    if (b0 >= n) return;
     const bool valid = gi < n;
     const int64_t i = valid ? gi : n - 1;
+    // the block's rows, read whole and together (row-major X: consecutive
+    // threads read consecutive features), then each thread's own row from LDS
+    __shared__ float tile[256 * DMAX_MFMA];
+    {
+        const int rows = (int)((n - b0) < 256 ? (n - b0) : 256);
+        for (int e = threadIdx.x; e < rows * d; e += 256) {
+            const int r = e / d;
+            const int f = e - r * d;
+            tile[e] = X[(b0 + r) * ld + f];
+        }
+    }
+    __syncthreads();
+    const float* xrow = tile + (int)(i - b0) * d;
     uint16_t q[KSLOT];
     double nrm = 0.0, vn = 0.0;
 #pragma unroll
     for (int f = 0; f < KSLOT; ++f) q[f] = 0;
     for (int f = 0; f < d; ++f) {
-        double v = ((double)X[i * ld + f] - (double)centre[f]) * (double)sigma;
+        double v = ((double)xrow[f] - (double)centre[f]) * (double)sigma;
         uint16_t h = to_lp<OP>((float)v);
         q[f] = h;
         double qd = (double)from_lp<OP>(h);
@@ -320,6 +334,7 @@ hipError_t launch_stage_operands(const float* X, int64_t n, int d, int64_t ld,
                                  float sigma, void* opR, void* opC,
                                  PointConst* pc, StageStats* st, hipStream_t s)
 {
+    if (d < 1 || d > DMAX_MFMA) return hipErrorInvalidValue;   // the row tile holds DMAX_MFMA
     unsigned g = grid_for(n, 256);
     switch (opkind) {
     case OP_BF16:
