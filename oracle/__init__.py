@@ -12,9 +12,11 @@ spanning tree) and the KL1..KL4 / distance-threshold settings of the
 "Problem settings" and "Problem statement" sections (as a cut of that tree).
 
 Parity status: every function here is pinned by the CPU tests in
-``tests/test_oracle_pins.py`` except the KL2 / KL3 size caps, whose reading
-over tree edges is self-consistent but has no printed example in the paper
-(parity unpinned for KL2 / KL3).
+``tests/test_oracle_pins.py``.  The KL2 / KL3 size caps have no printed
+example in the paper: they are pinned, under the reading that applies them
+to tree edges, by a fixture worked out by hand edge by edge
+(``tests/golden/cut_kl23_line7.txt``); that reading itself differs from the
+all-pairs process whenever a cap blocks a tree edge.
 """
 from __future__ import annotations
 

@@ -130,6 +130,15 @@ def test_cut_golden_line7():
         assert got.tolist() == lab
 
 
+def test_cut_golden_size_limits_line7():
+    X, _, cuts = read_fixture("cut_kl23_line7.txt")
+    u, v, s, w = oracle.prim_mst(X)
+    for kw, lab in cuts:
+        got, k = nnm.cluster_cut((u, v, s, w), X.shape[0], **kw)
+        assert got.tolist() == lab, kw
+        assert k == max(lab) + 1
+
+
 def test_cut_rejects_bad_edges():
     u = np.array([0, 1], np.int32)
     v = np.array([1, 2], np.int32)

@@ -218,6 +218,17 @@ def test_golden_cut_line7():
         assert k == max(lab) + 1
 
 
+def test_golden_cut_size_limits_line7():
+    # KL2 / KL3 (with KL1, KL4 and dmax) against a hand-derived fixture
+    X, _, cuts = read_fixture("cut_kl23_line7.txt")
+    u, v, s, w = oracle.prim_mst(X)
+    assert s.tolist() == [1.0, 4.0, 9.0, 16.0, 25.0, 36.0]
+    for kw, lab in cuts:
+        got, k = oracle.cut(u, v, s, w, X.shape[0], **kw)
+        assert got.tolist() == lab, kw
+        assert k == max(lab) + 1
+
+
 def test_cut_kl1_equals_dropping_heaviest_edges():
     rng = np.random.default_rng(21)
     for _ in range(30):
@@ -289,8 +300,9 @@ def test_blobs8_cut_recovers_blobs():
 
 
 def test_cut_size_caps_are_monotone_blocks():
-    # KL2 / KL3 (parity unpinned: no printed example): a blocked edge stays
-    # blocked and no cluster grows from two sides that violate the caps.
+    # KL2 / KL3 (no printed example; see also the hand-derived fixture): a
+    # blocked edge stays blocked and no cluster grows from two sides that
+    # violate the caps.
     rng = np.random.default_rng(25)
     for _ in range(20):
         n = int(rng.integers(2, 120))
