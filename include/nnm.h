@@ -233,7 +233,9 @@ nnm_status mst_build_batched(const nnm_instance *inst, int32_t count,
  *               0..K-1 in order of first appearance over i = 0..n-1;
  *   n_clusters  host output: K.
  * Errors: NNM_EINVAL (n < 1, null pointer, an edge with u >= v or out of
- * range, edges not sorted by key).
+ * range, edges not sorted by key, a negative or NaN s or w, w decreasing
+ * along the key order, or an edge taken by the cut whose two ends the edges
+ * taken before it already connect, i.e. the edges are not a tree).
  */
 nnm_status cluster_cut(const nnm_edge *edges_host, int64_t n,
                        const nnm_cut_params *params, int32_t *labels_host,

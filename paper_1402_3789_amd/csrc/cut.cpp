@@ -59,7 +59,9 @@ struct Dsu {
 // unite them concurrently (lock-free union-find, the larger root index is
 // linked under the smaller, so each root is its component's smallest point);
 // labels follow from the roots in increasing order, i.e. by first appearance.
-void forest_labels(const nnm_edge* edges, int64_t n, int64_t m, int32_t* labels, int64_t* n_clusters)
+// Returns false when an edge joins two points that the other edges already
+// connect (the edges are not a forest).
+bool forest_labels(const nnm_edge* edges, int64_t n, int64_t m, int32_t* labels, int64_t* n_clusters)
 {
     unsigned nt = std::thread::hardware_concurrency();
     if (nt < 1) nt = 1;
@@ -92,6 +94,7 @@ void forest_labels(const nnm_edge* edges, int64_t n, int64_t m, int32_t* labels,
     // the union-find walks are memory-latency bound: the parent words of the
     // edges (and points) a few iterations ahead are prefetched
     constexpr int64_t AHEAD = 16;
+    std::atomic<bool> cycle{false};
     parallel(m, [&](int, int64_t a, int64_t b) {
         for (int64_t e = a; e < b; ++e) {
             if (e + AHEAD < b) {
@@ -102,7 +105,12 @@ void forest_labels(const nnm_edge* edges, int64_t n, int64_t m, int32_t* labels,
             for (;;) {
                 x = find(x);
                 y = find(y);
-                if (x == y) break;
+                if (x == y) {
+                    // in a forest the other edges never connect an edge's two
+                    // ends, whatever has been linked so far
+                    cycle.store(true, std::memory_order_relaxed);
+                    break;
+                }
                 if (x > y) std::swap(x, y);          // link y (larger) under x
                 int32_t expect = y;
                 if (up[(size_t)y].compare_exchange_strong(expect, x, std::memory_order_acq_rel)) break;
@@ -133,6 +141,7 @@ void forest_labels(const nnm_edge* edges, int64_t n, int64_t m, int32_t* labels,
             if (root[(size_t)i] != (int32_t)i) labels[i] = labels[root[(size_t)i]];
     });
     *n_clusters = count[nt];
+    return !cycle.load();
 }
 
 bool key_before(const nnm_edge& a, const nnm_edge& b)
@@ -155,8 +164,10 @@ extern "C" nnm_status cluster_cut(const nnm_edge* edges, int64_t n, const nnm_cu
         auto check = [&](int64_t a, int64_t b) {
             for (int64_t e = a; e < b; ++e) {
                 const nnm_edge& x = edges[e];
-                if (x.u < 0 || x.u >= x.v || x.v >= n || !(x.s >= 0.0)) return false;
-                if (e > 0 && !key_before(edges[e - 1], x)) return false;
+                if (x.u < 0 || x.u >= x.v || x.v >= n || !(x.s >= 0.0) || !(x.w >= 0.0)) return false;
+                // w = sqrt(s) is nondecreasing in key order: the distance
+                // threshold may then be tested on a prefix
+                if (e > 0 && (!key_before(edges[e - 1], x) || edges[e - 1].w > x.w)) return false;
             }
             return true;
         };
@@ -191,8 +202,7 @@ extern "C" nnm_status cluster_cut(const nnm_edge* edges, int64_t n, const nnm_cu
         }
         int64_t m = lo;
         if (kl1 > 0) m = std::min<int64_t>(m, std::max<int64_t>(0, n - kl1));
-        forest_labels(edges, n, m, labels, n_clusters);
-        return NNM_OK;
+        return forest_labels(edges, n, m, labels, n_clusters) ? NNM_OK : NNM_EINVAL;
     }
 
     Dsu dsu(n);
@@ -217,6 +227,7 @@ extern "C" nnm_status cluster_cut(const nnm_edge* edges, int64_t n, const nnm_cu
         const nnm_edge& x = edges[it.second];
         const int32_t ra = dsu.root(x.u), rb = dsu.root(x.v);
         const int64_t sa = dsu.size[(size_t)ra], sb = dsu.size[(size_t)rb];
+        if (ra == rb) return NNM_EINVAL;        // the edges are not a forest
         if (priority) {
             const int cls = ((sa < sb ? sa : sb) < kl4) ? 0 : 1;
             if (cls != it.first) {

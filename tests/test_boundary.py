@@ -153,6 +153,30 @@ def test_cut_rejects_bad_edges():
                          np.array([1.0, 1.5])), 3)                      # v out of range
     lab, k = nnm.cluster_cut((u[:0], v[:0], s[:0], s[:0]), 1)
     assert k == 1 and lab.tolist() == [0]
+    # w decreasing along the key order (w must be sqrt(s), nondecreasing)
+    with pytest.raises(N.NNMError):
+        nnm.cluster_cut((u, v, np.array([1.0, 2.0]), np.array([1.5, 1.0])), 3)
+    # not a tree: the third edge closes a cycle (heap path, with and without KL4)
+    cu = np.array([0, 0, 1], np.int32)
+    cv = np.array([1, 2, 2], np.int32)
+    cs = np.array([1.0, 2.0, 3.0])
+    for kw in ({}, dict(kl4=3), dict(kl2=5)):
+        with pytest.raises(N.NNMError):
+            nnm.cluster_cut((cu, cv, cs, np.sqrt(cs)), 4, **kw)
+
+
+def test_cut_rejects_cycle_on_forest_path():
+    rng = np.random.default_rng(17)
+    n = 70_001
+    u, v, s, w = _big_sorted_tree(rng, n)
+    # the last edge repeats an earlier one (with a larger key): a cycle
+    u, v, s = u.copy(), v.copy(), s.copy()
+    u[-1], v[-1], s[-1] = u[10], v[10], s[-2] + 1.0
+    w = np.sqrt(s)
+    with pytest.raises(N.NNMError):
+        nnm.cluster_cut((u, v, s, w), n)
+    with pytest.raises(N.NNMError):
+        nnm.cluster_cut((u, v, s, w), n, dmax=1e9)
 
 
 def _big_sorted_tree(rng, n):

@@ -146,9 +146,15 @@ def int16grid(seed: int = 0, n: int = 2_000_000, d: int = 25, levels: int = 16):
 
 
 def batch256(seed: int = 0, count: int = 256, n_lo: int = 1024,
-             n_hi: int = 65536, d_lo: int = 4, d_hi: int = 25):
-    """List of ``count`` independent mixture instances of uneven N and D."""
+             n_hi: int = 65536, d_lo: int = 4, d_hi: int = 25,
+             with_components: bool = False):
+    """List of ``count`` independent mixture instances of uneven N and D.
+
+    With ``with_components`` the result is ``(instances, ks)``, ks[i] being
+    the number of mixture components instance i was drawn from (the draws
+    are the same either way)."""
     out = []
+    ks = []
     for ss in np.random.SeedSequence(int(seed)).spawn(count):
         rng = np.random.default_rng(ss)
         n = int(round(float(_log_uniform(rng, n_lo, n_hi, 1)[0])))
@@ -163,6 +169,9 @@ def batch256(seed: int = 0, count: int = 256, n_lo: int = 1024,
         X = np.concatenate(pts)
         X = X[rng.permutation(n)]
         out.append(X.astype(np.float32))
+        ks.append(k)
+    if with_components:
+        return out, ks
     return out
 
 
