@@ -58,7 +58,9 @@ typedef enum {
     NNM_ENOMEM = -2,        /* (not raised: the library allocates nothing)    */
     NNM_EDEVICE = -3,       /* a HIP call failed                              */
     NNM_ENONFINITE = -4,    /* a feature is NaN or infinite                   */
-    NNM_EUNSUPPORTED = -5   /* precision not usable for these inputs          */
+    NNM_EUNSUPPORTED = -5,  /* precision not usable for these inputs          */
+    NNM_ETOOLARGE = -6      /* input needs more than the fixed scratch of
+                               mst_build_noalloc                              */
 } nnm_status;
 
 /*
@@ -197,6 +199,28 @@ nnm_status knn_build(const float *X_dev, int64_t n, int32_t d, int64_t ld,
 nnm_status mst_build(const float *X_dev, int64_t n, int32_t d, int64_t ld,
                      const nnm_options *opt, void *ws_dev, size_t ws_bytes,
                      nnm_edge *edges_dev, void *stream, nnm_report *rep);
+
+/*
+ * mst_build for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same tree as mst_build, with no workspace argument.  Its scratch
+ * memory is a fixed device array of NNM_NOALLOC_SCRATCH_BYTES inside the
+ * library (one per GPU, held from the library's first use on that GPU until
+ * the process ends); the call allocates nothing and creates no HIP events,
+ * so the report's phase times (ms_candidates .. ms_sort) stay 0.
+ *   X_dev, n, d, ld, opt, edges_dev, stream, rep: as for mst_build.
+ * Limit: inputs whose mst_workspace_size() exceeds NNM_NOALLOC_SCRATCH_BYTES
+ * return NNM_ETOOLARGE before any device work (with default options up to
+ * about 65,536 points of at most 26 features).
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (other host threads, other streams) race and must be serialised by
+ * the caller.  Errors otherwise as for mst_build.
+ */
+#define NNM_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+nnm_status mst_build_noalloc(const float *X_dev, int64_t n, int32_t d,
+                             int64_t ld, const nnm_options *opt,
+                             nnm_edge *edges_dev, void *stream,
+                             nnm_report *rep);
 
 /* One instance of a batched call. */
 typedef struct {

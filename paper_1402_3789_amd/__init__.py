@@ -19,7 +19,7 @@ import numpy as np
 from . import _native as N
 from ._native import NNMError, NativeMissing, PREC  # noqa: F401
 
-__all__ = ["mst_build", "knn_build", "cluster_cut", "mst_build_batched", "Tree",
+__all__ = ["mst_build", "mst_build_noalloc", "knn_build", "cluster_cut", "mst_build_batched", "Tree",
            "options", "NNMError", "NativeMissing"]
 
 
@@ -128,6 +128,24 @@ def mst_build(X, precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
                        ctypes.c_void_p(ws.data_ptr()), nb.value,
                        ctypes.c_void_p(edges.data_ptr()), _stream(stream), ctypes.byref(rep))
     N.check("mst_build", code)
+    return Tree(edges[: n - 1], n, rep.as_dict())
+
+
+def mst_build_noalloc(X, precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
+                      force_fallback=False, col_splits=0, stream=None, edges=None) -> Tree:
+    """mst_build with the library's fixed device scratch instead of a
+    workspace (nothing is allocated by the library; ``edges``, if given, is a
+    float64 CUDA tensor of at least [n-1, 3] that receives the tree)."""
+    torch = _torch()
+    n, d, ld = _check_x(X)
+    o = options(precision, knn_k, survivor_cap, disable_prune, force_fallback, col_splits)
+    if edges is None:
+        edges = torch.empty((max(n - 1, 1), 3), dtype=torch.float64, device=X.device)
+    rep = N.Report()
+    code = N.lib().mst_build_noalloc(ctypes.c_void_p(X.data_ptr()), n, d, ld, ctypes.byref(o),
+                                     ctypes.c_void_p(edges.data_ptr()), _stream(stream),
+                                     ctypes.byref(rep))
+    N.check("mst_build_noalloc", code)
     return Tree(edges[: n - 1], n, rep.as_dict())
 
 

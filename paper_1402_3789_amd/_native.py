@@ -13,6 +13,8 @@ NNM_ENOMEM = -2
 NNM_EDEVICE = -3
 NNM_ENONFINITE = -4
 NNM_EUNSUPPORTED = -5
+NNM_ETOOLARGE = -6
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "auto": 3, "fp16": 4}
 PREC_NAME = {v: k for k, v in PREC.items()}
@@ -87,6 +89,9 @@ _SIG = {
     "mst_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                  ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_size_t,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Report)]),
+    "mst_build_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.c_int64, ctypes.POINTER(Options), ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.POINTER(Report)]),
     "mst_batched_workspace_size": (ctypes.c_int, [ctypes.POINTER(Instance), ctypes.c_int32,
                                                   ctypes.POINTER(Options),
                                                   ctypes.POINTER(ctypes.c_size_t)]),

@@ -20,6 +20,7 @@ extern "C" const char* nnm_strerror(int32_t status)
     case NNM_EDEVICE: return "device error";
     case NNM_ENONFINITE: return "non-finite feature value";
     case NNM_EUNSUPPORTED: return "precision not supported for these inputs";
+    case NNM_ETOOLARGE: return "input larger than the fixed scratch of mst_build_noalloc";
     default: return "unknown status";
     }
 }

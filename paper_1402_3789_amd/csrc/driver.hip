@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <vector>
 
 #include "cand_common.h"
@@ -263,6 +264,7 @@ struct Run {
     WS w;
     hipStream_t s;
     nnm_report* rep;
+    bool timers = false;    // HIP-event phase timers (with a report, unless the caller can't allocate)
     nnm_options o;
     BoundConst bc;
     float sigma = 1.f;
@@ -527,7 +529,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     {
         double ms = 0.0;
         {
-            Timer t(R.rep != nullptr, R.s, &ms);
+            Timer t(R.timers, R.s, &ms);
             if (use32) HIP_TRY(launch_cand_fp32(a, R.s));
             else HIP_TRY(launch_cand_mfma(p.opkind, a, R.s));
         }
@@ -578,7 +580,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     r.err_bits = w.ctr->err_bits;
     int32_t over = 0;
     {
-        Timer t(R.rep != nullptr, R.s, R.rep ? &R.rep->ms_rescore : nullptr);
+        Timer t(R.timers, R.s, R.rep ? &R.rep->ms_rescore : nullptr);
         HIP_TRY(hipMemsetAsync(&w.ctr->over, 0, sizeof(int32_t), R.s));
         HIP_TRY(launch_rescore(r, w.overflow_list, R.s));
         HIP_TRY(hipMemcpyAsync(&over, &w.ctr->over, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
@@ -743,6 +745,7 @@ nnm_status begin(Run& R, const float* X, int64_t n, int32_t d, int64_t ld, int32
     carve(R.p, ws, &R.w);
     R.s = (hipStream_t)stream;
     R.rep = rep;
+    R.timers = rep != nullptr;
     if (rep) memset(rep, 0, sizeof(*rep));
     return NNM_OK;
 }
@@ -798,11 +801,11 @@ nnm_status mst_rounds(Run& R, const float* X)
     nnm_status st;
     MergeArgs m = merge_args(R);
     {
-        Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
+        Timer t(R.timers, R.s, rep ? &rep->ms_merge : nullptr);
         HIP_TRY(launch_init_points(m, R.s));
     }
     {
-        Timer t(rep != nullptr, R.s, rep ? &rep->ms_sort : nullptr);
+        Timer t(R.timers, R.s, rep ? &rep->ms_sort : nullptr);
         st = spatial_order(R, X);
         if (st != NNM_OK) return st;
     }
@@ -816,13 +819,13 @@ nnm_status mst_rounds(Run& R, const float* X)
         R.round = round;
         if (rep && round < 32) rep->comps_per_round[round] = ncomp;
         {
-            Timer t(rep != nullptr, R.s, rep ? &rep->ms_sort : nullptr);
+            Timer t(R.timers, R.s, rep ? &rep->ms_sort : nullptr);
             st = sort_points(R, X);
             if (st != NNM_OK) return st;
         }
         int32_t rcount = 0;
         {
-            Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
+            Timer t(R.timers, R.s, rep ? &rep->ms_merge : nullptr);
             HIP_TRY(launch_reset_comp(m, R.s));
             HIP_TRY(launch_cursor(m, R.s));
             HIP_TRY(launch_compmin1(m, R.s));
@@ -837,7 +840,7 @@ nnm_status mst_rounds(Run& R, const float* X)
             // known bound
             int32_t nrep = 0;
             {
-                Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
+                Timer t(R.timers, R.s, rep ? &rep->ms_merge : nullptr);
                 HIP_TRY(launch_pick_reps(m, w.compS, w.rep_pos, ncomp, w.rflag2, R.s));
                 HIP_TRY(launch_compact(w.rflag2, n, w.olist, &w.ctr->rcount, w.scan_temp, R.s));
                 HIP_TRY(hipMemcpyAsync(&nrep, &w.ctr->rcount, sizeof(int32_t), hipMemcpyDeviceToHost, R.s));
@@ -853,7 +856,7 @@ nnm_status mst_rounds(Run& R, const float* X)
                 R.kk = 0;
                 if (st != NNM_OK) return st;
                 if (rep && round < 32) rep->rows_per_round[round] += nrep;
-                Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
+                Timer t(R.timers, R.s, rep ? &rep->ms_merge : nullptr);
                 HIP_TRY(launch_cursor(m, R.s));
                 HIP_TRY(launch_compmin1(m, R.s));
                 HIP_TRY(launch_flag_rescan(m, R.s));
@@ -868,7 +871,7 @@ nnm_status mst_rounds(Run& R, const float* X)
             if (st != NNM_OK) return st;
         }
         {
-            Timer t(rep != nullptr, R.s, rep ? &rep->ms_merge : nullptr);
+            Timer t(R.timers, R.s, rep ? &rep->ms_merge : nullptr);
             if (rcount > 0) {
                 HIP_TRY(launch_cursor(m, R.s));
                 HIP_TRY(launch_compmin1(m, R.s));
@@ -918,15 +921,18 @@ nnm_status sort_edges(Run& R, SortRec** res)
 
 }  // namespace
 
-extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_t ld,
-                                const nnm_options* opt, void* ws_dev, size_t ws_bytes,
-                                nnm_edge* edges_dev, void* stream, nnm_report* rep)
+namespace {
+
+nnm_status mst_build_in(const float* X_dev, int64_t n, int32_t d, int64_t ld, const nnm_options* opt,
+                        void* ws_dev, size_t ws_bytes, nnm_edge* edges_dev, void* stream,
+                        nnm_report* rep, bool timers)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (n > 1 && !edges_dev) return NNM_EINVAL;
     Run R;
     nnm_status st = begin(R, X_dev, n, d, ld, 0, opt, ws_dev, ws_bytes, stream, rep, true);
     if (st != NNM_OK) return st;
+    R.timers = R.timers && timers;
     st = stage(R, X_dev);
     if (st != NNM_OK) return st;
     if (n == 1) return finish_report(R, t0);
@@ -935,7 +941,7 @@ extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_
     st = mst_rounds(R, X_dev);
     if (st != NNM_OK) return st;
     {
-        Timer t(rep != nullptr, R.s, rep ? &rep->ms_sort : nullptr);
+        Timer t(R.timers, R.s, rep ? &rep->ms_sort : nullptr);
         SortRec* res = nullptr;
         st = sort_edges(R, &res);
         if (st != NNM_OK) return st;
@@ -943,6 +949,60 @@ extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_
         HIP_TRY(hipStreamSynchronize(R.s));
     }
     return finish_report(R, t0);
+}
+
+// Fixed scratch of mst_build_noalloc: a file-scope device array, so the
+// entry point needs no allocation.  Every GPU the library runs on holds its
+// own copy from the time the library's code is loaded there until the
+// process ends.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = NNM_NOALLOC_SCRATCH_BYTES;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The current device's copy of `scratch` (looked up on the first call on
+// that device, with that device current).
+nnm_status scratch_of_current_device(void** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return NNM_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NNM_EDEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NNM_OK;
+}
+
+}  // namespace
+
+extern "C" nnm_status mst_build(const float* X_dev, int64_t n, int32_t d, int64_t ld,
+                                const nnm_options* opt, void* ws_dev, size_t ws_bytes,
+                                nnm_edge* edges_dev, void* stream, nnm_report* rep)
+{
+    return mst_build_in(X_dev, n, d, ld, opt, ws_dev, ws_bytes, edges_dev, stream, rep, true);
+}
+
+extern "C" nnm_status mst_build_noalloc(const float* X_dev, int64_t n, int32_t d, int64_t ld,
+                                        const nnm_options* opt, nnm_edge* edges_dev, void* stream,
+                                        nnm_report* rep)
+{
+    // every argument and size check comes before the first device call
+    if (!X_dev || n < 1 || d < 1 || d > DMAX || ld < d || (n > 1 && !edges_dev)) return NNM_EINVAL;
+    size_t need = 0;
+    nnm_status st = mst_workspace_size(n, d, opt, &need);
+    if (st != NNM_OK) return st;
+    if (need > NOALLOC_SCRATCH_BYTES) return NNM_ETOOLARGE;
+    void* ws = nullptr;
+    st = scratch_of_current_device(&ws);
+    if (st != NNM_OK) return st;
+    // no HIP events either: the phase times of the report stay 0
+    return mst_build_in(X_dev, n, d, ld, opt, ws, NOALLOC_SCRATCH_BYTES, edges_dev, stream, rep, false);
 }
 
 namespace {
@@ -1012,6 +1072,7 @@ extern "C" nnm_status mst_build_batched(const nnm_instance* inst, int32_t count,
     nnm_report rep0;
     memset(&rep0, 0, sizeof(rep0));
     R.rep = reps ? &rep0 : nullptr;
+    R.timers = R.rep != nullptr;
     std::vector<int32_t> off(count + 1, 0);
     std::vector<InstDev> hin(count);
     std::vector<nnm_edge*> outp(count);
@@ -1033,7 +1094,7 @@ extern "C" nnm_status mst_build_batched(const nnm_instance* inst, int32_t count,
     if (tot > count) {
         st = mst_rounds(R, X);
         if (st != NNM_OK) return st;
-        Timer t(R.rep != nullptr, R.s, R.rep ? &R.rep->ms_sort : nullptr);
+        Timer t(R.timers, R.s, R.rep ? &R.rep->ms_sort : nullptr);
         SortRec* res = nullptr;
         st = sort_edges(R, &res);
         if (st != NNM_OK) return st;

@@ -100,6 +100,32 @@ def test_entry_points_reject_bad_arguments_before_device_work():
                        None, ctypes.byref(rep)) == N.NNM_EINVAL
 
 
+def test_noalloc_rejects_bad_and_oversized_inputs_before_device_work():
+    L = N.lib()
+    o = nnm.options()
+    rep = N.Report()
+    fake = ctypes.c_void_p(0x1000)    # never dereferenced: checks fail first
+    assert L.mst_build_noalloc(None, 10, 4, 4, ctypes.byref(o), fake, None,
+                               ctypes.byref(rep)) == N.NNM_EINVAL
+    assert L.mst_build_noalloc(fake, 0, 4, 4, ctypes.byref(o), fake, None,
+                               ctypes.byref(rep)) == N.NNM_EINVAL
+    assert L.mst_build_noalloc(fake, 10, 33, 33, ctypes.byref(o), fake, None,
+                               ctypes.byref(rep)) == N.NNM_EINVAL
+    assert L.mst_build_noalloc(fake, 10, 4, 3, ctypes.byref(o), fake, None,
+                               ctypes.byref(rep)) == N.NNM_EINVAL
+    assert L.mst_build_noalloc(fake, 10, 4, 4, ctypes.byref(o), None, None,
+                               ctypes.byref(rep)) == N.NNM_EINVAL
+    # the largest n whose workspace fits the fixed scratch, and one far past it
+    nb = ctypes.c_size_t(0)
+    assert L.mst_workspace_size(65536, 25, ctypes.byref(o), ctypes.byref(nb)) == 0
+    assert nb.value <= N.NOALLOC_SCRATCH_BYTES
+    assert L.mst_workspace_size(300_000, 25, ctypes.byref(o), ctypes.byref(nb)) == 0
+    assert nb.value > N.NOALLOC_SCRATCH_BYTES
+    code = L.mst_build_noalloc(fake, 300_000, 25, 25, ctypes.byref(o), fake, None,
+                               ctypes.byref(rep))
+    assert code == N.NNM_ETOOLARGE and "scratch" in N.strerror(code)
+
+
 def _random_tree(rng, n, d=3, ties=False):
     X = rng.standard_normal((n, d)).astype(np.float32)
     if ties:
