@@ -52,6 +52,28 @@ def load_traffic(precision, workload):
     return t.get("bytes_per_launch")
 
 
+def oracle_digest_match(tree, n, labels):
+    """Compare the tree and the KL1 = 500 cut with the oracle's digests of the
+    same workload (tests/golden/aniso500_oracle.json, written from the oracle
+    alone); None when that file is absent or covers other data."""
+    p = os.path.join(ROOT, "tests", "golden", "aniso500_oracle.json")
+    if not os.path.exists(p):
+        return None
+    want = json.load(open(p))
+    if want.get("n") != n:
+        return None
+    import numpy as np
+    u, v, s, w = tree.to_numpy()
+    h = hashlib.sha256()
+    for a, t in ((u, "<i4"), (v, "<i4"), (s, "<f8"), (w, "<f8")):
+        h.update(np.ascontiguousarray(a, dtype=t).tobytes())
+    same_tree = h.hexdigest() == want["tree_sha256"]
+    cut = [c for c in want["cuts"] if set(c) == {"kl1", "clusters", "labels_sha256"} and c["kl1"] == 500]
+    lab = hashlib.sha256(np.ascontiguousarray(labels, "<i4").tobytes()).hexdigest()
+    same_cut = bool(cut) and lab == cut[0]["labels_sha256"]
+    return bool(same_tree and same_cut)
+
+
 def cpu_baseline(X, seconds):
     """Dense FP64 Prim (the oracle) on the first n_s points of the workload."""
     import oracle
@@ -120,10 +142,13 @@ def main():
     Xd = torch.from_numpy(X).to("cuda:0")
     torch.cuda.synchronize()
 
+    last_labels = {}
+
     def step(precision):
         tree = nnm.mst_build(Xd, precision=precision)
         # the cut copies the n-1 edges to the host and cuts them there
         labels, k = nnm.cluster_cut(tree, n, kl1=500)
+        last_labels[precision] = labels
         return tree, k
 
     for i in range(args.warmup):
@@ -173,7 +198,9 @@ def main():
             others[prec] = {"ms_per_step": round(ms2, 3), "value": pairs / (ms2 * 1e-3),
                             "speedup_of_" + args.precision: round(ms2 / ms, 3),
                             "identical_tree": bool(same),
-                            "ms_candidates": round(tr2.report["ms_candidates"], 3)}
+                            "oracle_match": oracle_digest_match(tr2, n, last_labels[prec]),
+                            "ms_candidates": round(tr2.report["ms_candidates"], 3),
+                            "max_err_ratio": tr2.report["max_err_ratio"]}
             log(f"[bench] {prec}: {ms2:.1f} ms/step, identical tree: {same}")
 
     cpu = None
@@ -182,6 +209,8 @@ def main():
         log(f"[bench] cpu oracle: {cpu['value']:.3g} pair-distances/s ({cpu['sample']})")
 
     last = reps[-1]
+    match = oracle_digest_match(tree, n, last_labels[args.precision])
+    log(f"[bench] {args.precision} tree and cut vs the oracle's digests: {match}")
     out = {
         "metric": "MST+cut wall-time at N=2M,D=25; pair-distances/s, mixed-prec vs FP32",
         "value": pairs / (ms * 1e-3),
@@ -199,11 +228,13 @@ def main():
                    "precision": args.precision, "cut": "kl1=500", "seed": 0},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "oracle_match": match,
         "fp32_path": others.get("fp32"),
         "other_paths": {k2: v2 for k2, v2 in others.items() if k2 != "fp32"},
         "report": {k2: last[k2] for k2 in ("rounds", "rows_scanned", "pairs_evaluated",
                                             "survivors", "overflow_rows", "max_abs_err",
-                                            "max_rel_err", "max_bound", "ms_candidates", "ms_rescore",
+                                            "max_rel_err", "max_bound", "max_err_ratio",
+                                            "ms_candidates", "ms_rescore",
                                             "ms_merge", "ms_sort", "rows_per_round",
                                             "comps_per_round")},
     }

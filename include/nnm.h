@@ -136,7 +136,9 @@ typedef struct {
     int64_t overflow_rows;      /* rows that needed the exact full FP64 scan  */
     double max_abs_err;         /* max |t - s| over rescored candidates       */
     double max_rel_err;         /* max |t - s| / s over candidates with s > 0 */
-    double max_bound;           /* largest error bound applied                */
+    double max_bound;           /* largest bound E(t) on |t - s| that the
+                                   candidate pass applied to a rescored
+                                   candidate (0 on exact integer data)        */
     double ms_total;            /* wall time of the call, ms                  */
     double ms_candidates;       /* candidate kernels, ms (HIP events)         */
     double ms_rescore;          /* FP64 rescoring, ms                         */
@@ -151,6 +153,9 @@ typedef struct {
     int64_t exact_per_round[32];/* rows needing the exact scan in each round  */
     double cand_ms_per_round[32];/* candidate-kernel time in each round, ms    */
     int64_t surv_per_round[32]; /* survivors rescored in each round           */
+    double max_err_ratio;       /* max over rescored candidates of |t - s| /
+                                   E(t), E(t) the bound applied to it (0/0 = 0,
+                                   x/0 = inf); the proof makes it <= 1        */
 } nnm_report;
 
 /* Fill *opt with the defaults (AUTO precision, automatic k and caps). */

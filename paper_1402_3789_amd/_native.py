@@ -55,7 +55,8 @@ class Report(ctypes.Structure):
                 ("over_per_round", ctypes.c_int64 * 32),
                 ("exact_per_round", ctypes.c_int64 * 32),
                 ("cand_ms_per_round", ctypes.c_double * 32),
-                ("surv_per_round", ctypes.c_int64 * 32)]
+                ("surv_per_round", ctypes.c_int64 * 32),
+                ("max_err_ratio", ctypes.c_double)]
 
     def as_dict(self):
         out = {}

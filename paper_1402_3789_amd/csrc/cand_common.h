@@ -3,6 +3,7 @@
 // chunks and the chunk pruning test.
 #pragma once
 
+#include "bound.h"
 #include "nnm_common.h"
 
 namespace nnm {

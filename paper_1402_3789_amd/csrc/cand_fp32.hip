@@ -16,16 +16,6 @@ namespace {
 constexpr int BM = 256;
 constexpr int BN = CHUNK;
 
-__device__ __forceinline__ float fp32_thresh_from_U(double U, double crel, double a0)
-{
-    return d2f_up((U * (1.0 + crel) + a0) * (1.0 + 0x1p-40));
-}
-
-__device__ __forceinline__ double fp32_upper_from_t(double t, double crel, double a0)
-{
-    return (t + a0) / (1.0 - crel) * (1.0 + 0x1p-40);
-}
-
 template <int DP>
 __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
 {
@@ -41,8 +31,8 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
     const int64_t slot = (int64_t)tile.x + tid;
     const bool valid = slot < tile.y;
     const int rp = valid ? (a.rows ? a.rows[slot] : a.row0 + (int)slot) : 0;
-    const double crel = (double)(a.d + 3) * 0x1p-24 + 0x1p-40;
-    const double a0 = (double)a.d * 0x1p-148;
+    const double crel = fp32_crel(a.d);
+    const double a0 = fp32_a0(a.d);
 
     float xr[DP];
     {

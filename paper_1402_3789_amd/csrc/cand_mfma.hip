@@ -52,7 +52,6 @@ constexpr int WAVES = 4;
 constexpr int RB = 4;                 // 16-row blocks per wave
 constexpr int BM = WAVES * RB * 16;   // rows per workgroup (= threads)
 constexpr int BN = CHUNK;             // columns per LDS chunk
-constexpr float KFAC = 1.0f + 0x1p-20f;
 constexpr int SEEDW = 32;             // seeding window: sweep-order neighbours on each side
 constexpr int NQR = (DMAX_MFMA + 3) / 4;   // float4s of a row's coordinates
 
@@ -84,35 +83,6 @@ template <> struct OpTraits<OP_FP8> {
                                                          f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
     }
 };
-
-// Upper bound on the exact (scaled) key of a column whose candidate is t,
-// t + E(t) with E(t) = KFAC (eps + eta (2 sqrt(t + eps) + eta)) bounding
-// |t - s| (eps: accumulation slack, eta: quantisation slack, both already
-// combined with the column's).  FP32 with a margin that covers its own
-// roundings (sqrt within 1 ulp, a dozen operations).
-__device__ __forceinline__ float upper_from_t(float t, float eps, float eta, int exact)
-{
-    if (exact) return t;
-    const float e = KFAC * (eps + eta * (2.f * __builtin_sqrtf(fmaxf(t, 0.f) + eps) + eta));
-    return (t + e) + (__builtin_fabsf(t) + e) * 0x1p-18f;
-}
-
-// Largest candidate value that can still belong to a column whose exact key
-// is <= U (scaled units): t - E(t) <= U  iff  sqrt(t + eps) <= W with
-// W = KFAC eta + sqrt(KFAC^2 eta^2 + U + eps (1 + KFAC) + KFAC eta^2).
-// Never above FLT_MAX, so +inf candidates (masked columns) never pass.
-__device__ __forceinline__ float thresh_from_U(float U, float eps, float eta, int exact)
-{
-    float T;
-    if (exact) {
-        T = U;
-    } else {
-        const float ke = KFAC * eta;
-        const float W = ke + __builtin_sqrtf(ke * ke + U + eps * (1.f + KFAC) + ke * eta);
-        T = (W * W - eps) + (W * W + eps) * 0x1p-18f;
-    }
-    return fminf(T, 3.402823466e38f);
-}
 
 // Upper bound, in FP32, on the exact key of a pair whose FP32 direct-difference
 // sum of squares over d features is s (relative error below (d + 2) 2^-24,
@@ -328,9 +298,8 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     } else {
         if (my_valid) mypc = a.pc[my_rp];
         // one frame for every pair: the row's slack is fixed
-        rs[tid][0].z = (a.bc.gamma * (2.f * mypc.Q * a.bc.colQ + mypc.P + a.bc.colP) + mypc.rho + a.bc.colRho) *
-                       (1.f + 0x1p-20f);
-        rs[tid][0].w = (mypc.eta + a.bc.colEta) * (1.f + 0x1p-22f);
+        rs[tid][0].z = global_eps(mypc, a.bc);
+        rs[tid][0].w = global_eta(mypc, a.bc);
         rs[tid][0].x = my_valid ? thresh_from_U(U * s2, rs[tid][0].z, rs[tid][0].w, exact) : -__builtin_huge_valf();
     }
     if (tid == 0) {
@@ -588,13 +557,16 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                             pos = __float_as_int(s1.x);
                             rs[rl][1].x = __int_as_float(pos + 1);
                         }
+                        const float eps = st.z, eta = st.w;
+                        // LOCAL: t + E(t) in this chunk's frame (kept for the
+                        // error report) and the bound on the key in data units
+                        const float upv = LOCAL ? upper_from_t(v, eps, eta, exact) : v;
                         if (pos < a.S) {
                             a.surv_j[slot * a.S + pos] = (int)(c0 + cj);
                             a.surv_t[slot * a.S + pos] = v;
+                            if (LOCAL) a.surv_e[slot * a.S + pos] = upv;
                         }
-                        const float eps = st.z, eta = st.w;
-                        // LOCAL: a bound on the key (data units); else t itself
-                        const float key = LOCAL ? d2f_up((double)upper_from_t(v, eps, eta, exact) * inv_s2) : v;
+                        const float key = LOCAL ? d2f_up((double)upv * inv_s2) : v;
                         // the row's list (read above), rewritten with vector stores
                         float kth_old = __builtin_huge_valf();
 #pragma unroll

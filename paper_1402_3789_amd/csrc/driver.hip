@@ -36,7 +36,7 @@ struct Counters {
     // from every workgroup
     unsigned long long pairs[NSPREAD * SPREAD_STRIDE];
     unsigned long long survivors[NSPREAD * SPREAD_STRIDE];
-    unsigned long long err_bits[2];
+    unsigned long long err_bits[4];
 };
 
 unsigned long long spread_sum(const unsigned long long* v)
@@ -60,6 +60,7 @@ struct Plan {
     int L1 = 1, L2 = 1;             // fine / coarse landmarks of the spatial order
     int ninst = 1;                  // instances in the point set (batched calls)
     bool local = false;             // BF16 operands built per tile from FP32 (not exact data)
+    bool keep_e = false;            // workspace holds t + E(t) per survivor (BF16 asked for)
 };
 
 struct WS {
@@ -74,7 +75,7 @@ struct WS {
     double* rbest_s; int32_t* rbest_j; int32_t* rstat;
     unsigned long long* cbest_s; unsigned long long* cbest_p;
     int32_t* rflag; int32_t* rlist; double* u0s;
-    int32_t* surv_cnt; int32_t* surv_j; float* surv_t;
+    int32_t* surv_cnt; int32_t* surv_j; float* surv_t; float* surv_e;
     int32_t* overflow_list;
     SortRec* edges; SortRec* srtA; SortRec* srtB;
     void* scan_temp; void* radix_temp;
@@ -138,6 +139,7 @@ size_t carve(const Plan& p, void* base, WS* w)
     w->surv_cnt = c.take<int32_t>((size_t)p.rmax);
     w->surv_j = c.take<int32_t>((size_t)p.rmax * p.S);
     w->surv_t = c.take<float>((size_t)p.rmax * p.S);
+    w->surv_e = p.keep_e ? c.take<float>((size_t)p.rmax * p.S) : nullptr;
     w->overflow_list = c.take<int32_t>((size_t)p.rmax);
     w->edges = c.take<SortRec>(n);
     w->srtA = c.take<SortRec>(n);
@@ -200,6 +202,9 @@ nnm_status plan_common(int64_t n, int32_t d, int32_t k, const nnm_options* opt, 
     if (o.precision != NNM_PREC_FP32 && o.precision != NNM_PREC_AUTO && d > DMAX_MFMA)
         return NNM_EUNSUPPORTED;
     p->op_bytes = 64;
+    // the per-tile frame (BF16 on data that is not an integer grid) keeps
+    // the bound it applied to each survivor for the error report
+    p->keep_e = o.precision == NNM_PREC_BF16;
     int S = o.survivor_cap;
     if (S <= 0) {
         const double lnr = log((double)std::max<int64_t>(n / std::max(p->k, 1), 2));
@@ -507,6 +512,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     a.surv_cnt = w.surv_cnt;
     a.surv_j = w.surv_j;
     a.surv_t = w.surv_t;
+    a.surv_e = w.surv_e;
     a.pairs = w.ctr->pairs;
     a.X = X;
     a.ld = p.ld;
@@ -578,6 +584,10 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     r.oflag = w.oflag;
     r.survivors = w.ctr->survivors;
     r.err_bits = w.ctr->err_bits;
+    r.bound_mode = use32 ? BOUND_FP32 : (p.exact ? BOUND_EXACT : (a.local ? BOUND_LOCAL : BOUND_GLOBAL));
+    r.pcs = w.pcs;
+    r.bc = R.bc;
+    r.surv_e = w.surv_e;
     int32_t over = 0;
     {
         Timer t(R.timers, R.s, R.rep ? &R.rep->ms_rescore : nullptr);
@@ -673,21 +683,13 @@ nnm_status finish_report(Run& R, std::chrono::steady_clock::time_point t0)
                             : R.p.opkind == OP_FP16 ? NNM_PREC_FP16 : NNM_PREC_FP8;
     R.rep->integer_mode = R.p.exact;
     R.rep->knn_k = R.p.k;
-    // largest bound applied at the typical scale (per unit of sigma^2 s)
-    const BoundConst& b = R.bc;
-    if (R.p.opkind == OP_FP32) {
-        R.rep->max_bound = (double)(R.p.d + 3) * 0x1p-24;
-    } else if (b.exact) {
-        R.rep->max_bound = 0.0;
-    } else {
-        // per-tile frame: every scaled offset from a tile centre is below 2
-        // per feature, which caps Q, P, rho and eta
-        const double Qm = 2.0 * sqrt((double)R.p.d);
-        const double al = (R.p.opkind == OP_BF16 ? 0x1p-8 : 0x1p-11) + 0x1p-22;
-        const double eta = al * Qm + (R.p.opkind == OP_BF16 ? 0x1p-125 : 0x1p-25) * sqrt((double)R.p.d);
-        R.rep->max_bound = ((double)b.gamma * (2.0 * Qm * Qm + 2.0 * Qm * Qm) + 2.0 * Qm * Qm * 27.0 * 0x1p-24 +
-                            2.0 * eta * 2.0 * eta) / (double)b.sigma2;
-    }
+    // the largest bound E(t) the candidate pass applied to a rescored
+    // survivor, and the largest ratio of the observed error to it
+    double e2, e3;
+    memcpy(&e2, &c.err_bits[2], 8);
+    memcpy(&e3, &c.err_bits[3], 8);
+    R.rep->max_bound = e2;
+    R.rep->max_err_ratio = e3;
     R.rep->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return NNM_OK;
 }

@@ -187,6 +187,7 @@ struct CandArgs {
     int32_t* surv_cnt;        // [n_rows]
     int32_t* surv_j;          // [n_rows][S] sorted column positions
     float* surv_t;            // [n_rows][S] candidate values
+    float* surv_e;            // [n_rows][S] per-tile frame only: t + E(t) as applied
     unsigned long long* pairs;// [NSPREAD * SPREAD_STRIDE] count of evaluated pairs
     // chunk pruning and near-first order
     const float* X;           // original features (row-tile balls)
@@ -245,7 +246,13 @@ struct RescoreArgs {
     double* u0b;              // [n] by sorted position: bound for the re-scan (level 1)
     int32_t* oflag;           // [n] by sorted position: row overflowed (level 1)
     unsigned long long* survivors; // [NSPREAD * SPREAD_STRIDE] counter
-    unsigned long long* err_bits;  // [2]: max abs err, max rel err (double bits)
+    // error report: max |t - s|, max |t - s| / s, the largest bound E(t)
+    // applied to a rescored survivor and max |t - s| / E(t) (double bits)
+    unsigned long long* err_bits;  // [4]
+    int32_t bound_mode;       // BoundMode of the candidate pass that ran
+    const PointConst* pcs;    // BOUND_GLOBAL: per sorted position
+    BoundConst bc;            // BOUND_GLOBAL: column maxima
+    const float* surv_e;      // BOUND_LOCAL: [n_rows][S] t + E(t)
 };
 
 hipError_t launch_rescore(const RescoreArgs& a, int32_t* overflow_list, hipStream_t s);

@@ -6,6 +6,7 @@
 // the row's neighbour list.  Rows whose survivor list overflowed are handled
 // by an exact FP64 scan of the whole row instead.  These are the only places
 // besides the final edge sort where the GPU computes in FP64.
+#include "bound.h"
 #include "nnm_common.h"
 
 namespace nnm {
@@ -54,8 +55,16 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
     const float tf = (a.tfin && !over) ? __uint_as_float(a.tfin[slot]) : __builtin_huge_valf();
     double sv[E];
     int jv[E];
-    double emax = 0.0, rmax = 0.0;
+    double emax = 0.0, rmax = 0.0, bmax = 0.0, qmax = 0.0;
     int nsurv = 0;
+    // the bound the candidate pass applied to this row's survivors
+    float eps_r = 0.f, eta_r = 0.f;
+    if (a.bound_mode == BOUND_GLOBAL) {
+        const PointConst pr = a.pcs[rp];
+        eps_r = global_eps(pr, a.bc);
+        eta_r = global_eta(pr, a.bc);
+    }
+    const double crel = fp32_crel(a.d), a0 = fp32_a0(a.d);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         sv[e] = __builtin_huge_val();
@@ -73,6 +82,17 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
                 const double rel = err / s;
                 rmax = rel > rmax ? rel : rmax;
             }
+            // E(t), data units: what the candidate pass took |t - s| to be at most
+            double eb = 0.0;
+            if (a.bound_mode == BOUND_FP32)
+                eb = fp32_upper_from_t((double)tv, crel, a0) - (double)tv;
+            else if (a.bound_mode == BOUND_GLOBAL)
+                eb = ((double)upper_from_t(tv, eps_r, eta_r, 0) - (double)tv) * a.inv_sigma2;
+            else if (a.bound_mode == BOUND_LOCAL)
+                eb = ((double)a.surv_e[slot * a.S + idx] - (double)tv) * a.inv_sigma2;
+            bmax = eb > bmax ? eb : bmax;
+            const double q = err > 0.0 ? (eb > 0.0 ? err / eb : __builtin_huge_val()) : 0.0;
+            qmax = q > qmax ? q : qmax;
             ++nsurv;
             if (over || u0s < 0.0 || s <= u0s) {
                 sv[e] = s;
@@ -115,13 +135,19 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
     for (int off = 32; off > 0; off >>= 1) {
         const double o1 = __shfl_xor(emax, off);
         const double o2 = __shfl_xor(rmax, off);
+        const double o3 = __shfl_xor(bmax, off);
+        const double o4 = __shfl_xor(qmax, off);
         emax = o1 > emax ? o1 : emax;
         rmax = o2 > rmax ? o2 : rmax;
+        bmax = o3 > bmax ? o3 : bmax;
+        qmax = o4 > qmax ? o4 : qmax;
         nsurv += __shfl_xor(nsurv, off);
     }
     if (lane != 0) return;
     atomic_max_pos_double(&a.err_bits[0], emax);
     atomic_max_pos_double(&a.err_bits[1], rmax);
+    atomic_max_pos_double(&a.err_bits[2], bmax);
+    atomic_max_pos_double(&a.err_bits[3], qmax);
     if (over) {
         double b = kept >= kb ? bound : -1.0;
         if (u0s >= 0.0 && (b < 0.0 || u0s < b)) b = u0s;

@@ -7,11 +7,12 @@
   tests/golden/make_mixture64_digest.py wrote (oracle dense Prim and oracle
   cut; minutes of CPU time, so not repeated here).
 * batch256 (256 independent instances, N log-uniform in [1024, 65536], D in
-  4..25), built in one batched call: every instance's tree is checked for
-  structure (n - 1 edges, u < v, sorted by key, spanning); sampled instances
-  are compared bit for bit with the oracle's Prim, and their KL1 = 8 cuts with
-  the oracle's; on the largest instance, the smallest pair of sampled points
-  (the cut property for a single point) must be a tree edge.
+  4..25), built in one batched call in each candidate precision: every
+  instance's tree and its cut at KL1 = its own component count must match,
+  bit for bit, the oracle's digests (tests/golden/batch256_oracle.json,
+  written by tests/golden/make_fullsize_digests.py: oracle dense Prim and
+  oracle cut, one instance at a time); structure and the nearest-neighbour
+  edges of sampled points of the largest instance are checked as well.
 """
 import hashlib
 import json
@@ -90,30 +91,47 @@ def _structure(n, u, v, s):
     assert connected_components(g, directed=False)[0] == 1
 
 
-def test_batch256_full_size(nnm):
-    Xs = W.batch256(0)
+@pytest.fixture(scope="module")
+def batch():
+    with open(os.path.join(GOLDEN, "batch256_oracle.json")) as f:
+        want = json.load(f)
+    Xs, ks = W.batch256(0, with_components=True)
+    assert len(Xs) == want["count"] == 256
+    for x, k, wi in zip(Xs, ks, want["instances"]):
+        assert W.sha256(x) == wi["x_sha256"] and k == wi["components"]
+    return Xs, want["instances"]
+
+
+def _labels_digest(labels):
+    return hashlib.sha256(np.ascontiguousarray(labels, "<i4").tobytes()).hexdigest()
+
+
+@pytest.mark.parametrize("prec", ["auto", "fp32", "bf16"])
+def test_batch256_full_size(nnm, batch, prec):
+    """All 256 instances in one batched call: every tree, and every cut at
+    KL1 = the instance's own component count, identical to the oracle's
+    (digests written by tests/golden/make_fullsize_digests.py)."""
+    Xs, want = batch
     sizes = np.array([x.shape[0] for x in Xs])
-    _say("batch256", len(Xs), "instances,", int(sizes.sum()), "points")
-    trees = nnm.mst_build_batched([torch.from_numpy(x).to("cuda:0") for x in Xs])
+    _say("batch256", prec, len(Xs), "instances,", int(sizes.sum()), "points")
+    trees = nnm.mst_build_batched([torch.from_numpy(x).to("cuda:0") for x in Xs], precision=prec)
     torch.cuda.synchronize()
     host = [t.to_numpy() for t in trees]
+    bad = [b for b, (h, wi) in enumerate(zip(host, want)) if _tree_digest(*h) != wi["tree_sha256"]]
+    assert not bad, f"{prec}: {len(bad)} trees differ from the oracle, first {bad[:8]}"
+    for b, (x, h, wi) in enumerate(zip(Xs, host, want)):
+        c = wi["cut"]
+        labels, k = nnm.cluster_cut(h, n=x.shape[0], kl1=c["kl1"])
+        assert k == c["clusters"] and _labels_digest(labels) == c["labels_sha256"], \
+            f"{prec}: instance {b} cut differs"
+    _say("batch256", prec, "all 256 trees and cuts identical to the oracle")
+    if prec != "auto":
+        return
     for x, (u, v, s, w) in zip(Xs, host):
         _structure(x.shape[0], u, v, s)
         assert np.array_equal(w, np.sqrt(s))
-    _say("batch256 structure ok")
     rng = np.random.default_rng(31)
-    order = np.argsort(sizes, kind="stable")
-    mid = [int(i) for i in order if sizes[i] <= 12_000]
-    pick = sorted(set(mid[:6]) | set(rng.choice(mid, size=min(10, len(mid)), replace=False).tolist()))
-    for b in pick:
-        ref = oracle.prim_mst(Xs[b])
-        _same_tree(host[b], ref)
-        n = Xs[b].shape[0]
-        labels, k = nnm.cluster_cut(host[b], n=n, kl1=8)
-        want, wk = oracle.cut(*ref, n, kl1=8)
-        assert k == wk and np.array_equal(labels, want)
-    _say("batch256:", len(pick), "sampled instances identical to the oracle")
-    big = int(order[-1])
+    big = int(np.argmax(sizes))
     X = Xs[big]
     u, v, s, w = host[big]
     keys = set(zip(u.tolist(), v.tolist()))

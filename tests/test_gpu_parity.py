@@ -88,6 +88,34 @@ def test_integer_grid_ties(nnm, prec):
     assert k == ok and np.array_equal(lab, olab)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16", "fp8"])
+@pytest.mark.parametrize("data", ["aniso", "mixture", "grid"])
+def test_error_report_within_applied_bound(nnm, prec, data):
+    """Every rescored candidate's |t - s| is within the bound E(t) that the
+    candidate pass applied to it (report: max ratio <= 1), and the largest
+    error is within the largest bound; exact on integer data."""
+    if data == "aniso":
+        X, _ = W.aniso500(1, n=20000, k=40)
+    elif data == "mixture":
+        X, _ = W.mixture64(1, n=20000)
+    else:
+        X = W.int16grid(1, n=8000)
+    if prec == "fp8" and data != "grid":
+        pytest.skip("FP8 serves integer grids only")
+    _say("error report", prec, data, X.shape)
+    tree = nnm.mst_build(_dev(X), precision=prec)
+    torch.cuda.synchronize()
+    rep = tree.report
+    assert rep["survivors"] > 0
+    assert rep["max_err_ratio"] <= 1.0, rep
+    assert rep["max_abs_err"] <= rep["max_bound"] or rep["max_abs_err"] == 0.0
+    if data == "grid" and prec != "fp32":
+        assert rep["integer_mode"] == 1
+        assert rep["max_abs_err"] == 0.0 and rep["max_bound"] == 0.0
+    else:
+        assert rep["max_bound"] > 0.0
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 17, 255, 256, 257, 1000, 4097])
 def test_ragged_sizes(nnm, n):
     rng = np.random.default_rng(n)
