@@ -121,7 +121,9 @@ typedef struct {
     int32_t disable_prune;  /* 1: rescan every exhausted row (debug)          */
     int32_t force_fallback; /* 1: rescore every row by a full FP64 scan       */
     int32_t col_splits;     /* column splits per row tile (0 = auto)          */
-    int32_t reserved[10];
+    int32_t fixed_chunks;   /* 1: column chunks never follow the components
+                               (debug)                                        */
+    int32_t reserved[9];
 } nnm_options;
 
 /* Per-call measurements (all optional to read; filled when non-NULL). */

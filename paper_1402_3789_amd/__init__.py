@@ -29,7 +29,7 @@ def _torch():
 
 
 def options(precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
-            force_fallback=False, col_splits=0) -> N.Options:
+            force_fallback=False, col_splits=0, fixed_chunks=False) -> N.Options:
     o = N.Options()
     N.lib().nnm_default_options(ctypes.byref(o))
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
@@ -38,6 +38,7 @@ def options(precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
     o.disable_prune = int(bool(disable_prune))
     o.force_fallback = int(bool(force_fallback))
     o.col_splits = int(col_splits)
+    o.fixed_chunks = int(bool(fixed_chunks))
     return o
 
 
@@ -113,12 +114,14 @@ class Tree:
 
 
 def mst_build(X, precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
-              force_fallback=False, col_splits=0, stream=None, workspace=None) -> Tree:
+              force_fallback=False, col_splits=0, stream=None, workspace=None,
+              fixed_chunks=False) -> Tree:
     """Exact key-ordered minimum spanning tree of the rows of X (device)."""
     torch = _torch()
     n, d, ld = _check_x(X)
     L = N.lib()
-    o = options(precision, knn_k, survivor_cap, disable_prune, force_fallback, col_splits)
+    o = options(precision, knn_k, survivor_cap, disable_prune, force_fallback, col_splits,
+                fixed_chunks)
     nb = ctypes.c_size_t(0)
     N.check("mst_workspace_size", L.mst_workspace_size(n, d, ctypes.byref(o), ctypes.byref(nb)))
     ws = (workspace or _WS).get(nb.value, X.device)

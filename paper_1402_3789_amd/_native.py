@@ -35,7 +35,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("knn_k", ctypes.c_int32),
                 ("survivor_cap", ctypes.c_int32), ("disable_prune", ctypes.c_int32),
                 ("force_fallback", ctypes.c_int32), ("col_splits", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 10)]
+                ("fixed_chunks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
 
 
 class Report(ctypes.Structure):

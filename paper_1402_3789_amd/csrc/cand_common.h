@@ -8,10 +8,6 @@
 
 namespace nnm {
 
-// Chunk size of the candidate sweep; chunk balls are built for it, and for
-// super-chunks of SUPER consecutive chunks.
-constexpr int CHUNK = 256;
-constexpr int SUPER = 16;
 
 // Shared-memory scratch for the per-workgroup tile ball and the per-chunk
 // pruning decision (one instance per workgroup).
@@ -211,6 +207,85 @@ __device__ inline float block_max(TileShared& sh, float v)
     return m;
 }
 
+// Column chunks of the sweep: CHUNK consecutive sorted positions each
+// (super-chunks of SUPER consecutive chunks), or (TAB) the component-aligned
+// tables of CandArgs, in which no chunk or super-chunk crosses a component.
+// TAB is a template parameter of the kernels, so each kernel carries the
+// arithmetic of one kind only.
+template <bool TAB>
+__device__ __forceinline__ int n_chunks(const CandArgs& a)
+{
+    if constexpr (TAB) return a.tabn[0];
+    else return (a.np + CHUNK - 1) / CHUNK;
+}
+
+template <bool TAB>
+__device__ __forceinline__ int64_t chunk_begin(const CandArgs& a, int ci)
+{
+    if constexpr (TAB) return (int64_t)a.cstart[ci];
+    else return (int64_t)ci * CHUNK;
+}
+
+template <bool TAB>
+__device__ __forceinline__ int64_t chunk_end(const CandArgs& a, int ci)
+{
+    if constexpr (TAB) {
+        return (int64_t)a.cstart[ci + 1];
+    } else {
+        const int64_t e = (int64_t)(ci + 1) * CHUNK;
+        return e < a.np ? e : (int64_t)a.np;
+    }
+}
+
+// The chunk holding sorted position p (0 <= p < np).
+template <bool TAB>
+__device__ __forceinline__ int chunk_at(const CandArgs& a, int64_t p)
+{
+    if constexpr (TAB) return a.pos2chunk[p];
+    else return (int)(p / CHUNK);
+}
+
+// First chunk, and end chunk, of the columns [lo, hi) of a tile (in the
+// aligned tables an instance's range starts and ends on chunk boundaries).
+template <bool TAB>
+__device__ __forceinline__ int chunk_first_of(const CandArgs& a, int64_t lo)
+{
+    if constexpr (TAB) return lo < a.np ? a.pos2chunk[lo] : a.tabn[0];
+    else return (int)(lo / CHUNK);
+}
+
+template <bool TAB>
+__device__ __forceinline__ int chunk_end_of(const CandArgs& a, int64_t hi)
+{
+    if constexpr (TAB) return hi < a.np ? a.pos2chunk[hi] : a.tabn[0];
+    else return (int)((hi + CHUNK - 1) / CHUNK);
+}
+
+template <bool TAB>
+__device__ __forceinline__ int super_of(const CandArgs& a, int ci)
+{
+    if constexpr (TAB) return a.csup[ci];
+    else return ci / SUPER;
+}
+
+template <bool TAB>
+__device__ __forceinline__ int super_first(const CandArgs& a, int sc)
+{
+    if constexpr (TAB) return a.sfirst[sc];
+    else return sc * SUPER;
+}
+
+template <bool TAB>
+__device__ __forceinline__ int super_end(const CandArgs& a, int sc)
+{
+    if constexpr (TAB) {
+        return a.sfirst[sc + 1];
+    } else {
+        const int e = (sc + 1) * SUPER, nc = n_chunks<TAB>(a);
+        return e < nc ? e : nc;
+    }
+}
+
 // Near-first visiting order of the chunks [lo, hi) around `start`:
 // start, start+1, start-1, start+2, ...  step -> chunk index or -1.
 __device__ __forceinline__ int zigzag(int step, int start, int lo, int hi)
@@ -236,20 +311,20 @@ __device__ __forceinline__ int zigzag(int step, int start, int lo, int hi)
 // chunk).  process() must end by storing its waves' maxima of U_i in
 // sh.wmax; umax is refreshed from them, behind one barrier, only after a
 // chunk was processed.  All 256 threads call this with identical arguments.
-template <typename Fn>
+template <bool TAB, typename Fn>
 __device__ inline void sweep_chunks(TileShared& sh, const CandArgs& a, int lo_r, int hi_r,
                                     float umax, Fn&& process)
 {
-    const int first_ch = sh.col_lo / CHUNK;
-    const int nch = (sh.col_hi + CHUNK - 1) / CHUNK - first_ch;
+    const int first_ch = chunk_first_of<TAB>(a, sh.col_lo);
+    const int nch = chunk_end_of<TAB>(a, sh.col_hi) - first_ch;
     const int cps = (nch + a.col_splits - 1) / a.col_splits;
     const int ch_lo = first_ch + (int)blockIdx.y * cps;
     const int ch_hi = ch_lo + cps < first_ch + nch ? ch_lo + cps : first_ch + nch;
     if (ch_lo >= ch_hi) return;
-    int start = sh.first_pos / CHUNK;
+    int start = chunk_at<TAB>(a, sh.first_pos);
     start = start < ch_lo ? ch_lo : (start >= ch_hi ? ch_hi - 1 : start);
-    const int sc_lo = ch_lo / SUPER, sc_hi = (ch_hi - 1) / SUPER + 1;
-    const int sc_start = start / SUPER;
+    const int sc_lo = super_of<TAB>(a, ch_lo), sc_hi = super_of<TAB>(a, ch_hi - 1) + 1;
+    const int sc_start = super_of<TAB>(a, start);
     bool stale = false;
     for (int ss = 0; ss < sc_hi - sc_lo; ++ss) {
         const int sc = zigzag(ss, sc_start, sc_lo, sc_hi);
@@ -261,13 +336,14 @@ __device__ inline void sweep_chunks(TileShared& sh, const CandArgs& a, int lo_r,
             }
             if (ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE) > umax) continue;
         }
-        const int c_lo = sc * SUPER > ch_lo ? sc * SUPER : ch_lo;
-        const int c_hi = sc * SUPER + SUPER < ch_hi ? sc * SUPER + SUPER : ch_hi;
+        const int sf = super_first<TAB>(a, sc), se = super_end<TAB>(a, sc);
+        const int c_lo = sf > ch_lo ? sf : ch_lo;
+        const int c_hi = se < ch_hi ? se : ch_hi;
         const int cstart = (sc == sc_start) ? start : (sc > sc_start ? c_lo : c_hi - 1);
         for (int cs = 0; cs < c_hi - c_lo; ++cs) {
             const int ci = zigzag(cs, cstart, c_lo, c_hi);
-            const int64_t c0 = (int64_t)ci * CHUNK;
-            const int64_t c1 = (a.np - c0) < CHUNK ? a.np - 1 : c0 + CHUNK - 1;
+            const int64_t c0 = chunk_begin<TAB>(a, ci);
+            const int64_t c1 = chunk_end<TAB>(a, ci) - 1;
             const int lo_c = a.compS[c0], hi_c = a.compS[c1];
             if (lo_r == hi_r && lo_c == hi_c && lo_r == lo_c) continue;   // all one component
             if (a.prune) {
@@ -297,6 +373,7 @@ __device__ inline void sweep_chunks(TileShared& sh, const CandArgs& a, int lo_r,
 // wave evaluates the same candidates, so all threads of the workgroup step
 // in lockstep when they call next() with the same umax.
 static_assert(SUPER == 16 && DMAX == 32, "chunk tests: 16 steps x 4 lanes x 8 features");
+template <bool TAB>
 struct ChunkIter {
     int ch_lo, ch_hi, start;         // chunk range of this split; the tile's own chunk
     int sc_lo, sc_hi, sc_start;      // super-chunk range; the tile's own super-chunk
@@ -306,6 +383,7 @@ struct ChunkIter {
     int c_lo, c_hi, cstart, cs;      // current super-chunk's chunks; next step
     unsigned cmask;                  // its passing steps
     int my_lo, my_hi;                // lanes 0..SUPER-1: component range of that step's chunk
+    int my_b0, my_b1;                // TAB: and its sorted positions [b0, b1)
     bool in_super;
     // chunk data of super-chunk psc (-1: none): lane step + 16 part holds
     // centre features [8 part, 8 part + 8), the radius and the component
@@ -314,33 +392,41 @@ struct ChunkIter {
     float4 pc0, pc1;
     float prad;
     int plo, phi;
+    int pb0, pb1;
 
     __device__ void init(const TileShared& sh, const CandArgs& a)
     {
-        const int first_ch = sh.col_lo / CHUNK;
-        const int nch = (sh.col_hi + CHUNK - 1) / CHUNK - first_ch;
+        const int first_ch = chunk_first_of<TAB>(a, sh.col_lo);
+        const int nch = chunk_end_of<TAB>(a, sh.col_hi) - first_ch;
         const int cps = (nch + a.col_splits - 1) / a.col_splits;
         ch_lo = first_ch + (int)blockIdx.y * cps;
         ch_hi = ch_lo + cps < first_ch + nch ? ch_lo + cps : first_ch + nch;
-        start = sh.first_pos / CHUNK;
-        start = start < ch_lo ? ch_lo : (start >= ch_hi ? ch_hi - 1 : start);
-        sc_lo = ch_lo / SUPER;
-        sc_hi = ch_lo < ch_hi ? (ch_hi - 1) / SUPER + 1 : sc_lo;
-        sc_start = start / SUPER;
+        if (ch_lo < ch_hi) {
+            start = chunk_at<TAB>(a, sh.first_pos);
+            start = start < ch_lo ? ch_lo : (start >= ch_hi ? ch_hi - 1 : start);
+            sc_lo = super_of<TAB>(a, ch_lo);
+            sc_hi = super_of<TAB>(a, ch_hi - 1) + 1;
+            sc_start = super_of<TAB>(a, start);
+        } else {
+            start = ch_lo;
+            sc_lo = sc_hi = sc_start = 0;   // nothing to visit
+        }
         ss = 0;
         sbase = -64;
         smask = 0ull;
         cmask = 0u;
         in_super = false;
         my_lo = my_hi = 0;
+        my_b0 = my_b1 = 0;
         psc = -1;
     }
 
     // chunks [lo, hi) of super-chunk sc within this split, and its first one
-    __device__ void super_range(int sc, int* lo, int* hi, int* first) const
+    __device__ void super_range(const CandArgs& a, int sc, int* lo, int* hi, int* first) const
     {
-        *lo = sc * SUPER > ch_lo ? sc * SUPER : ch_lo;
-        *hi = sc * SUPER + SUPER < ch_hi ? sc * SUPER + SUPER : ch_hi;
+        const int sf = super_first<TAB>(a, sc), se = super_end<TAB>(a, sc);
+        *lo = sf > ch_lo ? sf : ch_lo;
+        *hi = se < ch_hi ? se : ch_hi;
         *first = (sc == sc_start) ? start : (sc > sc_start ? *lo : *hi - 1);
     }
 
@@ -349,13 +435,17 @@ struct ChunkIter {
     {
         const int lane = threadIdx.x & 63, step = lane & 15, part = lane >> 4;
         int lo, hi, first;
-        super_range(sc, &lo, &hi, &first);
+        super_range(a, sc, &lo, &hi, &first);
         // steps past the end load the first chunk again; their test is off
         const int ci = zigzag(step < hi - lo ? step : 0, first, lo, hi);
-        const int64_t c0 = (int64_t)ci * CHUNK;
-        const int64_t c1 = (a.np - c0) < CHUNK ? a.np - 1 : c0 + CHUNK - 1;
+        const int64_t c0 = chunk_begin<TAB>(a, ci);
+        const int64_t c1 = chunk_end<TAB>(a, ci) - 1;
         plo = a.compS[c0];
         phi = a.compS[c1];
+        if constexpr (TAB) {
+            pb0 = (int)c0;
+            pb1 = (int)c1 + 1;
+        }
         const float* b = a.balls + (int64_t)ci * BALL_STRIDE;
         pc0 = *reinterpret_cast<const float4*>(b + 8 * part);
         pc1 = *reinterpret_cast<const float4*>(b + 8 * part + 4);
@@ -394,11 +484,17 @@ struct ChunkIter {
         cmask = (unsigned)__ballot(pass);
         my_lo = plo;
         my_hi = phi;
+        if constexpr (TAB) {
+            my_b0 = pb0;
+            my_b1 = pb1;
+        }
     }
 
-    // Next chunk to process, or -1; *lo_c / *hi_c receive its component range.
+    // Next chunk to process, or -1; *lo_c / *hi_c receive its component range
+    // and [*b0, *b1) its sorted positions (read with the chunk's test data,
+    // so fetching the chunk waits on no further load).
     __device__ int next(const TileShared& sh, const CandArgs& a, int lo_r, int hi_r, float umax,
-                        int* lo_c, int* hi_c)
+                        int* lo_c, int* hi_c, int* b0, int* b1)
     {
         const int lane = threadIdx.x & 63;
         for (;;) {
@@ -410,7 +506,15 @@ struct ChunkIter {
                     // off is wave-uniform: a lane read, not an LDS permute
                     *lo_c = __builtin_amdgcn_readlane(my_lo, off);
                     *hi_c = __builtin_amdgcn_readlane(my_hi, off);
-                    return zigzag(off, cstart, c_lo, c_hi);
+                    const int ci = zigzag(off, cstart, c_lo, c_hi);
+                    if constexpr (TAB) {
+                        *b0 = __builtin_amdgcn_readlane(my_b0, off);
+                        *b1 = __builtin_amdgcn_readlane(my_b1, off);
+                    } else {
+                        *b0 = ci * CHUNK;
+                        *b1 = *b0 + CHUNK < a.np ? *b0 + CHUNK : a.np;
+                    }
+                    return ci;
                 }
                 in_super = false;
             }
@@ -423,8 +527,8 @@ struct ChunkIter {
                 if (step < nsc) {
                     const int sc = zigzag(step, sc_start, sc_lo, sc_hi);
                     // a super-chunk entirely inside the tile's only component
-                    const int64_t s0 = (int64_t)sc * SUPER * CHUNK;
-                    const int64_t s1 = (a.np - s0) < SUPER * CHUNK ? a.np - 1 : s0 + SUPER * CHUNK - 1;
+                    const int64_t s0 = chunk_begin<TAB>(a, super_first<TAB>(a, sc));
+                    const int64_t s1 = chunk_end<TAB>(a, super_end<TAB>(a, sc) - 1) - 1;
                     const float lb = a.prune ? ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE) : 0.f;
                     pass = !(lo_r == hi_r && a.compS[s0] == lo_r && a.compS[s1] == lo_r) && lb <= umax;
                 }
@@ -438,7 +542,7 @@ struct ChunkIter {
             const int off = ss - sbase + (int)__builtin_ctzll(m);
             ss = sbase + off + 1;
             const int sc = zigzag(sbase + off, sc_start, sc_lo, sc_hi);
-            super_range(sc, &c_lo, &c_hi, &cstart);
+            super_range(a, sc, &c_lo, &c_hi, &cstart);
             if (psc != sc) load_super(a, sc);          // not loaded ahead: wait for it here
             test_super(sh, a, lo_r, hi_r, umax, c_hi - c_lo);
             cs = 0;

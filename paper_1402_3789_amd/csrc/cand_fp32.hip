@@ -16,7 +16,7 @@ namespace {
 constexpr int BM = 256;
 constexpr int BN = CHUNK;
 
-template <int DP>
+template <int DP, bool TAB>
 __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
 {
     constexpr int F4 = DP / 4;
@@ -111,16 +111,17 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
     __syncthreads();
     const float umax0 = fmaxf(fmaxf(sh.wmax[0], sh.wmax[1]), fmaxf(sh.wmax[2], sh.wmax[3]));
 
-    sweep_chunks(sh, a, lo_r, hi_r, umax0, [&](int ci, int lo_c, int hi_c) {
+    sweep_chunks<TAB>(sh, a, lo_r, hi_r, umax0, [&](int ci, int lo_c, int hi_c) {
         // a chunk made only of the row's own component holds no candidate
         const bool own = lo_c == hi_c && lo_c == rc;
-        const int64_t c0 = (int64_t)ci * BN;
-        const int ncols = (int)((a.np - c0) < BN ? (a.np - c0) : BN);
+        const int64_t c0 = chunk_begin<TAB>(a, ci);
+        const int ncols = (int)(chunk_end<TAB>(a, ci) - c0);
         const int cl = sh.col_lo, ch = sh.col_hi;
         if (a.share && valid) {
             T = fminf(T, __uint_as_float(a.gT[slot]));
             U = fminf(U, __uint_as_float(a.gU[slot]));
         }
+
         // per-row ball test: a wave whose rows are all farther from the
         // chunk's ball than their bounds skips the chunk; if every wave
         // does, so does the workgroup
@@ -204,6 +205,23 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
                   pairs * (unsigned long long)(wrows < 64 ? wrows : 64));
 }
 
+template <bool TAB>
+hipError_t launch_dp(const CandArgs& a, int dp, dim3 grid, size_t shm, hipStream_t s)
+{
+    switch (dp) {
+    case 4: k_cand_fp32<4, TAB><<<grid, 256, shm, s>>>(a); break;
+    case 8: k_cand_fp32<8, TAB><<<grid, 256, shm, s>>>(a); break;
+    case 12: k_cand_fp32<12, TAB><<<grid, 256, shm, s>>>(a); break;
+    case 16: k_cand_fp32<16, TAB><<<grid, 256, shm, s>>>(a); break;
+    case 20: k_cand_fp32<20, TAB><<<grid, 256, shm, s>>>(a); break;
+    case 24: k_cand_fp32<24, TAB><<<grid, 256, shm, s>>>(a); break;
+    case 28: k_cand_fp32<28, TAB><<<grid, 256, shm, s>>>(a); break;
+    case 32: k_cand_fp32<32, TAB><<<grid, 256, shm, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_cand_fp32(const CandArgs& a, hipStream_t s)
@@ -214,18 +232,8 @@ hipError_t launch_cand_fp32(const CandArgs& a, hipStream_t s)
     dim3 grid(nt, (unsigned)a.col_splits);
     size_t shm = (size_t)BM * a.k * sizeof(float);
     const int dp = (a.d + 3) / 4 * 4;
-    switch (dp) {
-    case 4: k_cand_fp32<4><<<grid, 256, shm, s>>>(a); break;
-    case 8: k_cand_fp32<8><<<grid, 256, shm, s>>>(a); break;
-    case 12: k_cand_fp32<12><<<grid, 256, shm, s>>>(a); break;
-    case 16: k_cand_fp32<16><<<grid, 256, shm, s>>>(a); break;
-    case 20: k_cand_fp32<20><<<grid, 256, shm, s>>>(a); break;
-    case 24: k_cand_fp32<24><<<grid, 256, shm, s>>>(a); break;
-    case 28: k_cand_fp32<28><<<grid, 256, shm, s>>>(a); break;
-    case 32: k_cand_fp32<32><<<grid, 256, shm, s>>>(a); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (a.cstart) return launch_dp<true>(a, dp, grid, shm, s);
+    return launch_dp<false>(a, dp, grid, shm, s);
 }
 
 }  // namespace nnm

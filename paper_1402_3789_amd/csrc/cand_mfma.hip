@@ -198,7 +198,7 @@ __device__ __forceinline__ void local_operands(const float* x, const float* c, f
 //   topk[r][0..KP): the k smallest candidates, +inf padded (t, or for LOCAL
 //              upper bounds on keys in data units, since the frame changes
 //              per chunk).  KP is k rounded up to 8 or 32.
-template <int OP, bool LOCAL, bool SHARE, int KP>
+template <int OP, bool LOCAL, bool SHARE, int KP, bool TAB>
 __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
 {
     typedef OpTraits<OP> Tr;
@@ -367,11 +367,10 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     // each chunk's loads and used behind the next barrier (any older value is
     // still a valid bound)
     float pf_gU = __builtin_huge_valf();
-    auto fetch = [&](int ci) {
-        const int64_t c0 = (int64_t)ci * BN;
+    auto fetch = [&](int ci, int64_t c0, int64_t cend) {
         if (SHARE && my_valid) pf_gU = __uint_as_float(a.gU[my_slot]);
         if (tid < BALL_STRIDE) pf_ball = a.balls[(int64_t)ci * BALL_STRIDE + tid];
-        const bool in = c0 + tid < a.np;
+        const bool in = c0 + tid < cend;
         if constexpr (LOCAL) {
             const float4* src = reinterpret_cast<const float4*>(a.xs + (c0 + (in ? tid : 0)) * DMAX);
 #pragma unroll
@@ -386,9 +385,9 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     // registers -> LDS buffer b, in fragment order; columns this tile never
     // pairs with (beyond the data, outside its column range, or in the
     // component of a one-component tile) get t = +inf where the format has one
-    auto stash = [&](int ci, int b) {
-        const int64_t c0 = (int64_t)ci * BN;
-        const bool col_ok = c0 + tid < a.np && c0 + tid >= cl && c0 + tid < ch &&
+    auto stash = [&](int64_t c0, int b) {
+        // (pf_cc < 0: past the chunk's end; component ids are >= 0)
+        const bool col_ok = pf_cc >= 0 && c0 + tid >= cl && c0 + tid < ch &&
                             !(one_comp && pf_cc == lo_r);
         colcomp[b][tid] = col_ok ? pf_cc : -1;
         if (tid < BALL_STRIDE) ballbuf[b][tid] = pf_ball;
@@ -451,9 +450,8 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         }
     };
 
-    auto process = [&](int ci, int b, int lo_c, int hi_c) {
-        const int64_t c0 = (int64_t)ci * BN;
-        const int ncols = (int)((a.np - c0) < BN ? (a.np - c0) : BN);
+    auto process = [&](int b, int lo_c, int hi_c, int64_t c0, int64_t cend) {
+        const int ncols = (int)(cend - c0);
         const bool pure = lo_c == hi_c;                    // the chunk is one component
         // per-row tests: a row skips a chunk made only of its own component,
         // or whose ball lies farther than its bound; a wave whose rows all
@@ -670,14 +668,14 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         }
     };
 
-    ChunkIter itr;
+    ChunkIter<TAB> itr;
     itr.init(sh, a);
-    int cur_lo = 0, cur_hi = 0;
-    int cur = itr.next(sh, a, lo_r, hi_r, umax, &cur_lo, &cur_hi);
-    if (cur >= 0) fetch(cur);
+    int cur_lo = 0, cur_hi = 0, cur_b0 = 0, cur_b1 = 0;
+    int cur = itr.next(sh, a, lo_r, hi_r, umax, &cur_lo, &cur_hi, &cur_b0, &cur_b1);
+    if (cur >= 0) fetch(cur, cur_b0, cur_b1);
     int buf = 0;
     while (cur >= 0) {
-        stash(cur, buf);
+        stash(cur_b0, buf);
         __syncthreads();        // chunk cur in LDS; every wave is done with buf ^ 1's last use
         umax = fmaxf(fmaxf(wmx[buf][0], wmx[buf][1]), fmaxf(wmx[buf][2], wmx[buf][3]));
         // bounds found by the other column splits of the row (loaded with the
@@ -693,15 +691,17 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
             }
             wdirty = true;
         }
-        int nlo = 0, nhi = 0;
-        const int nxt = itr.next(sh, a, lo_r, hi_r, umax, &nlo, &nhi);
-        if (nxt >= 0) fetch(nxt);                      // in flight while cur is processed
-        process(cur, buf, cur_lo, cur_hi);
+        int nlo = 0, nhi = 0, nb0 = 0, nb1 = 0;
+        const int nxt = itr.next(sh, a, lo_r, hi_r, umax, &nlo, &nhi, &nb0, &nb1);
+        if (nxt >= 0) fetch(nxt, nb0, nb1);            // in flight while cur is processed
+        process(buf, cur_lo, cur_hi, cur_b0, cur_b1);
         // this wave's bound for the pruning tests of later chunks
         wave_max(buf ^ 1);
         cur = nxt;
         cur_lo = nlo;
         cur_hi = nhi;
+        cur_b0 = nb0;
+        cur_b1 = nb1;
         buf ^= 1;
     }
     if (!SHARE && my_valid) a.surv_cnt[my_slot] = __float_as_int(rs[tid][1].x);
@@ -715,18 +715,25 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                   pairs * (unsigned long long)(wrows < 64 ? wrows : 64));
 }
 
-template <int OP, bool LOCAL>
-void launch_one(const CandArgs& a, dim3 grid, size_t, hipStream_t s)
+template <int OP, bool LOCAL, bool TAB>
+void launch_tab(const CandArgs& a, dim3 grid, hipStream_t s)
 {
     if (a.k <= 8) {
         const size_t shm = (size_t)BM * 8 * sizeof(float);
-        if (a.share) k_cand_mfma<OP, LOCAL, true, 8><<<grid, 256, shm, s>>>(a);
-        else k_cand_mfma<OP, LOCAL, false, 8><<<grid, 256, shm, s>>>(a);
+        if (a.share) k_cand_mfma<OP, LOCAL, true, 8, TAB><<<grid, 256, shm, s>>>(a);
+        else k_cand_mfma<OP, LOCAL, false, 8, TAB><<<grid, 256, shm, s>>>(a);
     } else {
         const size_t shm = (size_t)BM * KMAX * sizeof(float);
-        if (a.share) k_cand_mfma<OP, LOCAL, true, KMAX><<<grid, 256, shm, s>>>(a);
-        else k_cand_mfma<OP, LOCAL, false, KMAX><<<grid, 256, shm, s>>>(a);
+        if (a.share) k_cand_mfma<OP, LOCAL, true, KMAX, TAB><<<grid, 256, shm, s>>>(a);
+        else k_cand_mfma<OP, LOCAL, false, KMAX, TAB><<<grid, 256, shm, s>>>(a);
     }
+}
+
+template <int OP, bool LOCAL>
+void launch_one(const CandArgs& a, dim3 grid, size_t, hipStream_t s)
+{
+    if (a.cstart) launch_tab<OP, LOCAL, true>(a, grid, s);
+    else launch_tab<OP, LOCAL, false>(a, grid, s);
 }
 
 }  // namespace

@@ -46,6 +46,11 @@ unsigned long long spread_sum(const unsigned long long* v)
     return t;
 }
 
+// Component-aligned column chunks are used in the merge rounds whose
+// components hold ALIGN_AVG points or more on average (fewer, larger
+// components: few partly filled chunks).
+constexpr int64_t ALIGN_AVG = 512;
+
 struct Plan {
     int64_t n = 0;
     int d = 0;
@@ -82,6 +87,7 @@ struct WS {
     int32_t* perm0; int32_t* rank0; int32_t* ckey; int32_t* flag; int32_t* excl;
     float* balls;
     float* sballs;
+    ChunkTabs tabs;
     uint32_t* gT; uint32_t* gU;
     uint32_t* tfin;
     void* spatial_temp;
@@ -151,8 +157,24 @@ size_t carve(const Plan& p, void* base, WS* w)
     w->ckey = c.take<int32_t>(n);
     w->flag = c.take<int32_t>(n);
     w->excl = c.take<int32_t>(n);
-    w->balls = c.take<float>((n + CHUNK - 1) / CHUNK * BALL_STRIDE);
-    w->sballs = c.take<float>((n + CHUNK * SUPER - 1) / (CHUNK * SUPER) * BALL_STRIDE);
+    // fixed chunks, or component-aligned ones (at most n / ALIGN_AVG
+    // components, each adding at most one chunk and one super-chunk)
+    const size_t nseg_max = n / ALIGN_AVG + 1;
+    const size_t nch_max = (n + CHUNK - 1) / CHUNK + nseg_max;
+    const size_t nsc_max = (n + CHUNK * SUPER - 1) / (CHUNK * SUPER) + nseg_max;
+    w->balls = c.take<float>(nch_max * BALL_STRIDE);
+    w->sballs = c.take<float>(nsc_max * BALL_STRIDE);
+    w->tabs.segstart = c.take<int32_t>(nseg_max + 1);
+    w->tabs.ccnt = c.take<int32_t>(nseg_max);
+    w->tabs.scnt = c.take<int32_t>(nseg_max);
+    w->tabs.cbase = c.take<int32_t>(nseg_max);
+    w->tabs.sbase = c.take<int32_t>(nseg_max);
+    w->tabs.cstart = c.take<int32_t>(nch_max + 1);
+    w->tabs.csup = c.take<int32_t>(nch_max);
+    w->tabs.sfirst = c.take<int32_t>(nsc_max + 1);
+    w->tabs.spos = c.take<int32_t>(nsc_max + 1);
+    w->tabs.pos2chunk = c.take<int32_t>(n);
+    w->tabs.tabn = c.take<int32_t>(2);
     w->gT = c.take<uint32_t>((size_t)p.rmax);
     w->gU = c.take<uint32_t>((size_t)p.rmax);
     w->tfin = c.take<uint32_t>((size_t)p.rmax);
@@ -277,6 +299,7 @@ struct Run {
     int round = 0;          // current merge round (per-round report entries)
     int kk = 0;             // neighbours sought by the current scan (0 = the cache depth)
     bool fp32_scan = false; // the current scan uses the FP32 kernel whatever the precision
+    bool aligned = false;   // this round's column chunks follow the components (w.tabs)
 };
 
 int ceil_log2(int64_t v)
@@ -421,7 +444,7 @@ MergeArgs merge_args(Run& R)
 // Order points by component (components by their earliest spatial position,
 // members by spatial position); gather the operands in that order and
 // compute the bounding ball of every chunk.
-nnm_status sort_points(Run& R, const float* X)
+nnm_status sort_points(Run& R, const float* X, int64_t ncomp)
 {
     Plan& p = R.p;
     WS& w = R.w;
@@ -435,8 +458,13 @@ nnm_status sort_points(Run& R, const float* X)
         HIP_TRY(launch_gather_points(p.n, p.opkind, w.perm, w.opR, w.opC, w.pc, X, p.d, p.ld, w.comp,
                                      w.opRs, w.opCs, w.pcs, w.xs, w.compS, R.s));
     // balls from the sorted FP32 copy (the same values, contiguous rows)
-    HIP_TRY(launch_chunk_balls(w.xs, p.n, CHUNK, w.balls, R.s));
-    HIP_TRY(launch_chunk_balls(w.xs, p.n, CHUNK * SUPER, w.sballs, R.s));
+    if (R.aligned) {
+        HIP_TRY(launch_chunk_tables(w.compS, p.n, ncomp, w.tabs, w.xs, w.balls, w.sballs, w.scan_temp,
+                                    R.s));
+    } else {
+        HIP_TRY(launch_chunk_balls(w.xs, p.n, CHUNK, w.balls, R.s));
+        HIP_TRY(launch_chunk_balls(w.xs, p.n, CHUNK * SUPER, w.sballs, R.s));
+    }
     return NNM_OK;
 }
 
@@ -519,6 +547,13 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     a.perm = w.perm;
     a.balls = w.balls;
     a.sballs = w.sballs;
+    if (R.aligned) {
+        a.cstart = w.tabs.cstart;
+        a.csup = w.tabs.csup;
+        a.sfirst = w.tabs.sfirst;
+        a.pos2chunk = w.tabs.pos2chunk;
+        a.tabn = w.tabs.tabn;
+    }
     a.prune = R.o.disable_prune ? 0 : 1;
     a.local = (p.local && !use32) ? 1 : 0;
     a.share = a.col_splits > 1 ? 1 : 0;
@@ -758,7 +793,8 @@ nnm_status knn_round(Run& R, const float* X)
     HIP_TRY(launch_init_points(m, R.s));
     nnm_status st = spatial_order(R, X);
     if (st != NNM_OK) return st;
-    st = sort_points(R, X);
+    R.aligned = false;
+    st = sort_points(R, X, R.p.n);
     if (st != NNM_OK) return st;
     // every row, no bound: exact k-nearest-neighbour prefixes
     return scan_rows(R, X, nullptr, R.p.n, false);
@@ -822,7 +858,8 @@ nnm_status mst_rounds(Run& R, const float* X)
         if (rep && round < 32) rep->comps_per_round[round] = ncomp;
         {
             Timer t(R.timers, R.s, rep ? &rep->ms_sort : nullptr);
-            st = sort_points(R, X);
+            R.aligned = round > 0 && ncomp * ALIGN_AVG <= n && !R.o.fixed_chunks;
+            st = sort_points(R, X, ncomp);
             if (st != NNM_OK) return st;
         }
         int32_t rcount = 0;

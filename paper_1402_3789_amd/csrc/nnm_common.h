@@ -23,6 +23,10 @@ constexpr int BALL_STRIDE = DMAX + 4;
 constexpr int NSPREAD = 64;           // slots of the spread event counters
 constexpr int SPREAD_STRIDE = 16;     // u64 per slot: one 128-byte cache line each
 constexpr int SMAX = 2048;                       // survivor cap
+// Column chunk of the candidate sweep (at most CHUNK sorted positions; the
+// bounding balls are built per chunk) and super-chunks of SUPER chunks.
+constexpr int CHUNK = 256;
+constexpr int SUPER = 16;
 
 enum OpKind : int { OP_BF16 = 0, OP_FP16 = 1, OP_FP8 = 2, OP_FP32 = 3 };
 
@@ -193,8 +197,18 @@ struct CandArgs {
     const float* X;           // original features (row-tile balls)
     int64_t ld;
     const int32_t* perm;      // sorted position -> point
-    const float* balls;       // [ceil(np / CHUNK)][BALL_STRIDE]
-    const float* sballs;      // [ceil(np / (CHUNK * SUPER))][BALL_STRIDE]
+    const float* balls;       // [chunks][BALL_STRIDE]
+    const float* sballs;      // [super-chunks][BALL_STRIDE]
+    // component-aligned column chunks (NULL: chunks of CHUNK consecutive
+    // sorted positions, super-chunks of SUPER consecutive chunks): chunk c is
+    // [cstart[c], cstart[c + 1]), in super-chunk csup[c]; super-chunk q is
+    // chunks [sfirst[q], sfirst[q + 1]); pos2chunk[p] is the chunk holding
+    // sorted position p; tabn = {chunks, super-chunks}
+    const int32_t* cstart;
+    const int32_t* csup;
+    const int32_t* sfirst;
+    const int32_t* pos2chunk;
+    const int32_t* tabn;
     int32_t prune;
     int32_t local;            // BF16/FP16: operands built per tile from xs
     // thresholds shared by the column splits of one row (float bits)
@@ -333,6 +347,25 @@ hipError_t launch_component_order(const int32_t* comp, const int32_t* perm0, con
 // balls of the chunks of bn rows of the sorted FP32 copy xs ([n][DMAX], zero
 // beyond the data's features)
 hipError_t launch_chunk_balls(const float* xs, int64_t n, int bn, float* balls, hipStream_t s);
+
+// Component-aligned chunk tables of the sorted order (see CandArgs) and the
+// bounding balls of their chunks and super-chunks.
+struct ChunkTabs {
+    int32_t* segstart;   // [n + 1]
+    int32_t* ccnt;       // [n] chunks per segment
+    int32_t* scnt;       // [n] super-chunks per segment
+    int32_t* cbase;      // [n] first chunk of each segment
+    int32_t* sbase;      // [n] first super-chunk of each segment
+    int32_t* cstart;     // [n + 1]
+    int32_t* csup;       // [n]
+    int32_t* sfirst;     // [n + 1]
+    int32_t* spos;       // [n + 1] first sorted position of each super-chunk
+    int32_t* pos2chunk;  // [n]
+    int32_t* tabn;       // [2]
+};
+hipError_t launch_chunk_tables(const int32_t* seg, int64_t n, int64_t nseg, const ChunkTabs& t,
+                               const float* xs, float* balls, float* sballs, void* scan_temp,
+                               hipStream_t s);
 
 // Many instances in one point set (spatial.hip).
 struct InstDev {

@@ -95,14 +95,20 @@ __global__ __launch_bounds__(256) void k_segment_ids(const int32_t* __restrict__
 // (DMAX floats a row, zero beyond the data's features): centre = FP64 mean
 // rounded to FP32, radius = FP64 max distance to that centre, rounded up.
 // Eight lanes per row, one float4 each, so every read is a whole row.
+// Ball of the sorted positions [c0, c1) of block b: fixed blocks of bn
+// positions, or (starts != NULL) [starts[b], starts[b + 1]) for the first
+// *count blocks (blocks past the count return at once).
 __global__ __launch_bounds__(256) void k_chunk_balls(const float* __restrict__ xs, int64_t n, int bn,
+                                                     const int32_t* __restrict__ starts,
+                                                     const int32_t* __restrict__ count,
                                                      float* __restrict__ balls)
 {
     __shared__ double acc[4][DMAX];
     __shared__ alignas(16) float cen[DMAX];
     __shared__ double rmax[4];
-    const int64_t c0 = (int64_t)blockIdx.x * bn;
-    const int64_t c1 = c0 + bn < n ? c0 + bn : n;
+    if (starts && (int)blockIdx.x >= *count) return;
+    const int64_t c0 = starts ? (int64_t)starts[blockIdx.x] : (int64_t)blockIdx.x * bn;
+    const int64_t c1 = starts ? (int64_t)starts[blockIdx.x + 1] : (c0 + bn < n ? c0 + bn : n);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int q = threadIdx.x & 7;               // float4 of the row
     const int r = threadIdx.x >> 3;              // row of a pass of 32
@@ -423,7 +429,103 @@ hipError_t launch_chunk_balls(const float* xs, int64_t n, int bn, float* balls, 
     static_assert(DMAX == 32, "eight float4 per padded row");
     const int64_t nc = (n + bn - 1) / bn;
     if (nc <= 0) return hipSuccess;
-    k_chunk_balls<<<(unsigned)nc, 256, 0, s>>>(xs, n, bn, balls);
+    k_chunk_balls<<<(unsigned)nc, 256, 0, s>>>(xs, n, bn, nullptr, nullptr, balls);
+    return hipGetLastError();
+}
+
+// ---- component-aligned column chunks --------------------------------------
+// In the merge rounds the sorted order holds each component as one segment.
+// A fixed chunk that straddles two segments has a bounding ball spanning two
+// components, far apart, which nearly every row's ball test passes; so once
+// components are large each segment [a, b) is cut on its own into chunks
+// starting at a, a + CHUNK, ... and its chunks into super-chunks of SUPER.
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_tab_segstart(const int32_t* __restrict__ seg, int64_t n,
+                                                      int32_t* __restrict__ segstart)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    if (p == 0 || seg[p] != seg[p - 1]) segstart[seg[p]] = (int32_t)p;
+    if (p == n - 1) segstart[seg[p] + 1] = (int32_t)n;
+}
+
+__global__ __launch_bounds__(256) void k_tab_counts(const int32_t* __restrict__ segstart, int64_t nseg,
+                                                    int32_t* __restrict__ ccnt, int32_t* __restrict__ scnt)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nseg) return;
+    const int len = segstart[g + 1] - segstart[g];
+    const int c = (len + CHUNK - 1) / CHUNK;
+    ccnt[g] = c;
+    scnt[g] = (c + SUPER - 1) / SUPER;
+}
+
+// One block per segment.
+__global__ __launch_bounds__(256) void k_tab_fill(const int32_t* __restrict__ segstart, int64_t nseg,
+                                                  int64_t n, const int32_t* __restrict__ ccnt,
+                                                  const int32_t* __restrict__ scnt,
+                                                  const int32_t* __restrict__ cbase,
+                                                  const int32_t* __restrict__ sbase,
+                                                  int32_t* __restrict__ cstart, int32_t* __restrict__ csup,
+                                                  int32_t* __restrict__ sfirst, int32_t* __restrict__ spos,
+                                                  int32_t* __restrict__ tabn)
+{
+    const int64_t g = blockIdx.x;
+    const int a = segstart[g];
+    const int cb = cbase[g], sb = sbase[g];
+    for (int c = threadIdx.x; c < ccnt[g]; c += 256) {
+        cstart[cb + c] = a + c * CHUNK;
+        csup[cb + c] = sb + c / SUPER;
+    }
+    for (int q = threadIdx.x; q < scnt[g]; q += 256) {
+        sfirst[sb + q] = cb + q * SUPER;
+        spos[sb + q] = a + q * SUPER * CHUNK;
+    }
+    if (g == nseg - 1 && threadIdx.x == 0) {
+        const int nch = cb + ccnt[g], nsc = sb + scnt[g];
+        cstart[nch] = (int32_t)n;
+        sfirst[nsc] = nch;
+        spos[nsc] = (int32_t)n;
+        tabn[0] = nch;
+        tabn[1] = nsc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tab_pos2chunk(const int32_t* __restrict__ seg, int64_t n,
+                                                       const int32_t* __restrict__ segstart,
+                                                       const int32_t* __restrict__ cbase,
+                                                       int32_t* __restrict__ pos2chunk)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int g = seg[p];
+    pos2chunk[p] = cbase[g] + (int)((p - segstart[g]) / CHUNK);
+}
+
+}  // namespace
+
+hipError_t launch_chunk_tables(const int32_t* seg, int64_t n, int64_t nseg, const ChunkTabs& t,
+                               const float* xs, float* balls, float* sballs, void* scan_temp,
+                               hipStream_t s)
+{
+    static_assert(DMAX == 32, "eight float4 per padded row");
+    if (n <= 0 || nseg <= 0) return hipSuccess;
+    k_tab_segstart<<<g256(n), 256, 0, s>>>(seg, n, t.segstart);
+    k_tab_counts<<<g256(nseg), 256, 0, s>>>(t.segstart, nseg, t.ccnt, t.scnt);
+    hipError_t e = launch_exclusive_scan(t.ccnt, t.cbase, nseg, scan_temp, nullptr, s);
+    if (e != hipSuccess) return e;
+    e = launch_exclusive_scan(t.scnt, t.sbase, nseg, scan_temp, nullptr, s);
+    if (e != hipSuccess) return e;
+    k_tab_fill<<<(unsigned)nseg, 256, 0, s>>>(t.segstart, nseg, n, t.ccnt, t.scnt, t.cbase, t.sbase,
+                                              t.cstart, t.csup, t.sfirst, t.spos, t.tabn);
+    k_tab_pos2chunk<<<g256(n), 256, 0, s>>>(seg, n, t.segstart, t.cbase, t.pos2chunk);
+    // at most n / CHUNK + nseg chunks and n / (CHUNK SUPER) + nseg super-chunks
+    const int64_t mc = (n + CHUNK - 1) / CHUNK + nseg;
+    const int64_t ms = (n + CHUNK * SUPER - 1) / (CHUNK * SUPER) + nseg;
+    k_chunk_balls<<<(unsigned)mc, 256, 0, s>>>(xs, n, CHUNK, t.cstart, t.tabn, balls);
+    k_chunk_balls<<<(unsigned)ms, 256, 0, s>>>(xs, n, CHUNK, t.spos, t.tabn + 1, sballs);
     return hipGetLastError();
 }
 

@@ -162,15 +162,35 @@ def test_near_ties_below_half_precision(nnm):
         _tree_equal(nnm, X, precision=prec)
 
 
-@pytest.mark.parametrize("knob", ["k1", "k32", "cap64", "fallback", "noprune", "splits4"])
+@pytest.mark.parametrize("knob", ["k1", "k32", "cap64", "fallback", "noprune", "splits4",
+                                  "fixed_chunks"])
 def test_forced_paths_give_identical_trees(nnm, knob):
     X, _ = W.mixture64(1, n=3000, d=12)
     kw = {"k1": dict(knn_k=1), "k32": dict(knn_k=32), "cap64": dict(survivor_cap=64),
           "fallback": dict(force_fallback=True), "noprune": dict(disable_prune=True),
-          "splits4": dict(col_splits=4)}[knob]
+          "splits4": dict(col_splits=4), "fixed_chunks": dict(fixed_chunks=True)}[knob]
     _say("forced path", knob, X.shape)
     for prec in ("fp16", "fp32"):
         _tree_equal(nnm, X, precision=prec, **kw)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16", "fp32"])
+def test_component_aligned_chunks_ragged_segments(nnm, prec):
+    """Few large components of sizes that are no multiple of the chunk (and
+    some far below it): the merge rounds cut column chunks along the
+    components; the tree must equal the oracle's and the fixed-chunk run's."""
+    rng = np.random.default_rng(77)
+    sizes = [37, 300, 1023, 4097, 2500, 9000, 13, 700, 256, 257, 3]
+    d = 10
+    centres = rng.uniform(0, 40, size=(len(sizes), d))
+    X = np.concatenate([c + rng.standard_normal((m, d)) * rng.uniform(0.2, 1.5)
+                        for c, m in zip(centres, sizes)])
+    X = X[rng.permutation(X.shape[0])].astype(np.float32)
+    _say("aligned chunks, ragged components", prec, X.shape)
+    tree, _ = _tree_equal(nnm, X, precision=prec)
+    fixed = nnm.mst_build(_dev(X), precision=prec, fixed_chunks=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(tree.host_bytes(), fixed.host_bytes())
 
 
 def test_overflow_twice_goes_to_exact_scan(nnm):
