@@ -360,204 +360,6 @@ __device__ inline void sweep_chunks(TileShared& sh, const CandArgs& a, int lo_r,
     }
 }
 
-// Nearest-first iterator over the chunks of this workgroup's column range:
-// super-chunks in zigzag order around the tile's own, then the chunks of
-// each super-chunk in zigzag order.  A candidate is skipped when it lies
-// entirely inside the tile's only component, or when the tile ball is
-// farther from its ball than the bound umax.  Super-chunks are tested one
-// per lane, 64 at a time; the SUPER chunks of a super-chunk are tested
-// together on entry, four lanes per chunk (a quarter of the features each).
-// Outcomes are kept until used up (a larger, older umax only keeps more).
-// The chunk data of the next passing super-chunk is loaded on entry to the
-// current one, so that the memory latency hides behind its chunks.  Every
-// wave evaluates the same candidates, so all threads of the workgroup step
-// in lockstep when they call next() with the same umax.
-static_assert(SUPER == 16 && DMAX == 32, "chunk tests: 16 steps x 4 lanes x 8 features");
-template <bool TAB>
-struct ChunkIter {
-    int ch_lo, ch_hi, start;         // chunk range of this split; the tile's own chunk
-    int sc_lo, sc_hi, sc_start;      // super-chunk range; the tile's own super-chunk
-    int ss;                          // next super-chunk step
-    int sbase;                       // super-chunk steps [sbase, sbase + 64) tested
-    unsigned long long smask;
-    int c_lo, c_hi, cstart, cs;      // current super-chunk's chunks; next step
-    unsigned cmask;                  // its passing steps
-    int my_lo, my_hi;                // lanes 0..SUPER-1: component range of that step's chunk
-    int my_b0, my_b1;                // TAB: and its sorted positions [b0, b1)
-    bool in_super;
-    // chunk data of super-chunk psc (-1: none): lane step + 16 part holds
-    // centre features [8 part, 8 part + 8), the radius and the component
-    // range of the chunk at that step
-    int psc;
-    float4 pc0, pc1;
-    float prad;
-    int plo, phi;
-    int pb0, pb1;
-
-    __device__ void init(const TileShared& sh, const CandArgs& a)
-    {
-        const int first_ch = chunk_first_of<TAB>(a, sh.col_lo);
-        const int nch = chunk_end_of<TAB>(a, sh.col_hi) - first_ch;
-        const int cps = (nch + a.col_splits - 1) / a.col_splits;
-        ch_lo = first_ch + (int)blockIdx.y * cps;
-        ch_hi = ch_lo + cps < first_ch + nch ? ch_lo + cps : first_ch + nch;
-        if (ch_lo < ch_hi) {
-            start = chunk_at<TAB>(a, sh.first_pos);
-            start = start < ch_lo ? ch_lo : (start >= ch_hi ? ch_hi - 1 : start);
-            sc_lo = super_of<TAB>(a, ch_lo);
-            sc_hi = super_of<TAB>(a, ch_hi - 1) + 1;
-            sc_start = super_of<TAB>(a, start);
-        } else {
-            start = ch_lo;
-            sc_lo = sc_hi = sc_start = 0;   // nothing to visit
-        }
-        ss = 0;
-        sbase = -64;
-        smask = 0ull;
-        cmask = 0u;
-        in_super = false;
-        my_lo = my_hi = 0;
-        my_b0 = my_b1 = 0;
-        psc = -1;
-    }
-
-    // chunks [lo, hi) of super-chunk sc within this split, and its first one
-    __device__ void super_range(const CandArgs& a, int sc, int* lo, int* hi, int* first) const
-    {
-        const int sf = super_first<TAB>(a, sc), se = super_end<TAB>(a, sc);
-        *lo = sf > ch_lo ? sf : ch_lo;
-        *hi = se < ch_hi ? se : ch_hi;
-        *first = (sc == sc_start) ? start : (sc > sc_start ? *lo : *hi - 1);
-    }
-
-    // issue the loads of super-chunk sc's chunk data (nothing waits here)
-    __device__ void load_super(const CandArgs& a, int sc)
-    {
-        const int lane = threadIdx.x & 63, step = lane & 15, part = lane >> 4;
-        int lo, hi, first;
-        super_range(a, sc, &lo, &hi, &first);
-        // steps past the end load the first chunk again; their test is off
-        const int ci = zigzag(step < hi - lo ? step : 0, first, lo, hi);
-        const int64_t c0 = chunk_begin<TAB>(a, ci);
-        const int64_t c1 = chunk_end<TAB>(a, ci) - 1;
-        plo = a.compS[c0];
-        phi = a.compS[c1];
-        if constexpr (TAB) {
-            pb0 = (int)c0;
-            pb1 = (int)c1 + 1;
-        }
-        const float* b = a.balls + (int64_t)ci * BALL_STRIDE;
-        pc0 = *reinterpret_cast<const float4*>(b + 8 * part);
-        pc1 = *reinterpret_cast<const float4*>(b + 8 * part + 4);
-        prad = b[DMAX];
-        psc = sc;
-    }
-
-    // chunk tests of the loaded super-chunk (nc chunks) into cmask; the
-    // quarter sums of squares are added across the four lanes of a chunk
-    // (at most 12 roundings in all, within the margins of ball_lb2)
-    __device__ void test_super(const TileShared& sh, const CandArgs& a, int lo_r, int hi_r,
-                               float umax, int nc)
-    {
-        const int lane = threadIdx.x & 63, step = lane & 15, part = lane >> 4;
-        const float4* c4 = reinterpret_cast<const float4*>(sh.cen) + 2 * part;
-        const float4 t0 = c4[0], t1 = c4[1];
-        float s = 0.f;
-        {
-            const float d0 = t0.x - pc0.x, d1 = t0.y - pc0.y, d2 = t0.z - pc0.z, d3 = t0.w - pc0.w;
-            const float e0 = t1.x - pc1.x, e1 = t1.y - pc1.y, e2 = t1.z - pc1.z, e3 = t1.w - pc1.w;
-            s = __builtin_fmaf(d0, d0, s);
-            s = __builtin_fmaf(d1, d1, s);
-            s = __builtin_fmaf(d2, d2, s);
-            s = __builtin_fmaf(d3, d3, s);
-            s = __builtin_fmaf(e0, e0, s);
-            s = __builtin_fmaf(e1, e1, s);
-            s = __builtin_fmaf(e2, e2, s);
-            s = __builtin_fmaf(e3, e3, s);
-        }
-        s += __shfl_xor(s, 16);
-        s += __shfl_xor(s, 32);
-        const float lb = __builtin_sqrtf(s) * (1.0f - 0x1p-18f) - sh.rball - prad;
-        const float lb2 = lb > 0.f ? lb * lb * (1.0f - 0x1p-20f) : 0.f;
-        const bool pass = part == 0 && step < nc && !(lo_r == hi_r && plo == phi && lo_r == plo) &&
-                          (!a.prune || lb2 <= umax);
-        cmask = (unsigned)__ballot(pass);
-        my_lo = plo;
-        my_hi = phi;
-        if constexpr (TAB) {
-            my_b0 = pb0;
-            my_b1 = pb1;
-        }
-    }
-
-    // Next chunk to process, or -1; *lo_c / *hi_c receive its component range
-    // and [*b0, *b1) its sorted positions (read with the chunk's test data,
-    // so fetching the chunk waits on no further load).
-    __device__ int next(const TileShared& sh, const CandArgs& a, int lo_r, int hi_r, float umax,
-                        int* lo_c, int* hi_c, int* b0, int* b1)
-    {
-        const int lane = threadIdx.x & 63;
-        for (;;) {
-            if (in_super) {
-                const unsigned m = cmask >> cs;
-                if (m != 0u) {
-                    const int off = cs + (int)__builtin_ctz(m);
-                    cs = off + 1;
-                    // off is wave-uniform: a lane read, not an LDS permute
-                    *lo_c = __builtin_amdgcn_readlane(my_lo, off);
-                    *hi_c = __builtin_amdgcn_readlane(my_hi, off);
-                    const int ci = zigzag(off, cstart, c_lo, c_hi);
-                    if constexpr (TAB) {
-                        *b0 = __builtin_amdgcn_readlane(my_b0, off);
-                        *b1 = __builtin_amdgcn_readlane(my_b1, off);
-                    } else {
-                        *b0 = ci * CHUNK;
-                        *b1 = *b0 + CHUNK < a.np ? *b0 + CHUNK : a.np;
-                    }
-                    return ci;
-                }
-                in_super = false;
-            }
-            const int nsc = sc_hi - sc_lo;
-            if (ss >= nsc) return -1;
-            if (ss >= sbase + 64) {
-                sbase = ss;
-                const int step = ss + lane;
-                bool pass = false;
-                if (step < nsc) {
-                    const int sc = zigzag(step, sc_start, sc_lo, sc_hi);
-                    // a super-chunk entirely inside the tile's only component
-                    const int64_t s0 = chunk_begin<TAB>(a, super_first<TAB>(a, sc));
-                    const int64_t s1 = chunk_end<TAB>(a, super_end<TAB>(a, sc) - 1) - 1;
-                    const float lb = a.prune ? ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE) : 0.f;
-                    pass = !(lo_r == hi_r && a.compS[s0] == lo_r && a.compS[s1] == lo_r) && lb <= umax;
-                }
-                smask = __ballot(pass);
-            }
-            const unsigned long long m = smask >> (ss - sbase);
-            if (m == 0ull) {
-                ss = sbase + 64;
-                continue;
-            }
-            const int off = ss - sbase + (int)__builtin_ctzll(m);
-            ss = sbase + off + 1;
-            const int sc = zigzag(sbase + off, sc_start, sc_lo, sc_hi);
-            super_range(a, sc, &c_lo, &c_hi, &cstart);
-            if (psc != sc) load_super(a, sc);          // not loaded ahead: wait for it here
-            test_super(sh, a, lo_r, hi_r, umax, c_hi - c_lo);
-            cs = 0;
-            in_super = true;
-            // the next passing super-chunk of the tested window, loaded ahead
-            psc = -1;
-            if (ss - sbase < 64) {
-                const unsigned long long m2 = smask >> (ss - sbase);
-                if (m2 != 0ull)
-                    load_super(a, zigzag(ss + (int)__builtin_ctzll(m2), sc_start, sc_lo, sc_hi));
-            }
-        }
-    }
-};
-
 // Max over the 64 rows of the calling wave of v (one value per lane), stored
 // in sh.wmax[wave].
 __device__ __forceinline__ void wave_max_store(TileShared& sh, float v)

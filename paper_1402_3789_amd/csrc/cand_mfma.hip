@@ -31,9 +31,12 @@
 // applies the component mask.
 //
 // Search order and pruning.  Points are stored in a spatial order, so the
-// chunks are visited nearest-first starting at the tile's own position, and
-// a chunk is skipped when the distance between the tile's bounding ball and
-// the chunk's bounding ball already exceeds every row's U_i.
+// chunks are visited nearest-first starting at the tile's own position, a
+// group of candidate chunks at a time: a chunk is a candidate unless the
+// distance between the tile's bounding ball and the chunk's already exceeds
+// every row's U_i; each row then tests its own distance to every
+// candidate's ball against its U_i, and only the chunks some wave's rows
+// need are staged and evaluated -- by the waves that need them.
 //
 // MFMA layouts used (16x16x32): lane l supplies A[m = l%16][k-slice l/16]
 // and B[k-slice l/16][n = l%16]; result register r of lane l is
@@ -106,6 +109,143 @@ __device__ __forceinline__ float pick32(const f32x4_t (&a0)[RB], const f32x4_t (
     const float hi = (e & 1) ? w[3] : w[2];
     return (e & 2) ? hi : lo;
 }
+
+// Candidate chunks of the sweep, a group at a time.  The super-chunks of the
+// workgroup's column range are visited nearest-first (zigzag around the
+// tile's own) and tested 64 at a time against the tile ball, one lane each;
+// a group takes the next GS passing super-chunks and wave w expands the
+// w-th: its (at most SUPER) chunks are tested against the tile ball, four
+// lanes per chunk (a quarter of the features each), all loads of the group
+// issued together.  Each chunk's ball, position range and component range
+// go to candidate slot SUPER w + step in LDS, flagged (bit 4 of gneed) when
+// the chunk passed.  Every wave runs the super-chunk part identically, so
+// all take the same decisions.
+constexpr int GS = 4;                 // super-chunks per group (one per wave)
+constexpr int GW = GS * SUPER;        // candidate slots per group
+static_assert(GW == 64 && DMAX == 32, "one lane per slot; 4 lanes x 8 features per chunk");
+
+template <bool TAB>
+struct GroupGen {
+    int ch_lo, ch_hi, start;         // chunk range of this split; the tile's own chunk
+    int sc_lo, sc_hi, sc_start;      // super-chunk range; the tile's own super-chunk
+    int ss;                          // next super-chunk step
+    int sbase;                       // steps [sbase, sbase + 64) tested into smask
+    unsigned long long smask;
+
+    __device__ void init(const TileShared& sh, const CandArgs& a)
+    {
+        const int first_ch = chunk_first_of<TAB>(a, sh.col_lo);
+        const int nch = chunk_end_of<TAB>(a, sh.col_hi) - first_ch;
+        const int cps = (nch + a.col_splits - 1) / a.col_splits;
+        ch_lo = first_ch + (int)blockIdx.y * cps;
+        ch_hi = ch_lo + cps < first_ch + nch ? ch_lo + cps : first_ch + nch;
+        if (ch_lo < ch_hi) {
+            start = chunk_at<TAB>(a, sh.first_pos);
+            start = start < ch_lo ? ch_lo : (start >= ch_hi ? ch_hi - 1 : start);
+            sc_lo = super_of<TAB>(a, ch_lo);
+            sc_hi = super_of<TAB>(a, ch_hi - 1) + 1;
+            sc_start = super_of<TAB>(a, start);
+        } else {
+            start = ch_lo;
+            sc_lo = sc_hi = sc_start = 0;    // nothing to visit
+        }
+        ss = 0;
+        sbase = -64;
+        smask = 0ull;
+    }
+
+    // The next (at most GS) super-chunks that pass the tile-level test
+    // against the bound umax, into scl; returns how many.
+    __device__ int take(const TileShared& sh, const CandArgs& a, int lo_r, int hi_r, float umax,
+                        int (&scl)[GS])
+    {
+        const int lane = threadIdx.x & 63;
+        const int nsc = sc_hi - sc_lo;
+        int g = 0;
+        while (g < GS && ss < nsc) {
+            if (ss >= sbase + 64) {
+                sbase = ss;
+                const int step = ss + lane;
+                bool pass = false;
+                if (step < nsc) {
+                    const int sc = zigzag(step, sc_start, sc_lo, sc_hi);
+                    // a super-chunk entirely inside the tile's only component
+                    const int64_t s0 = chunk_begin<TAB>(a, super_first<TAB>(a, sc));
+                    const int64_t s1 = chunk_end<TAB>(a, super_end<TAB>(a, sc) - 1) - 1;
+                    const float lb = a.prune ? ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE) : 0.f;
+                    pass = !(lo_r == hi_r && a.compS[s0] == lo_r && a.compS[s1] == lo_r) && lb <= umax;
+                }
+                smask = __ballot(pass);
+            }
+            const unsigned long long m = smask >> (ss - sbase);
+            if (m == 0ull) {
+                ss = sbase + 64;
+                continue;
+            }
+            const int off = ss - sbase + (int)__builtin_ctzll(m);
+            scl[g++] = zigzag(sbase + off, sc_start, sc_lo, sc_hi);
+            ss = sbase + off + 1;
+        }
+        return g;
+    }
+
+    // Wave w expands super-chunk sc (-1: none) into slots [SUPER w, SUPER w + SUPER).
+    __device__ void expand(const TileShared& sh, const CandArgs& a, int lo_r, int hi_r, float umax,
+                           int sc, int w, float (*gball)[BALL_STRIDE], int4* gpos, int32_t* gneed)
+    {
+        const int lane = threadIdx.x & 63, step = lane & 15, part = lane >> 4;
+        const int slot = SUPER * w + step;
+        if (sc < 0) {
+            if (part == 0) gneed[slot] = 0;
+            return;
+        }
+        const int sf = super_first<TAB>(a, sc), se = super_end<TAB>(a, sc);
+        const int lo = sf > ch_lo ? sf : ch_lo;
+        const int hi = se < ch_hi ? se : ch_hi;
+        const int first = (sc == sc_start) ? start : (sc > sc_start ? lo : hi - 1);
+        const int nc = hi - lo;
+        // steps past the end read the first chunk again; they are not candidates
+        const int ci = zigzag(step < nc ? step : 0, first, lo, hi);
+        const int64_t c0 = chunk_begin<TAB>(a, ci);
+        const int64_t c1 = chunk_end<TAB>(a, ci);
+        const int clo = a.compS[c0], chi = a.compS[c1 - 1];
+        const float* b = a.balls + (int64_t)ci * BALL_STRIDE;
+        const float4 q0 = *reinterpret_cast<const float4*>(b + 8 * part);
+        const float4 q1 = *reinterpret_cast<const float4*>(b + 8 * part + 4);
+        const float rad = b[DMAX];
+        // tile ball vs chunk ball: quarter sums of squares added across the
+        // four lanes of a chunk (at most 12 roundings, within ball_lb2's margins)
+        const float4* c4 = reinterpret_cast<const float4*>(sh.cen) + 2 * part;
+        const float4 t0 = c4[0], t1 = c4[1];
+        float s = 0.f;
+        {
+            const float d0 = t0.x - q0.x, d1 = t0.y - q0.y, d2 = t0.z - q0.z, d3 = t0.w - q0.w;
+            const float e0 = t1.x - q1.x, e1 = t1.y - q1.y, e2 = t1.z - q1.z, e3 = t1.w - q1.w;
+            s = __builtin_fmaf(d0, d0, s);
+            s = __builtin_fmaf(d1, d1, s);
+            s = __builtin_fmaf(d2, d2, s);
+            s = __builtin_fmaf(d3, d3, s);
+            s = __builtin_fmaf(e0, e0, s);
+            s = __builtin_fmaf(e1, e1, s);
+            s = __builtin_fmaf(e2, e2, s);
+            s = __builtin_fmaf(e3, e3, s);
+        }
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        const float lb = __builtin_sqrtf(s) * (1.0f - 0x1p-18f) - sh.rball - rad;
+        const float lb2 = lb > 0.f ? lb * lb * (1.0f - 0x1p-20f) : 0.f;
+        const bool pass = step < nc && !(lo_r == hi_r && clo == chi && lo_r == clo) &&
+                          (!a.prune || lb2 <= umax);
+        float4* gb = reinterpret_cast<float4*>(&gball[slot][8 * part]);
+        gb[0] = q0;
+        gb[1] = q1;
+        if (part == 0) {
+            gball[slot][DMAX] = rad;
+            gpos[slot] = make_int4((int)c0, (int)c1, clo, chi);
+            gneed[slot] = pass ? 16 : 0;
+        }
+    }
+};
 
 // Operand format helpers for the local frame (BF16 / FP16).
 template <int OP> struct LpFmt;
@@ -205,12 +345,18 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     typedef typename Tr::frag_t frag_t;
     constexpr int PF = Tr::BYTES / 16;                     // uint4s of one column's operand
 
-    __shared__ frag_t colbuf[2][BN / 16 * 4 * 16];         // two chunks: one in use, one filling
+    __shared__ __align__(16) frag_t colbuf[2][BN / 16 * 4 * 16];  // two chunks: one in use, one filling
     __shared__ __align__(16) int32_t colcomp[2][BN];
     __shared__ float cmax[2][4][4];                        // LOCAL: per-wave column maxima
-    __shared__ __align__(16) float ballbuf[2][BALL_STRIDE];  // the chunk's bounding ball
     __shared__ float4 rs[BM][2];                           // per-row state, see above
-    __shared__ float wmx[2][4];                            // per-wave max of U, double-buffered
+    __shared__ float wmx[4];                               // per-wave max of U
+    // the current group of candidate chunks (see GroupGen); their balls are
+    // only read before the group's first chunk is staged, so they share
+    // the chunk buffers' memory
+    static_assert(sizeof(colbuf) >= GW * BALL_STRIDE * sizeof(float), "balls fit the chunk buffers");
+    float (*gball)[BALL_STRIDE] = reinterpret_cast<float (*)[BALL_STRIDE]>(&colbuf[0][0]);
+    __shared__ int4 gpos[GW];                              // [b0, b1), component range
+    __shared__ int32_t gneed[GW];                          // bit w: wave w needs it; bit 4: candidate
     __shared__ TileShared sh;
     extern __shared__ float4 topk4[];                      // [BM][KP / 4]
     float* topk = reinterpret_cast<float*>(topk4);
@@ -245,7 +391,6 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     float4 xq[NQR];                                        // kept for the per-row ball tests
 #pragma unroll
     for (int q = 0; q < NQR; ++q) xq[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
-    float reach = __builtin_huge_valf(), reachU = __builtin_huge_valf();   // sqrt bound of U
     float* my_tk = topk + tid * KP;
     for (int e = 0; e < KP; ++e) my_tk[e] = __builtin_huge_valf();
     float U = 0.f;
@@ -313,24 +458,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         sh.col_lo = tile.z;
         sh.col_hi = tile.w;
     }
-    // Max of rowU over the calling wave into wmx[b].  Sweep step i reads
-    // wmx[i & 1] after its barrier and writes wmx[(i + 1) & 1] at its end, so
-    // every wave reads the same values and takes the same chunk sequence.
-    // The maximum is recomputed only after the wave's bounds may have moved
-    // (slow path, split sharing); otherwise the cached value is written.
-    float wm = 0.f;
-    bool wdirty = true;
-    auto wave_max = [&](int b) {
-        if (wdirty) {
-            float v = my_valid ? rs[tid][0].y : 0.f;
-            for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-            wm = v;
-            wdirty = false;
-        }
-        if (lane == 0) wmx[b][wave] = wm;
-    };
-    wave_max(0);
-    __syncthreads();
+    __syncthreads();                                       // the row stage in colbuf is written
     // row fragments stay in registers for the whole sweep
     frag_t bfrag[RB];
     int32_t rcomp[RB];
@@ -353,7 +481,6 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     const int lo_r = sh.lo, hi_r = sh.hi;
     const bool one_comp = lo_r == hi_r;
     const int cl = sh.col_lo, ch = sh.col_hi;
-    float umax = fmaxf(fmaxf(wmx[0][0], wmx[0][1]), fmaxf(wmx[0][2], wmx[0][3]));
     __syncthreads();                                       // the row stage in colbuf is consumed
 
     // ---- column sweep: nearest chunks first, the next one in flight ---------
@@ -362,14 +489,12 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     uint4 pf[LOCAL ? 1 : PF];
     float4 pfx[LOCAL ? NQR : 1];
     int pf_cc = -1;
-    float pf_ball = 0.f;
     // the bound the other column splits have found for this row, read with
     // each chunk's loads and used behind the next barrier (any older value is
     // still a valid bound)
     float pf_gU = __builtin_huge_valf();
-    auto fetch = [&](int ci, int64_t c0, int64_t cend) {
+    auto fetch = [&](int64_t c0, int64_t cend) {
         if (SHARE && my_valid) pf_gU = __uint_as_float(a.gU[my_slot]);
-        if (tid < BALL_STRIDE) pf_ball = a.balls[(int64_t)ci * BALL_STRIDE + tid];
         const bool in = c0 + tid < cend;
         if constexpr (LOCAL) {
             const float4* src = reinterpret_cast<const float4*>(a.xs + (c0 + (in ? tid : 0)) * DMAX);
@@ -390,7 +515,6 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         const bool col_ok = pf_cc >= 0 && c0 + tid >= cl && c0 + tid < ch &&
                             !(one_comp && pf_cc == lo_r);
         colcomp[b][tid] = col_ok ? pf_cc : -1;
-        if (tid < BALL_STRIDE) ballbuf[b][tid] = pf_ball;
         if constexpr (LOCAL) {
             float y[DMAX];
 #pragma unroll
@@ -450,22 +574,12 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         }
     };
 
-    auto process = [&](int b, int lo_c, int hi_c, int64_t c0, int64_t cend) {
+    // chunk [c0, cend) in LDS buffer b, components lo_c..hi_c; wneed: some
+    // row of this wave passed its test for the chunk (else nothing to do)
+    auto process = [&](int b, int lo_c, int hi_c, int64_t c0, int64_t cend, bool wneed) {
+        if (!wneed) return;
         const int ncols = (int)(cend - c0);
         const bool pure = lo_c == hi_c;                    // the chunk is one component
-        // per-row tests: a row skips a chunk made only of its own component,
-        // or whose ball lies farther than its bound; a wave whose rows all
-        // skip does no work on the chunk
-        bool need = my_valid && !(pure && lo_c == my_comp);
-        if (a.prune && need) {
-            const float Ucur = rs[tid][0].y;
-            if (Ucur != reachU) {                          // the root only when U moved
-                reachU = Ucur;
-                reach = reach_of(Ucur);
-            }
-            need = point_ball_reach(xq, &ballbuf[b][0], reach);
-        }
-        if (!__ballot(need)) return;
         // per-tile frame: this chunk's slack and threshold for the row (the
         // wave's rows are read back by other lanes of the same wave only).
         // In the global frame the slack is fixed and T follows U wherever U
@@ -511,7 +625,6 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         // touched by two lanes at once, and lanes of different rows proceed
         // together.
         auto slow = [&](int cb, const f32x4_t (&acc0)[RB], const f32x4_t (&acc1)[RB], bool two) {
-            wdirty = true;
             uint32_t hm = 0;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
@@ -668,41 +781,76 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         }
     };
 
-    ChunkIter<TAB> itr;
-    itr.init(sh, a);
-    int cur_lo = 0, cur_hi = 0, cur_b0 = 0, cur_b1 = 0;
-    int cur = itr.next(sh, a, lo_r, hi_r, umax, &cur_lo, &cur_hi, &cur_b0, &cur_b1);
-    if (cur >= 0) fetch(cur, cur_b0, cur_b1);
+    // Groups of candidate chunks, nearest super-chunks first.  Per group:
+    // the tile's bound umax (max over its rows' U), the candidates of up to
+    // GS passing super-chunks (tile-level tests), each row's test against
+    // every candidate (bits per wave), then the chunks some wave needs, in
+    // order, with the next one in flight.
+    GroupGen<TAB> gen;
+    gen.init(sh, a);
+    float reach = __builtin_huge_valf(), reachU = __builtin_huge_valf();   // sqrt bound of U
     int buf = 0;
-    while (cur >= 0) {
-        stash(cur_b0, buf);
-        __syncthreads();        // chunk cur in LDS; every wave is done with buf ^ 1's last use
-        umax = fmaxf(fmaxf(wmx[buf][0], wmx[buf][1]), fmaxf(wmx[buf][2], wmx[buf][3]));
-        // bounds found by the other column splits of the row (loaded with the
-        // chunk now in LDS, so nothing waits here)
-        if (SHARE) {
-            if (my_valid) {
-                const float g = pf_gU;
-                if (g < rs[tid][0].y) {
-                    rs[tid][0].y = g;
+    for (;;) {
+        float um = my_valid ? rs[tid][0].y : 0.f;
+        for (int off = 32; off > 0; off >>= 1) um = fmaxf(um, __shfl_xor(um, off));
+        if (lane == 0) wmx[wave] = um;
+        __syncthreads();                                   // every wave done with the last group
+        const float umax = fmaxf(fmaxf(wmx[0], wmx[1]), fmaxf(wmx[2], wmx[3]));
+        int scl[GS];
+        const int g = gen.take(sh, a, lo_r, hi_r, umax, scl);
+        if (g == 0) break;                                 // the same decision in every wave
+        gen.expand(sh, a, lo_r, hi_r, umax, wave < g ? scl[wave < GS ? wave : 0] : -1, wave, gball, gpos,
+                   gneed);
+        __syncthreads();                                   // candidates in LDS
+        const unsigned long long vmask = __ballot((gneed[lane] & 16) != 0);
+        if (a.prune) {
+            const float Ucur = rs[tid][0].y;
+            if (Ucur != reachU) {                          // the root only when U moved
+                reachU = Ucur;
+                reach = reach_of(Ucur);
+            }
+        }
+        for (unsigned long long m = vmask; m != 0ull; m &= m - 1ull) {
+            const int slot = (int)__builtin_ctzll(m);
+            const int4 gp = gpos[slot];
+            // a row skips a chunk made only of its own component, or whose
+            // ball lies farther than its bound
+            bool need = my_valid && !(gp.z == gp.w && gp.z == my_comp);
+            if (a.prune && need) need = point_ball_reach(xq, &gball[slot][0], reach);
+            if (__ballot(need) != 0ull && lane == 0) atomicOr(&gneed[slot], 1 << wave);
+        }
+        __syncthreads();                                   // every wave's needs in LDS
+        const int gn = gneed[lane];
+        unsigned long long nmask = __ballot((gn & 15) != 0);
+        int cur = nmask ? (int)__builtin_ctzll(nmask) : -1;
+        if (cur >= 0) {
+            nmask &= nmask - 1ull;
+            fetch(gpos[cur].x, gpos[cur].y);
+        }
+        while (cur >= 0) {
+            const int4 cp = gpos[cur];
+            const bool wn = ((__builtin_amdgcn_readlane(gn, cur) >> wave) & 1) != 0;
+            stash(cp.x, buf);
+            __syncthreads();    // chunk cur in LDS; every wave is done with buf ^ 1's last use
+            // bounds found by the other column splits of the row (loaded with
+            // the chunk now in LDS, so nothing waits here)
+            if (SHARE && my_valid) {
+                const float gu = pf_gU;
+                if (gu < rs[tid][0].y) {
+                    rs[tid][0].y = gu;
                     if (!LOCAL)
-                        rs[tid][0].x = fminf(rs[tid][0].x, thresh_from_U(g * s2, rs[tid][0].z, rs[tid][0].w, exact));
+                        rs[tid][0].x = fminf(rs[tid][0].x, thresh_from_U(gu * s2, rs[tid][0].z, rs[tid][0].w, exact));
                 }
             }
-            wdirty = true;
+            const int nxt = nmask ? (int)__builtin_ctzll(nmask) : -1;
+            if (nxt >= 0) {
+                nmask &= nmask - 1ull;
+                fetch(gpos[nxt].x, gpos[nxt].y);           // in flight while cur is processed
+            }
+            process(buf, cp.z, cp.w, cp.x, cp.y, wn);
+            cur = nxt;
+            buf ^= 1;
         }
-        int nlo = 0, nhi = 0, nb0 = 0, nb1 = 0;
-        const int nxt = itr.next(sh, a, lo_r, hi_r, umax, &nlo, &nhi, &nb0, &nb1);
-        if (nxt >= 0) fetch(nxt, nb0, nb1);            // in flight while cur is processed
-        process(buf, cur_lo, cur_hi, cur_b0, cur_b1);
-        // this wave's bound for the pruning tests of later chunks
-        wave_max(buf ^ 1);
-        cur = nxt;
-        cur_lo = nlo;
-        cur_hi = nhi;
-        cur_b0 = nb0;
-        cur_b1 = nb1;
-        buf ^= 1;
     }
     if (!SHARE && my_valid) a.surv_cnt[my_slot] = __float_as_int(rs[tid][1].x);
     // the row's final threshold (one frame for every pair): a survivor above
