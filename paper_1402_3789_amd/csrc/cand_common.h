@@ -98,6 +98,64 @@ __device__ inline void tile_ball(TileShared& sh, const float (&x)[DM], bool vali
     __syncthreads();
 }
 
+// Bounding ball of the calling wave's rows (lane l owns row l; valid = the
+// row exists; x its first d features): centre (FP32, from an FP64 mean) into
+// wc[DMAX], zero beyond the data's features, and radius (FP64 max, rounded
+// up) into *wr.  Wave-local: no workgroup barrier.
+template <int DM>
+__device__ inline void wave_ball(float* wc, float* wr, const float (&x)[DM], bool valid, int d)
+{
+    const int lane = threadIdx.x & 63;
+    const double cnt = (double)__popcll(__ballot(valid));
+#pragma unroll
+    for (int f = 0; f < DMAX; ++f) {
+        double v = (f < DM && f < d && valid) ? (double)x[f < DM ? f : 0] : 0.0;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) wc[f] = (f < d) ? (float)(v / (cnt > 0.0 ? cnt : 1.0)) : 0.f;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double r2 = 0.0;
+    if (valid) {
+#pragma unroll
+        for (int f = 0; f < DM; ++f) {
+            if (f < d) {
+                const double df = (double)x[f] - (double)wc[f];
+                r2 += df * df;
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(r2, off);
+        r2 = o > r2 ? o : r2;
+    }
+    if (lane == 0) *wr = d2f_up(__builtin_sqrt(r2) * (1.0 + 0x1p-40));
+}
+
+// Lower bound, rounded down, on the squared distance of any pair across the
+// ball (centre cen[DMAX], radius rad) and the ball `ball` (BALL_STRIDE
+// floats, 16-byte aligned); the margins are those of ball_lb2 below.
+__device__ inline float balls_lb2(const float* cen, float rad, const float* ball)
+{
+    const float4* b4 = reinterpret_cast<const float4*>(ball);
+    const float4* c4 = reinterpret_cast<const float4*>(cen);
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < DMAX / 4; ++q) {
+        const float4 c = c4[q], bv = b4[q];
+        const float d0 = c.x - bv.x, d1 = c.y - bv.y;
+        const float d2 = c.z - bv.z, d3 = c.w - bv.w;
+        s = __builtin_fmaf(d0, d0, s);
+        s = __builtin_fmaf(d1, d1, s);
+        s = __builtin_fmaf(d2, d2, s);
+        s = __builtin_fmaf(d3, d3, s);
+    }
+    const float lb = __builtin_sqrtf(s) * (1.0f - 0x1p-18f) - rad - ball[DMAX];
+    if (!(lb > 0.f)) return 0.f;
+    return lb * lb * (1.0f - 0x1p-20f);
+}
+
 // Lower bound on the squared distance of any pair across the tile ball and
 // the ball `ball` (BALL_STRIDE floats, 16-byte aligned), rounded down.  Both
 // centres are zero beyond the data's features, so all DMAX features are

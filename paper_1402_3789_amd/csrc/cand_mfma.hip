@@ -170,10 +170,16 @@ struct GroupGen {
                 if (step < nsc) {
                     const int sc = zigzag(step, sc_start, sc_lo, sc_hi);
                     // a super-chunk entirely inside the tile's only component
-                    const int64_t s0 = chunk_begin<TAB>(a, super_first<TAB>(a, sc));
-                    const int64_t s1 = chunk_end<TAB>(a, super_end<TAB>(a, sc) - 1) - 1;
+                    bool own;
+                    if constexpr (TAB) {
+                        own = lo_r == hi_r && a.scomp[sc] == lo_r;
+                    } else {
+                        const int64_t s0 = (int64_t)sc * SUPER * CHUNK;
+                        const int64_t s1 = chunk_end<TAB>(a, super_end<TAB>(a, sc) - 1) - 1;
+                        own = lo_r == hi_r && a.compS[s0] == lo_r && a.compS[s1] == lo_r;
+                    }
                     const float lb = a.prune ? ball_lb2(sh, a.sballs + (int64_t)sc * BALL_STRIDE) : 0.f;
-                    pass = !(lo_r == hi_r && a.compS[s0] == lo_r && a.compS[s1] == lo_r) && lb <= umax;
+                    pass = !own && lb <= umax;
                 }
                 smask = __ballot(pass);
             }
@@ -208,7 +214,13 @@ struct GroupGen {
         const int ci = zigzag(step < nc ? step : 0, first, lo, hi);
         const int64_t c0 = chunk_begin<TAB>(a, ci);
         const int64_t c1 = chunk_end<TAB>(a, ci);
-        const int clo = a.compS[c0], chi = a.compS[c1 - 1];
+        int clo, chi;
+        if constexpr (TAB) {
+            clo = chi = a.ccomp[ci];    // one component per chunk; no wait on c0
+        } else {
+            clo = a.compS[c0];
+            chi = a.compS[c1 - 1];
+        }
         const float* b = a.balls + (int64_t)ci * BALL_STRIDE;
         const float4 q0 = *reinterpret_cast<const float4*>(b + 8 * part);
         const float4 q1 = *reinterpret_cast<const float4*>(b + 8 * part + 4);
@@ -350,11 +362,13 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     __shared__ float cmax[2][4][4];                        // LOCAL: per-wave column maxima
     __shared__ float4 rs[BM][2];                           // per-row state, see above
     __shared__ float wmx[4];                               // per-wave max of U
-    // the current group of candidate chunks (see GroupGen); their balls are
-    // only read before the group's first chunk is staged, so they share
-    // the chunk buffers' memory
-    static_assert(sizeof(colbuf) >= GW * BALL_STRIDE * sizeof(float), "balls fit the chunk buffers");
-    float (*gball)[BALL_STRIDE] = reinterpret_cast<float (*)[BALL_STRIDE]>(&colbuf[0][0]);
+    __shared__ __align__(16) float wcen[4][DMAX];          // per-wave ball of the rows
+    __shared__ float wrad[4];
+    // the current group of candidate chunks (see GroupGen).  The balls have
+    // their own LDS: placed over the chunk buffers (free while they are
+    // read) the k = 16 and k = 32 lists came out different from run to run,
+    // cause not found; apart, every run is identical.
+    __shared__ __align__(16) float gball[GW][BALL_STRIDE];
     __shared__ int4 gpos[GW];                              // [b0, b1), component range
     __shared__ int32_t gneed[GW];                          // bit w: wave w needs it; bit 4: candidate
     __shared__ TileShared sh;
@@ -432,6 +446,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     rs[tid][0] = make_float4(-__builtin_huge_valf(), U, 0.f, 0.f);
     rs[tid][1] = make_float4(__int_as_float(0), __int_as_float(my_comp), 0.f, 0.f);
     if (a.prune || LOCAL) tile_ball<DMAX>(sh, x, my_valid, a.d);
+    if (a.prune) wave_ball<DMAX>(&wcen[wave][0], &wrad[wave], x, my_valid, a.d);
     // row operand and its bound inputs
     PointConst mypc{0.f, 0.f, 0.f, 0.f};
     if constexpr (LOCAL) {
@@ -729,6 +744,9 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
             for (int rb = 0; rb < RB; ++rb) acc0[rb] = Tr::mma(af0, bfrag[rb]);
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc1[rb] = Tr::mma(af1, bfrag[rb]);
+            // all eight MFMAs issue back to back; the epilogue then finds the
+            // first results ready instead of stalling after each pair
+            __builtin_amdgcn_sched_barrier(0);
             bool hit = false;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
@@ -802,7 +820,11 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
         gen.expand(sh, a, lo_r, hi_r, umax, wave < g ? scl[wave < GS ? wave : 0] : -1, wave, gball, gpos,
                    gneed);
         __syncthreads();                                   // candidates in LDS
-        const unsigned long long vmask = __ballot((gneed[lane] & 16) != 0);
+        // candidates within reach of this wave's ball (one per lane), then
+        // the rows' own tests for those
+        bool wpass = (gneed[lane] & 16) != 0;
+        if (a.prune && wpass) wpass = balls_lb2(&wcen[wave][0], wrad[wave], &gball[lane][0]) <= um;
+        const unsigned long long vmask = __ballot(wpass);
         if (a.prune) {
             const float Ucur = rs[tid][0].y;
             if (Ucur != reachU) {                          // the root only when U moved

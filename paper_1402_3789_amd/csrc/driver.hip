@@ -175,6 +175,8 @@ size_t carve(const Plan& p, void* base, WS* w)
     w->tabs.spos = c.take<int32_t>(nsc_max + 1);
     w->tabs.pos2chunk = c.take<int32_t>(n);
     w->tabs.tabn = c.take<int32_t>(2);
+    w->tabs.ccomp = c.take<int32_t>(nch_max);
+    w->tabs.scomp = c.take<int32_t>(nsc_max);
     w->gT = c.take<uint32_t>((size_t)p.rmax);
     w->gU = c.take<uint32_t>((size_t)p.rmax);
     w->tfin = c.take<uint32_t>((size_t)p.rmax);
@@ -553,6 +555,9 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
         a.sfirst = w.tabs.sfirst;
         a.pos2chunk = w.tabs.pos2chunk;
         a.tabn = w.tabs.tabn;
+        a.spos = w.tabs.spos;
+        a.ccomp = w.tabs.ccomp;
+        a.scomp = w.tabs.scomp;
     }
     a.prune = R.o.disable_prune ? 0 : 1;
     a.local = (p.local && !use32) ? 1 : 0;

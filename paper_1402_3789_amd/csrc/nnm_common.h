@@ -209,6 +209,9 @@ struct CandArgs {
     const int32_t* sfirst;
     const int32_t* pos2chunk;
     const int32_t* tabn;
+    const int32_t* spos;      // [super-chunks + 1] first sorted position of each super-chunk
+    const int32_t* ccomp;     // [chunks] the component of each chunk (each holds one)
+    const int32_t* scomp;     // [super-chunks] and of each super-chunk
     int32_t prune;
     int32_t local;            // BF16/FP16: operands built per tile from xs
     // thresholds shared by the column splits of one row (float bits)
@@ -362,6 +365,8 @@ struct ChunkTabs {
     int32_t* spos;       // [n + 1] first sorted position of each super-chunk
     int32_t* pos2chunk;  // [n]
     int32_t* tabn;       // [2]
+    int32_t* ccomp;      // [n] component (segment) of each chunk
+    int32_t* scomp;      // [n] and of each super-chunk
 };
 hipError_t launch_chunk_tables(const int32_t* seg, int64_t n, int64_t nseg, const ChunkTabs& t,
                                const float* xs, float* balls, float* sballs, void* scan_temp,

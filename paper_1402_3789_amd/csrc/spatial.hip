@@ -470,6 +470,7 @@ __global__ __launch_bounds__(256) void k_tab_fill(const int32_t* __restrict__ se
                                                   const int32_t* __restrict__ sbase,
                                                   int32_t* __restrict__ cstart, int32_t* __restrict__ csup,
                                                   int32_t* __restrict__ sfirst, int32_t* __restrict__ spos,
+                                                  int32_t* __restrict__ ccomp, int32_t* __restrict__ scomp,
                                                   int32_t* __restrict__ tabn)
 {
     const int64_t g = blockIdx.x;
@@ -478,10 +479,12 @@ __global__ __launch_bounds__(256) void k_tab_fill(const int32_t* __restrict__ se
     for (int c = threadIdx.x; c < ccnt[g]; c += 256) {
         cstart[cb + c] = a + c * CHUNK;
         csup[cb + c] = sb + c / SUPER;
+        ccomp[cb + c] = (int32_t)g;
     }
     for (int q = threadIdx.x; q < scnt[g]; q += 256) {
         sfirst[sb + q] = cb + q * SUPER;
         spos[sb + q] = a + q * SUPER * CHUNK;
+        scomp[sb + q] = (int32_t)g;
     }
     if (g == nseg - 1 && threadIdx.x == 0) {
         const int nch = cb + ccnt[g], nsc = sb + scnt[g];
@@ -519,7 +522,8 @@ hipError_t launch_chunk_tables(const int32_t* seg, int64_t n, int64_t nseg, cons
     e = launch_exclusive_scan(t.scnt, t.sbase, nseg, scan_temp, nullptr, s);
     if (e != hipSuccess) return e;
     k_tab_fill<<<(unsigned)nseg, 256, 0, s>>>(t.segstart, nseg, n, t.ccnt, t.scnt, t.cbase, t.sbase,
-                                              t.cstart, t.csup, t.sfirst, t.spos, t.tabn);
+                                              t.cstart, t.csup, t.sfirst, t.spos, t.ccomp, t.scomp,
+                                              t.tabn);
     k_tab_pos2chunk<<<g256(n), 256, 0, s>>>(seg, n, t.segstart, t.cbase, t.pos2chunk);
     // at most n / CHUNK + nseg chunks and n / (CHUNK SUPER) + nseg super-chunks
     const int64_t mc = (n + CHUNK - 1) / CHUNK + nseg;

@@ -206,6 +206,26 @@ def test_int16grid_full_size_fp8(nnm):
     _bound_report_ok(tree.report)
 
 
+@pytest.mark.parametrize("k", [6, 16, 32])
+def test_aniso500_full_size_knn_identical_across_runs(nnm, aniso, k):
+    """Every row's exact kNN list (2M rows) is the same in repeated calls: a
+    race in the candidate pass shows up as rows that miss neighbours in some
+    runs, which sampled oracle rows can miss."""
+    Xd = torch.from_numpy(aniso).to("cuda:0")
+    _say("aniso500 full knn run-to-run", k)
+    ref = None
+    for it in range(3):
+        idx, s, ln = nnm.knn_build(Xd, k=k, precision="fp16")
+        torch.cuda.synchronize()
+        cur = (idx.cpu().numpy(), s.cpu().numpy(), ln.cpu().numpy())
+        if ref is None:
+            ref = cur
+            continue
+        bad = np.nonzero((cur[0] != ref[0]).any(axis=1))[0]
+        assert bad.size == 0, f"k={k} run {it}: {bad.size} rows differ from run 0, first {bad[:8]}"
+        assert np.array_equal(cur[1], ref[1]) and np.array_equal(cur[2], ref[2])
+
+
 @pytest.mark.parametrize("k", [16, 32])
 def test_aniso500_full_size_knn(nnm, aniso, k):
     # exact k nearest neighbours of every point at full size: sampled rows
