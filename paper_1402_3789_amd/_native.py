@@ -5,7 +5,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(HERE, "libnnm.so")
+# NNM_LIB names another build of the same library (for instance one whose
+# host code is instrumented by a sanitizer).
+LIBPATH = os.environ.get("NNM_LIB") or os.path.join(HERE, "libnnm.so")
 
 NNM_OK = 0
 NNM_EINVAL = -1
