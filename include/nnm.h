@@ -123,7 +123,13 @@ typedef struct {
     int32_t col_splits;     /* column splits per row tile (0 = auto)          */
     int32_t fixed_chunks;   /* 1: column chunks never follow the components
                                (debug)                                        */
-    int32_t reserved[9];
+    int32_t graph;          /* 1: the merge rounds after the first run as one
+                               captured hipGraph, replayed once per round
+                               (launch sizes taken on the device, one host
+                               read per round); the graph is kept for later
+                               calls with the same buffers, sizes and
+                               settings.  Results are identical.             */
+    int32_t reserved[8];
 } nnm_options;
 
 /* Per-call measurements (all optional to read; filled when non-NULL). */
@@ -158,6 +164,15 @@ typedef struct {
     double max_err_ratio;       /* max over rescored candidates of |t - s| /
                                    E(t), E(t) the bound applied to it (0/0 = 0,
                                    x/0 = inf); the proof makes it <= 1        */
+    double ms_graph;            /* graph-replayed rounds (options.graph), ms;
+                                   their kernels are not in the phase times
+                                   above, nor in the per-round overflow and
+                                   candidate-time entries                     */
+    int32_t graph_rounds;       /* rounds run by replaying the graph          */
+    int32_t graph_nodes;        /* kernel nodes of the round graph            */
+    int32_t graph_captured;     /* 1: this call captured the graph (0: it was
+                                   kept from an earlier call)                 */
+    int32_t pad_;
 } nnm_report;
 
 /* Fill *opt with the defaults (AUTO precision, automatic k and caps). */

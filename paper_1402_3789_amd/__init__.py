@@ -29,7 +29,7 @@ def _torch():
 
 
 def options(precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
-            force_fallback=False, col_splits=0, fixed_chunks=False) -> N.Options:
+            force_fallback=False, col_splits=0, fixed_chunks=False, graph=False) -> N.Options:
     o = N.Options()
     N.lib().nnm_default_options(ctypes.byref(o))
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
@@ -39,6 +39,7 @@ def options(precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
     o.force_fallback = int(bool(force_fallback))
     o.col_splits = int(col_splits)
     o.fixed_chunks = int(bool(fixed_chunks))
+    o.graph = int(bool(graph))
     return o
 
 
@@ -115,13 +116,15 @@ class Tree:
 
 def mst_build(X, precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
               force_fallback=False, col_splits=0, stream=None, workspace=None,
-              fixed_chunks=False) -> Tree:
-    """Exact key-ordered minimum spanning tree of the rows of X (device)."""
+              fixed_chunks=False, graph=False) -> Tree:
+    """Exact key-ordered minimum spanning tree of the rows of X (device).
+    graph=True replays the merge rounds after the first from a captured
+    hipGraph (kept for later calls with the same buffers and settings)."""
     torch = _torch()
     n, d, ld = _check_x(X)
     L = N.lib()
     o = options(precision, knn_k, survivor_cap, disable_prune, force_fallback, col_splits,
-                fixed_chunks)
+                fixed_chunks, graph)
     nb = ctypes.c_size_t(0)
     N.check("mst_workspace_size", L.mst_workspace_size(n, d, ctypes.byref(o), ctypes.byref(nb)))
     ws = (workspace or _WS).get(nb.value, X.device)
@@ -178,11 +181,11 @@ def knn_build(X, k=16, precision="auto", survivor_cap=0, force_fallback=False,
 
 
 def mst_build_batched(Xs, precision="auto", knn_k=0, survivor_cap=0, force_fallback=False,
-                      stream=None, workspace=None):
+                      stream=None, workspace=None, col_splits=0, graph=False):
     """Independent trees of many instances in one call; list of Tree."""
     torch = _torch()
     L = N.lib()
-    o = options(precision, knn_k, survivor_cap, False, force_fallback)
+    o = options(precision, knn_k, survivor_cap, False, force_fallback, col_splits, False, graph)
     inst = (N.Instance * len(Xs))()
     outs = []
     for b, X in enumerate(Xs):

@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("knn_k", ctypes.c_int32),
                 ("survivor_cap", ctypes.c_int32), ("disable_prune", ctypes.c_int32),
                 ("force_fallback", ctypes.c_int32), ("col_splits", ctypes.c_int32),
-                ("fixed_chunks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+                ("fixed_chunks", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
 
 
 class Report(ctypes.Structure):
@@ -58,7 +59,9 @@ class Report(ctypes.Structure):
                 ("exact_per_round", ctypes.c_int64 * 32),
                 ("cand_ms_per_round", ctypes.c_double * 32),
                 ("surv_per_round", ctypes.c_int64 * 32),
-                ("max_err_ratio", ctypes.c_double)]
+                ("max_err_ratio", ctypes.c_double), ("ms_graph", ctypes.c_double),
+                ("graph_rounds", ctypes.c_int32), ("graph_nodes", ctypes.c_int32),
+                ("graph_captured", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
     def as_dict(self):
         out = {}

@@ -35,14 +35,43 @@ __device__ __forceinline__ int xcd_tile(int b, int G)
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-// Row slots [rbeg, rend) and column range [cl, ch) of this workgroup's tile.
-__device__ __forceinline__ int4 tile_of(const CandArgs& a, int bm)
+// One work item of a candidate launch: row tile t, column split sp of nsp,
+// in a launch of n_rows rows.  A host-sized launch has one item per
+// workgroup (the grid is tiles x splits); a device-sized one pops items
+// from its descriptor's queue.
+struct Item {
+    int t, sp, nsp, n_rows;
+};
+
+// Workgroups of a device-sized candidate launch (two per compute unit, twice over).
+constexpr unsigned QGRID = 1024;
+
+__device__ __forceinline__ Item grid_item(const CandArgs& a)
 {
-    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    if (a.tiles) return a.tiles[t];
-    const int rbeg = t * bm;
-    const int rend = rbeg + bm < a.n_rows ? rbeg + bm : a.n_rows;
+    return Item{xcd_tile((int)blockIdx.x, (int)gridDim.x), (int)blockIdx.y, a.col_splits, a.n_rows};
+}
+
+// Row slots [rbeg, rend) and column range [cl, ch) of a work item's tile.
+__device__ __forceinline__ int4 tile_of(const CandArgs& a, int bm, const Item& it)
+{
+    if (a.tiles) return a.tiles[it.t];
+    const int rbeg = it.t * bm;
+    const int rend = rbeg + bm < it.n_rows ? rbeg + bm : it.n_rows;
     return make_int4(rbeg, rend, 0, a.np);
+}
+
+// The next item of a device-sized launch (all 256 threads call it; `slot`
+// is a shared int); false once the launch's items are used up.
+__device__ __forceinline__ bool pop_item(const CandArgs& a, int& slot, Item& it)
+{
+    __syncthreads();                  // the previous item is finished
+    if (threadIdx.x == 0) slot = atomicAdd(&a.desc->queue, 1);
+    __syncthreads();
+    const int w = slot;
+    const int nt = a.desc->n_tiles, nsp = a.desc->splits;
+    if (w >= nt * nsp) return false;
+    it = Item{w % nt, w / nt, nsp, a.desc->n_rows};
+    return true;
 }
 
 // Centre (FP32, from an FP64 mean) and radius (FP64 max, rounded up) of the
@@ -370,13 +399,13 @@ __device__ __forceinline__ int zigzag(int step, int start, int lo, int hi)
 // sh.wmax; umax is refreshed from them, behind one barrier, only after a
 // chunk was processed.  All 256 threads call this with identical arguments.
 template <bool TAB, typename Fn>
-__device__ inline void sweep_chunks(TileShared& sh, const CandArgs& a, int lo_r, int hi_r,
-                                    float umax, Fn&& process)
+__device__ inline void sweep_chunks(TileShared& sh, const CandArgs& a, const Item& it, int lo_r,
+                                    int hi_r, float umax, Fn&& process)
 {
     const int first_ch = chunk_first_of<TAB>(a, sh.col_lo);
     const int nch = chunk_end_of<TAB>(a, sh.col_hi) - first_ch;
-    const int cps = (nch + a.col_splits - 1) / a.col_splits;
-    const int ch_lo = first_ch + (int)blockIdx.y * cps;
+    const int cps = (nch + it.nsp - 1) / it.nsp;
+    const int ch_lo = first_ch + it.sp * cps;
     const int ch_hi = ch_lo + cps < first_ch + nch ? ch_lo + cps : first_ch + nch;
     if (ch_lo >= ch_hi) return;
     int start = chunk_at<TAB>(a, sh.first_pos);

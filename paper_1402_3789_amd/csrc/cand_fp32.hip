@@ -16,8 +16,10 @@ namespace {
 constexpr int BM = 256;
 constexpr int BN = CHUNK;
 
+// One work item (row tile, column split); share: the row thresholds are
+// shared with the item's other column splits through gT / gU.
 template <int DP, bool TAB>
-__global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
+__device__ __forceinline__ void cand_fp32_item(const CandArgs& a, const Item& it, const bool share)
 {
     constexpr int F4 = DP / 4;
     __shared__ float4 cbuf[BN * F4];
@@ -27,7 +29,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
 
     const int tid = threadIdx.x;
     const int k = a.k;
-    const int4 tile = tile_of(a, BM);
+    const int4 tile = tile_of(a, BM, it);
     const int64_t slot = (int64_t)tile.x + tid;
     const bool valid = slot < tile.y;
     const int rp = valid ? (a.rows ? a.rows[slot] : a.row0 + (int)slot) : 0;
@@ -111,13 +113,13 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
     __syncthreads();
     const float umax0 = fmaxf(fmaxf(sh.wmax[0], sh.wmax[1]), fmaxf(sh.wmax[2], sh.wmax[3]));
 
-    sweep_chunks<TAB>(sh, a, lo_r, hi_r, umax0, [&](int ci, int lo_c, int hi_c) {
+    sweep_chunks<TAB>(sh, a, it, lo_r, hi_r, umax0, [&](int ci, int lo_c, int hi_c) {
         // a chunk made only of the row's own component holds no candidate
         const bool own = lo_c == hi_c && lo_c == rc;
         const int64_t c0 = chunk_begin<TAB>(a, ci);
         const int ncols = (int)(chunk_end<TAB>(a, ci) - c0);
         const int cl = sh.col_lo, ch = sh.col_hi;
-        if (a.share && valid) {
+        if (share && valid) {
             T = fminf(T, __uint_as_float(a.gT[slot]));
             U = fminf(U, __uint_as_float(a.gU[slot]));
         }
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
                 // same component, or a column this tile must not pair with
                 const int cc = ccomp[c];
                 if (cc < 0 || cc == rc) continue;
-                const int pos = a.share ? atomicAdd(&a.surv_cnt[slot], 1) : cnt++;
+                const int pos = share ? atomicAdd(&a.surv_cnt[slot], 1) : cnt++;
                 if (pos < a.S) {
                     a.surv_j[slot * a.S + pos] = (int)(c0 + c);
                     a.surv_t[slot * a.S + pos] = t;
@@ -186,11 +188,11 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
                         const float Un = d2f_up(Ud);
                         if (Tn < T) {
                             T = Tn;
-                            if (a.share) atomicMin(&a.gT[slot], __float_as_uint(T));
+                            if (share) atomicMin(&a.gT[slot], __float_as_uint(T));
                         }
                         if (Un < U) {
                             U = Un;
-                            if (a.share) atomicMin(&a.gU[slot], __float_as_uint(U));
+                            if (share) atomicMin(&a.gU[slot], __float_as_uint(U));
                         }
                     }
                 }
@@ -198,11 +200,48 @@ __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
         }
         wave_max_store(sh, valid ? U : 0.f);
     });
-    if (!a.share && valid) a.surv_cnt[slot] = cnt;
+    if (!share && valid) a.surv_cnt[slot] = cnt;
     const int wrows = sh.rows - (tid >> 6) * 64;
     if ((tid & 63) == 0 && a.pairs && wrows > 0)
         atomicAdd(&a.pairs[((blockIdx.x * 4 + (tid >> 6)) & (NSPREAD - 1)) * SPREAD_STRIDE],
                   pairs * (unsigned long long)(wrows < 64 ? wrows : 64));
+}
+
+template <int DP, bool TAB>
+__global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
+{
+    cand_fp32_item<DP, TAB>(a, grid_item(a), a.share != 0);
+}
+
+// device-sized launch: a fixed grid pops (tile, split) items
+template <int DP>
+__global__ __launch_bounds__(256, 2) void k_cand_fp32_q(CandArgs a)
+{
+    __shared__ int slot;
+    Item it;
+    while (pop_item(a, slot, it)) cand_fp32_item<DP, false>(a, it, it.nsp > 1);
+}
+
+template <int DP>
+void launch_q(const CandArgs& a, size_t shm, hipStream_t s)
+{
+    k_cand_fp32_q<DP><<<QGRID, 256, shm, s>>>(a);
+}
+
+hipError_t launch_dp_q(const CandArgs& a, int dp, size_t shm, hipStream_t s)
+{
+    switch (dp) {
+    case 4: launch_q<4>(a, shm, s); break;
+    case 8: launch_q<8>(a, shm, s); break;
+    case 12: launch_q<12>(a, shm, s); break;
+    case 16: launch_q<16>(a, shm, s); break;
+    case 20: launch_q<20>(a, shm, s); break;
+    case 24: launch_q<24>(a, shm, s); break;
+    case 28: launch_q<28>(a, shm, s); break;
+    case 32: launch_q<32>(a, shm, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <bool TAB>
@@ -226,6 +265,10 @@ hipError_t launch_dp(const CandArgs& a, int dp, dim3 grid, size_t shm, hipStream
 
 hipError_t launch_cand_fp32(const CandArgs& a, hipStream_t s)
 {
+    if (a.desc) {
+        if (a.cstart) return hipErrorInvalidValue;   // device-sized launches use fixed chunks
+        return launch_dp_q(a, (a.d + 3) / 4 * 4, (size_t)BM * a.k * sizeof(float), s);
+    }
     if (a.n_rows <= 0) return hipSuccess;
     const unsigned nt = a.tiles ? (unsigned)a.n_tiles : (unsigned)((a.n_rows + BM - 1) / BM);
     if (nt == 0) return hipSuccess;

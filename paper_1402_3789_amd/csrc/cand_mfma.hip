@@ -132,12 +132,12 @@ struct GroupGen {
     int sbase;                       // steps [sbase, sbase + 64) tested into smask
     unsigned long long smask;
 
-    __device__ void init(const TileShared& sh, const CandArgs& a)
+    __device__ void init(const TileShared& sh, const CandArgs& a, const Item& it)
     {
         const int first_ch = chunk_first_of<TAB>(a, sh.col_lo);
         const int nch = chunk_end_of<TAB>(a, sh.col_hi) - first_ch;
-        const int cps = (nch + a.col_splits - 1) / a.col_splits;
-        ch_lo = first_ch + (int)blockIdx.y * cps;
+        const int cps = (nch + it.nsp - 1) / it.nsp;
+        ch_lo = first_ch + it.sp * cps;
         ch_hi = ch_lo + cps < first_ch + nch ? ch_lo + cps : first_ch + nch;
         if (ch_lo < ch_hi) {
             start = chunk_at<TAB>(a, sh.first_pos);
@@ -350,8 +350,10 @@ __device__ __forceinline__ void local_operands(const float* x, const float* c, f
 //   topk[r][0..KP): the k smallest candidates, +inf padded (t, or for LOCAL
 //              upper bounds on keys in data units, since the frame changes
 //              per chunk).  KP is k rounded up to 8 or 32.
+// One work item: row tile it.t against column split it.sp of its tile's
+// column range.
 template <int OP, bool LOCAL, bool SHARE, int KP, bool TAB>
-__global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
+__device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it)
 {
     typedef OpTraits<OP> Tr;
     typedef typename Tr::frag_t frag_t;
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     const int lane = tid & 63;
     const int grp = lane >> 4;
     const int k = a.k;
-    const int4 tile = tile_of(a, BM);
+    const int4 tile = tile_of(a, BM, it);
     const int64_t row_base = tile.x;
     const int64_t row_end = tile.y;
     const int exact = a.bc.exact;
@@ -805,7 +807,7 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
     // every candidate (bits per wave), then the chunks some wave needs, in
     // order, with the next one in flight.
     GroupGen<TAB> gen;
-    gen.init(sh, a);
+    gen.init(sh, a, it);
     float reach = __builtin_huge_valf(), reachU = __builtin_huge_valf();   // sqrt bound of U
     int buf = 0;
     for (;;) {
@@ -885,6 +887,22 @@ __global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
                   pairs * (unsigned long long)(wrows < 64 ? wrows : 64));
 }
 
+template <int OP, bool LOCAL, bool SHARE, int KP, bool TAB>
+__global__ __launch_bounds__(256, 2) void k_cand_mfma(CandArgs a)
+{
+    cand_mfma_item<OP, LOCAL, SHARE, KP, TAB>(a, grid_item(a));
+}
+
+// device-sized launch: a fixed grid pops (tile, split) items; the splits of
+// a row always share their thresholds
+template <int OP, bool LOCAL, int KP>
+__global__ __launch_bounds__(256, 2) void k_cand_mfma_q(CandArgs a)
+{
+    __shared__ int slot;
+    Item it;
+    while (pop_item(a, slot, it)) cand_mfma_item<OP, LOCAL, true, KP, false>(a, it);
+}
+
 template <int OP, bool LOCAL, bool TAB>
 void launch_tab(const CandArgs& a, dim3 grid, hipStream_t s)
 {
@@ -902,18 +920,24 @@ void launch_tab(const CandArgs& a, dim3 grid, hipStream_t s)
 template <int OP, bool LOCAL>
 void launch_one(const CandArgs& a, dim3 grid, size_t, hipStream_t s)
 {
-    if (a.cstart) launch_tab<OP, LOCAL, true>(a, grid, s);
-    else launch_tab<OP, LOCAL, false>(a, grid, s);
+    if (a.desc) {
+        if (a.k <= 8) k_cand_mfma_q<OP, LOCAL, 8><<<QGRID, 256, (size_t)BM * 8 * sizeof(float), s>>>(a);
+        else k_cand_mfma_q<OP, LOCAL, KMAX><<<QGRID, 256, (size_t)BM * KMAX * sizeof(float), s>>>(a);
+    } else if (a.cstart) {
+        launch_tab<OP, LOCAL, true>(a, grid, s);
+    } else {
+        launch_tab<OP, LOCAL, false>(a, grid, s);
+    }
 }
 
 }  // namespace
 
 hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s)
 {
-    if (a.n_rows <= 0) return hipSuccess;
-    const unsigned nt = a.tiles ? (unsigned)a.n_tiles : (unsigned)((a.n_rows + BM - 1) / BM);
-    if (nt == 0) return hipSuccess;
-    dim3 grid(nt, (unsigned)a.col_splits);
+    if (a.desc && a.cstart) return hipErrorInvalidValue;   // device-sized launches use fixed chunks
+    const unsigned nt = a.desc ? 1u : a.tiles ? (unsigned)a.n_tiles : (unsigned)((a.n_rows + BM - 1) / BM);
+    if (!a.desc && (a.n_rows <= 0 || nt == 0)) return hipSuccess;
+    dim3 grid(nt, a.desc ? 1u : (unsigned)a.col_splits);
     size_t shm = (size_t)BM * a.k * sizeof(float);
     const bool local = a.local != 0;
     switch (opkind) {

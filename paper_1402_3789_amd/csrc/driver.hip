@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -31,6 +32,10 @@ struct Counters {
     int32_t over;                   // overflowed rows in the last batch
     int32_t tcount;                 // tiles of the last batch
     int32_t pad_[5];
+    // graph-replayed rounds: row counts kept on the device
+    int32_t dc[8];                  // [0] rows to scan [1] representatives
+                                    // [2] representatives scanned [3] overflowed rows
+    int32_t pad2_[8];
     // totals spread over NSPREAD slots on separate cache lines (slot =
     // workgroup mod NSPREAD), so that no address or line takes an atomic
     // from every workgroup
@@ -94,6 +99,7 @@ struct WS {
     double* u0b; int32_t* oflag; int32_t* olist; int32_t* rep_pos; int32_t* rflag2;
     int4* tiles; int32_t* tflag; int32_t* tstart;
     float* Xcat; int32_t* inst_off; InstDev* inst; nnm_edge** outp;
+    LaunchDesc* desc;
 };
 
 struct Carver {
@@ -194,6 +200,7 @@ size_t carve(const Plan& p, void* base, WS* w)
     w->inst_off = c.take<int32_t>((size_t)p.ninst + 1);
     w->inst = multi ? c.take<InstDev>((size_t)p.ninst) : nullptr;
     w->outp = multi ? c.take<nnm_edge*>((size_t)p.ninst) : nullptr;
+    w->desc = c.take<LaunchDesc>(1);
     return c.off + 256;
 }
 
@@ -302,6 +309,7 @@ struct Run {
     int kk = 0;             // neighbours sought by the current scan (0 = the cache depth)
     bool fp32_scan = false; // the current scan uses the FP32 kernel whatever the precision
     bool aligned = false;   // this round's column chunks follow the components (w.tabs)
+    int64_t max_inst = 0;   // points of the largest instance
 };
 
 int ceil_log2(int64_t v)
@@ -705,6 +713,285 @@ nnm_status scan_rows(Run& R, const float* X, const int32_t* rows, int64_t count,
     return NNM_OK;
 }
 
+// ---- device-sized scans (rounds replayed from a captured graph) ----------
+//
+// The same steps as scan_batch / scan_rows, sized on the device: each
+// launch covers rows [off, off + rmax) of a row list whose length is a
+// device count, and the overflow passes run a fixed number of times (empty
+// passes do no work).  No host read, no memset: everything here may be
+// captured.
+
+// overflow passes after the first scan: bounded re-scans on the matrix
+// cores, then the FP32 kernel, the last one with the exact scan for rows
+// that overflow again (exact data: matrix cores throughout)
+constexpr int DEV_PASSES = 3;
+
+nnm_status scan_batch_dev(Run& R, const float* X, const int32_t* rows, const int32_t* count,
+                          int32_t off, int kk, const double* u0, bool use32, int level)
+{
+    Plan& p = R.p;
+    WS& w = R.w;
+    LaunchDesc* D = w.desc;
+    const int32_t cap = (int32_t)p.rmax;
+    const int32_t target = u0 ? 8192 : 4096;
+    HIP_TRY(launch_desc_rows(D, count, off, cap, p.n, target, R.o.col_splits, R.s));
+    const int32_t* lrows = rows + off;
+    CandArgs a{};
+    a.opR = w.opRs;
+    a.opC = w.opCs;
+    a.xs = w.xs;
+    a.pc = w.pcs;
+    a.compS = w.compS;
+    a.rows = lrows;
+    a.row0 = 0;
+    a.u0 = u0;
+    a.n_rows = cap;
+    a.np = (int32_t)p.n;
+    a.d = p.d;
+    a.k = kk;
+    a.S = p.S;
+    a.col_splits = 0;
+    a.desc = D;
+    if (p.ninst > 1) {
+        const int64_t max_tiles = std::min<int64_t>(p.rmax, (int64_t)cap / 256 + p.ninst + 1);
+        HIP_TRY(launch_tiles_dev(lrows, cap, w.inst_off, p.ninst, 256, w.tflag, w.tstart, D,
+                                 w.scan_temp, R.s));
+        HIP_TRY(launch_tile_desc_dev(w.tstart, (int)max_tiles, lrows, w.inst_off, p.ninst, 256,
+                                     w.tiles, D, R.s));
+        HIP_TRY(launch_desc_splits(D, p.n, target, R.o.col_splits, R.s));
+        a.tiles = w.tiles;
+    }
+    a.bc = R.bc;
+    a.surv_cnt = w.surv_cnt;
+    a.surv_j = w.surv_j;
+    a.surv_t = w.surv_t;
+    a.surv_e = w.surv_e;
+    a.pairs = w.ctr->pairs;
+    a.X = X;
+    a.ld = p.ld;
+    a.perm = w.perm;
+    a.balls = w.balls;
+    a.sballs = w.sballs;
+    a.prune = R.o.disable_prune ? 0 : 1;
+    a.local = (p.local && !use32) ? 1 : 0;
+    a.share = 1;
+    a.gT = w.gT;
+    a.gU = w.gU;
+    const bool use_tfin = !use32 && !p.local;
+    a.tfin = use_tfin ? w.tfin : nullptr;
+    HIP_TRY(launch_fill_i32_desc(w.surv_cnt, 0, D, R.s));
+    if (use_tfin) HIP_TRY(launch_fill_i32_desc((int32_t*)w.tfin, 0x7F800000, D, R.s));
+    HIP_TRY(launch_fill_i32_desc((int32_t*)w.gT, 0x7F800000, D, R.s));
+    HIP_TRY(launch_fill_i32_desc((int32_t*)w.gU, 0x7F800000, D, R.s));
+    if (use32) HIP_TRY(launch_cand_fp32(a, R.s));
+    else HIP_TRY(launch_cand_mfma(p.opkind, a, R.s));
+    RescoreArgs r{};
+    r.X = X;
+    r.xs = w.xs;
+    r.ld = p.ld;
+    r.d = p.d;
+    r.n_rows = cap;
+    r.k = kk;
+    r.kstride = p.k;
+    r.S = p.S;
+    r.rows = lrows;
+    r.row0 = 0;
+    r.perm = w.perm;
+    r.tfin = a.tfin;
+    r.comp = w.comp;
+    r.surv_cnt = w.surv_cnt;
+    r.surv_j = w.surv_j;
+    r.surv_t = w.surv_t;
+    r.u0 = u0;
+    r.inv_sigma2 = use32 ? 1.0 : 1.0 / (double)R.bc.sigma2;
+    r.sigma2 = use32 ? 1.f : R.bc.sigma2;
+    r.force_fallback = R.o.force_fallback;
+    r.np = p.n;
+    r.inst_off = w.inst_off;
+    r.ninst = (int32_t)p.ninst;
+    r.cidx = w.cidx;
+    r.cs = w.cs;
+    r.clen = w.clen;
+    r.ccur = w.ccur;
+    r.clb = w.clb;
+    r.cflag = w.cflag;
+    r.overflow_rows = &D->over;
+    r.level = level;
+    r.kb = p.mst ? std::min(kk, 4) : kk;
+    r.u0b = w.u0b;
+    r.oflag = w.oflag;
+    r.survivors = w.ctr->survivors;
+    r.err_bits = w.ctr->err_bits;
+    r.bound_mode = use32 ? BOUND_FP32 : (p.exact ? BOUND_EXACT : (a.local ? BOUND_LOCAL : BOUND_GLOBAL));
+    r.pcs = w.pcs;
+    r.bc = R.bc;
+    r.surv_e = w.surv_e;
+    r.desc = D;
+    HIP_TRY(launch_rescore(r, w.overflow_list, R.s));
+    if (level == 2 || R.o.force_fallback)
+        HIP_TRY(launch_fallback_dev(r, w.overflow_list, &D->over, R.s));
+    return NNM_OK;
+}
+
+// scan_rows for the first *count entries of rows (at most n)
+nnm_status scan_rows_dev(Run& R, const float* X, const int32_t* rows, const int32_t* count,
+                         bool use_u0, int kk)
+{
+    Plan& p = R.p;
+    WS& w = R.w;
+    int32_t* on = &w.ctr->dc[3];
+    for (int64_t b0 = 0; b0 < p.n; b0 += p.rmax) {
+        HIP_TRY(launch_fill_i32(w.oflag, 0, p.n, R.s));
+        nnm_status st = scan_batch_dev(R, X, rows, count, (int32_t)b0, kk, use_u0 ? w.u0s : nullptr,
+                                       p.opkind == OP_FP32, 1);
+        if (st != NNM_OK) return st;
+        if (R.o.force_fallback) continue;
+        for (int pass = 1; pass <= DEV_PASSES; ++pass) {
+            HIP_TRY(launch_compact(w.oflag, p.n, w.olist, on, w.scan_temp, R.s));
+            HIP_TRY(launch_fill_i32(w.oflag, 0, p.n, R.s));
+            const bool use32 = p.opkind == OP_FP32 || (!p.exact && pass >= 2);
+            for (int64_t c0 = 0; c0 < p.n; c0 += p.rmax) {
+                st = scan_batch_dev(R, X, w.olist, on, (int32_t)c0, kk, w.u0b, use32,
+                                    pass == DEV_PASSES ? 2 : 1);
+                if (st != NNM_OK) return st;
+            }
+        }
+    }
+    return NNM_OK;
+}
+
+// One merge round (not the first) with every size on the device: the
+// body of the round graph.
+nnm_status round_dev(Run& R, const float* X)
+{
+    Plan& p = R.p;
+    WS& w = R.w;
+    const int64_t n = p.n;
+    MergeArgs m = merge_args(R);
+    int32_t* dc = w.ctr->dc;
+    R.aligned = false;
+    nnm_status st = sort_points(R, X, 0);
+    if (st != NNM_OK) return st;
+    HIP_TRY(launch_reset_comp(m, R.s));
+    HIP_TRY(launch_cursor(m, R.s));
+    HIP_TRY(launch_compmin1(m, R.s));
+    HIP_TRY(launch_flag_rescan(m, R.s));
+    HIP_TRY(launch_compact(w.rflag, n, w.rlist, &dc[0], w.scan_temp, R.s));
+    if (!R.o.disable_prune) {
+        // representatives of the components without a bound go first (their
+        // nearest outside point), when they are fewer than the rows to scan
+        HIP_TRY(launch_pick_reps_dev(m, w.compS, w.rep_pos, &w.ctr->ctr[1], w.rflag2, R.s));
+        HIP_TRY(launch_compact(w.rflag2, n, w.olist, &dc[1], w.scan_temp, R.s));
+        HIP_TRY(launch_rep_select(&dc[1], &dc[0], &dc[2], R.s));
+        HIP_TRY(launch_copy_i32_dev(w.rlist, w.olist, &dc[2], n, R.s));
+        st = scan_rows_dev(R, X, w.rlist, &dc[2], false, 1);
+        if (st != NNM_OK) return st;
+        HIP_TRY(launch_cursor(m, R.s));
+        HIP_TRY(launch_compmin1(m, R.s));
+        HIP_TRY(launch_flag_rescan(m, R.s));
+        HIP_TRY(launch_compact(w.rflag, n, w.rlist, &dc[0], w.scan_temp, R.s));
+    }
+    st = scan_rows_dev(R, X, w.rlist, &dc[0], true, p.k);
+    if (st != NNM_OK) return st;
+    HIP_TRY(launch_cursor(m, R.s));
+    HIP_TRY(launch_compmin1(m, R.s));
+    HIP_TRY(launch_compmin2(m, R.s));
+    HIP_TRY(launch_hook(m, R.s));
+    // a hook chain has at most as many links as the largest instance has
+    // points; each jump launch at least doubles every pointer's reach
+    HIP_TRY(launch_jump(m, ceil_log2(std::max<int64_t>(R.max_inst, 2)) + 1, R.s));
+    HIP_TRY(launch_fill_i32(&w.ctr->ctr[1], 0, 2, R.s));
+    HIP_TRY(launch_jump_check(m, R.s));
+    HIP_TRY(launch_relabel(m, R.s));
+    return NNM_OK;
+}
+
+// Executable round graphs kept for later calls: the kernels' arguments are
+// fixed by the workspace address, the input address, the plan, the options
+// and the frame, so a call with the same values replays the same graph.
+struct RoundGraph {
+    std::vector<uint64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int nodes = 0;
+    ~RoundGraph()
+    {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+    }
+};
+
+constexpr size_t GRAPH_CACHE = 8;
+std::mutex g_graph_mu;
+std::vector<std::shared_ptr<RoundGraph>> g_graphs;     // most recent last
+hipStream_t g_capture_stream[64] = {};
+
+template <typename T>
+void key_bytes(std::vector<uint64_t>& k, const T& v)
+{
+    uint64_t buf[(sizeof(T) + 7) / 8] = {};
+    memcpy(buf, &v, sizeof(T));
+    for (uint64_t x : buf) k.push_back(x);
+}
+
+std::vector<uint64_t> graph_key(const Run& R, const float* X, int dev)
+{
+    std::vector<uint64_t> k;
+    k.push_back((uint64_t)dev);
+    k.push_back((uint64_t)(uintptr_t)R.w.stats);      // workspace base
+    k.push_back((uint64_t)(uintptr_t)X);
+    const Plan& p = R.p;
+    const int64_t f[] = {p.n, p.d, p.ld, p.opkind, p.exact, p.k, p.S, p.rmax, p.mst, p.L1, p.L2,
+                         p.ninst, p.local, p.keep_e, R.max_inst};
+    for (int64_t x : f) k.push_back((uint64_t)x);
+    key_bytes(k, R.o);
+    key_bytes(k, R.bc);
+    return k;
+}
+
+// The round graph for this call: a kept one, or captured now (on a stream
+// of the library's; the graph is then launched on the caller's stream).
+nnm_status round_graph(Run& R, const float* X, std::shared_ptr<RoundGraph>* out, bool* captured)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return NNM_EDEVICE;
+    std::vector<uint64_t> key = graph_key(R, X, dev);
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    for (size_t i = 0; i < g_graphs.size(); ++i) {
+        if (g_graphs[i]->key == key) {
+            std::shared_ptr<RoundGraph> g = g_graphs[i];
+            g_graphs.erase(g_graphs.begin() + (long)i);
+            g_graphs.push_back(g);
+            *out = g;
+            *captured = false;
+            return NNM_OK;
+        }
+    }
+    if (!g_capture_stream[dev])
+        HIP_TRY(hipStreamCreateWithFlags(&g_capture_stream[dev], hipStreamNonBlocking));
+    auto g = std::make_shared<RoundGraph>();
+    g->key = std::move(key);
+    hipStream_t caller = R.s;
+    R.s = g_capture_stream[dev];
+    HIP_TRY(hipStreamBeginCapture(R.s, hipStreamCaptureModeThreadLocal));
+    nnm_status st = round_dev(R, X);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(R.s, &graph);
+    R.s = caller;
+    g->graph = graph;
+    if (st != NNM_OK) return st;
+    if (e != hipSuccess || !graph) return NNM_EDEVICE;
+    size_t nn = 0;
+    HIP_TRY(hipGraphGetNodes(graph, nullptr, &nn));
+    g->nodes = (int)nn;
+    HIP_TRY(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0));
+    g_graphs.push_back(g);
+    if (g_graphs.size() > GRAPH_CACHE) g_graphs.erase(g_graphs.begin());
+    *out = g;
+    *captured = true;
+    return NNM_OK;
+}
+
 nnm_status finish_report(Run& R, std::chrono::steady_clock::time_point t0)
 {
     if (!R.rep) return NNM_OK;
@@ -857,10 +1144,47 @@ nnm_status mst_rounds(Run& R, const float* X)
     Counters hc;
     memset(&hc, 0, sizeof(hc));
     unsigned long long pairs_before = 0, surv_before = 0;
+    std::shared_ptr<RoundGraph> rg;
     for (; ncomp > p.ninst; ++round) {
         if (round >= 64) return NNM_EDEVICE;   // cannot happen: components at least halve
         R.round = round;
         if (rep && round < 32) rep->comps_per_round[round] = ncomp;
+        if (R.o.graph && round >= 1) {
+            // replay the round graph; one read of the counters per round
+            if (!rg) {
+                bool captured = false;
+                st = round_graph(R, X, &rg, &captured);
+                if (st != NNM_OK) return st;
+                if (rep) {
+                    rep->graph_nodes = rg->nodes;
+                    rep->graph_captured = captured ? 1 : 0;
+                }
+            }
+            {
+                Timer t(R.timers, R.s, rep ? &rep->ms_graph : nullptr);
+                HIP_TRY(hipGraphLaunch(rg->exec, R.s));
+            }
+            HIP_TRY(hipMemcpyAsync(&hc, w.ctr, sizeof(hc), hipMemcpyDeviceToHost, R.s));
+            HIP_TRY(hipStreamSynchronize(R.s));
+            if (hc.ctr[2] != 0) return NNM_EDEVICE;   // cannot happen: enough jumps
+            const int64_t next = hc.ctr[1];
+            if (next >= ncomp) return NNM_EDEVICE;
+            ncomp = next;
+            if (rep) {
+                rep->graph_rounds += 1;
+                rep->rows_scanned += hc.dc[0] + hc.dc[2];
+                if (round < 32) {
+                    rep->rows_per_round[round] = hc.dc[0] + hc.dc[2];
+                    const unsigned long long pairs_now = spread_sum(hc.pairs);
+                    const unsigned long long surv_now = spread_sum(hc.survivors);
+                    rep->pairs_per_round[round] = (int64_t)(pairs_now - pairs_before);
+                    rep->surv_per_round[round] = (int64_t)(surv_now - surv_before);
+                    pairs_before = pairs_now;
+                    surv_before = surv_now;
+                }
+            }
+            continue;
+        }
         {
             Timer t(R.timers, R.s, rep ? &rep->ms_sort : nullptr);
             R.aligned = round > 0 && ncomp * ALIGN_AVG <= n && !R.o.fixed_chunks;
@@ -977,6 +1301,7 @@ nnm_status mst_build_in(const float* X_dev, int64_t n, int32_t d, int64_t ld, co
     nnm_status st = begin(R, X_dev, n, d, ld, 0, opt, ws_dev, ws_bytes, stream, rep, true);
     if (st != NNM_OK) return st;
     R.timers = R.timers && timers;
+    R.max_inst = n;
     st = stage(R, X_dev);
     if (st != NNM_OK) return st;
     if (n == 1) return finish_report(R, t0);
@@ -1045,8 +1370,13 @@ extern "C" nnm_status mst_build_noalloc(const float* X_dev, int64_t n, int32_t d
     void* ws = nullptr;
     st = scratch_of_current_device(&ws);
     if (st != NNM_OK) return st;
-    // no HIP events either: the phase times of the report stay 0
-    return mst_build_in(X_dev, n, d, ld, opt, ws, NOALLOC_SCRATCH_BYTES, edges_dev, stream, rep, false);
+    // no HIP events either: the phase times of the report stay 0; and no
+    // graph (instantiating one allocates)
+    nnm_options o;
+    nnm_default_options(&o);
+    if (opt) o = *opt;
+    o.graph = 0;
+    return mst_build_in(X_dev, n, d, ld, &o, ws, NOALLOC_SCRATCH_BYTES, edges_dev, stream, rep, false);
 }
 
 namespace {
@@ -1122,6 +1452,7 @@ extern "C" nnm_status mst_build_batched(const nnm_instance* inst, int32_t count,
     std::vector<nnm_edge*> outp(count);
     for (int32_t b = 0; b < count; ++b) {
         off[b + 1] = off[b] + (int32_t)inst[b].n;
+        R.max_inst = std::max<int64_t>(R.max_inst, inst[b].n);
         hin[b].X = inst[b].X_dev;
         hin[b].ld = inst[b].ld;
         hin[b].d = inst[b].d;

@@ -115,10 +115,11 @@ constexpr int REPS = 8;
 
 __global__ __launch_bounds__(256) void k_rep_flags(MergeArgs a, const int32_t* seg,
                                                    const int32_t* segstart, int64_t nseg,
-                                                   int32_t* flag2)
+                                                   int32_t* flag2, const int32_t* nseg_dev)
 {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= a.n) return;
+    if (nseg_dev) nseg = *nseg_dev;
     int f = 0;
     if (a.rflag[p] && a.u0s[p] < 0.0) {
         const int sg = seg[p];
@@ -129,6 +130,22 @@ __global__ __launch_bounds__(256) void k_rep_flags(MergeArgs a, const int32_t* s
         f = ((p - st) % stride == 0) ? 1 : 0;
     }
     flag2[p] = f;
+}
+
+__global__ __launch_bounds__(64) void k_rep_select(const int32_t* nrep, const int32_t* rcount,
+                                                   int32_t* eff)
+{
+    if (threadIdx.x != 0) return;
+    const int32_t r = *nrep;
+    *eff = (r > 0 && r < *rcount) ? r : 0;
+}
+
+__global__ __launch_bounds__(256) void k_copy_i32_dev(int32_t* __restrict__ dst,
+                                                      const int32_t* __restrict__ src,
+                                                      const int32_t* __restrict__ count)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < *count) dst[i] = src[i];
 }
 
 __global__ __launch_bounds__(256) void k_seg_starts(const int32_t* seg, int64_t n, int32_t* segstart)
@@ -294,7 +311,28 @@ hipError_t launch_pick_reps(const MergeArgs& a, const int32_t* seg, int32_t* seg
                             int64_t nseg, int32_t* flag2, hipStream_t s)
 {
     k_seg_starts<<<g256(a.n), 256, 0, s>>>(seg, a.n, segstart);
-    k_rep_flags<<<g256(a.n), 256, 0, s>>>(a, seg, segstart, nseg, flag2);
+    k_rep_flags<<<g256(a.n), 256, 0, s>>>(a, seg, segstart, nseg, flag2, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_pick_reps_dev(const MergeArgs& a, const int32_t* seg, int32_t* segstart,
+                                const int32_t* nseg, int32_t* flag2, hipStream_t s)
+{
+    k_seg_starts<<<g256(a.n), 256, 0, s>>>(seg, a.n, segstart);
+    k_rep_flags<<<g256(a.n), 256, 0, s>>>(a, seg, segstart, 0, flag2, nseg);
+    return hipGetLastError();
+}
+
+hipError_t launch_rep_select(const int32_t* nrep, const int32_t* rcount, int32_t* eff, hipStream_t s)
+{
+    k_rep_select<<<1, 64, 0, s>>>(nrep, rcount, eff);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_i32_dev(int32_t* dst, const int32_t* src, const int32_t* count, int64_t cap,
+                               hipStream_t s)
+{
+    k_copy_i32_dev<<<g256(cap), 256, 0, s>>>(dst, src, count);
     return hipGetLastError();
 }
 

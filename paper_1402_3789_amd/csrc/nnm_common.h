@@ -166,6 +166,20 @@ hipError_t launch_gather_points(int64_t n, int opkind, const int32_t* perm,
                                 void* opCs, PointConst* pcs, float* xs,
                                 int32_t* compS, hipStream_t s);
 
+// Rounds replayed from a captured hipGraph take the size of each launch
+// from the device: one descriptor per launch site, written by a one-thread
+// kernel just before the launch.  The kernels of such a launch run a fixed
+// grid that loops over the work; the candidate passes pop their (tile,
+// column split) items from `queue`.
+struct LaunchDesc {
+    int32_t n_rows;    // rows of the launch
+    int32_t n_tiles;   // row tiles (256 consecutive slots, or tile descriptors)
+    int32_t splits;    // column splits per tile
+    int32_t queue;     // next work item; zero before the candidate launch
+    int32_t over;      // rows whose survivor list overflowed (rescoring)
+    int32_t pad_[3];
+};
+
 // Candidate pass over a list of rows (sorted positions) against all columns.
 struct CandArgs {
     const void* opR;          // row-form operands, sorted order
@@ -220,6 +234,8 @@ struct CandArgs {
     uint32_t* tfin;           // [n_rows] or NULL: each row's final threshold (FP32
                               // bits, clamped at 0; min over column splits)
     uint32_t* gU;             // [n_rows] bound on the key of the k-th neighbour
+    // device-sized launch (NULL: n_rows, n_tiles and col_splits above)
+    LaunchDesc* desc;
 };
 
 hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s);
@@ -270,11 +286,27 @@ struct RescoreArgs {
     const PointConst* pcs;    // BOUND_GLOBAL: per sorted position
     BoundConst bc;            // BOUND_GLOBAL: column maxima
     const float* surv_e;      // BOUND_LOCAL: [n_rows][S] t + E(t)
+    const LaunchDesc* desc;   // device-sized launch (NULL: n_rows above)
 };
 
 hipError_t launch_rescore(const RescoreArgs& a, int32_t* overflow_list, hipStream_t s);
 hipError_t launch_fallback(const RescoreArgs& a, const int32_t* overflow_list, int n_over,
                            hipStream_t s);
+// the exact scan of the rows counted in *n_over (device-sized launch)
+hipError_t launch_fallback_dev(const RescoreArgs& a, const int32_t* overflow_list,
+                               const int32_t* n_over, hipStream_t s);
+
+// Descriptor of a device-sized launch over rows [off, off + cap) of a list
+// of *count rows: n_rows = clamp(*count - off, 0, cap), tiles of 256 rows,
+// column splits as the host would pick them (fixed_splits > 0: that many),
+// queue and overflow count cleared.
+hipError_t launch_desc_rows(LaunchDesc* d, const int32_t* count, int32_t off, int32_t cap,
+                            int64_t np, int32_t target, int32_t fixed_splits, hipStream_t s);
+// After tile descriptors were built: splits from d->n_tiles.
+hipError_t launch_desc_splits(LaunchDesc* d, int64_t np, int32_t target, int32_t fixed_splits,
+                              hipStream_t s);
+// p[0 .. d->n_rows) = v
+hipError_t launch_fill_i32_desc(int32_t* p, int32_t v, const LaunchDesc* d, hipStream_t s);
 
 // Merge-round kernels.
 struct MergeArgs {
@@ -311,6 +343,15 @@ hipError_t launch_jump(const MergeArgs& a, int iters, hipStream_t s);
 hipError_t launch_jump_check(const MergeArgs& a, hipStream_t s);
 hipError_t launch_pick_reps(const MergeArgs& a, const int32_t* seg, int32_t* segstart,
                             int64_t nseg, int32_t* flag2, hipStream_t s);
+// the same with the segment count on the device
+hipError_t launch_pick_reps_dev(const MergeArgs& a, const int32_t* seg, int32_t* segstart,
+                                const int32_t* nseg, int32_t* flag2, hipStream_t s);
+// *eff = *nrep when 0 < *nrep < *rcount, else 0 (the representatives are
+// scanned first only when they are fewer than the rows to scan)
+hipError_t launch_rep_select(const int32_t* nrep, const int32_t* rcount, int32_t* eff, hipStream_t s);
+// dst[0 .. *count) = src[0 .. *count), *count <= cap
+hipError_t launch_copy_i32_dev(int32_t* dst, const int32_t* src, const int32_t* count, int64_t cap,
+                               hipStream_t s);
 hipError_t launch_export_knn(int64_t n, int k, const int32_t* cidx, const double* cs,
                              const int32_t* clen, int32_t* idx, double* sd, int32_t* len,
                              hipStream_t s);
@@ -390,6 +431,14 @@ hipError_t launch_tiles(const int32_t* rows, int32_t row0, int64_t nb, const int
 hipError_t launch_tile_desc(const int32_t* tstart, int ntiles, const int32_t* rows, int32_t row0,
                             int64_t nb, const int32_t* off, int ninst, int bm, int4* tiles,
                             hipStream_t s);
+// Device-sized forms: the rows are the first d->n_rows of the list (at most
+// cap); the tile count goes to d->n_tiles (at most max_tiles).
+hipError_t launch_tiles_dev(const int32_t* rows, int64_t cap, const int32_t* off, int ninst, int bm,
+                            int32_t* flag, int32_t* tstart, LaunchDesc* d, void* scan_temp,
+                            hipStream_t s);
+hipError_t launch_tile_desc_dev(const int32_t* tstart, int max_tiles, const int32_t* rows,
+                                const int32_t* off, int ninst, int bm, int4* tiles,
+                                const LaunchDesc* d, hipStream_t s);
 hipError_t launch_write_edges_batched(const SortRec* sorted, int64_t ne, const int32_t* off, int ninst,
                                       SortRec* recA, SortRec* recB, void* radix_temp,
                                       nnm_edge* const* out, hipStream_t s);

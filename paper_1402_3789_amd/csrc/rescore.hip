@@ -29,12 +29,9 @@ __device__ __forceinline__ void atomic_max_pos_double(unsigned long long* p, dou
 // scanned again below that bound and gets an exact prefix of at least kb
 // neighbours (level 1).  A row that overflows again goes to the exact scan.
 template <int E>
-__global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflow_list)
+__device__ __forceinline__ void rescore_row(const RescoreArgs& a, int64_t slot, int32_t* overflow_list)
 {
-    const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t slot = (int64_t)blockIdx.x * 4 + wave;
-    if (slot >= a.n_rows) return;
     const int rp = a.rows ? a.rows[slot] : a.row0 + (int)slot;
     const int i = a.perm[rp];
     const int cnt = a.surv_cnt[slot];
@@ -171,17 +168,31 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflo
     atomicAdd(&a.survivors[(slot & (NSPREAD - 1)) * SPREAD_STRIDE], (unsigned long long)nsurv);
 }
 
+// one wave per row
+template <int E>
+__global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflow_list)
+{
+    const int64_t slot = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (slot < a.n_rows) rescore_row<E>(a, slot, overflow_list);
+}
+
+// device-sized: a fixed grid of waves strides over the launch's rows
+template <int E>
+__global__ __launch_bounds__(256) void k_rescore_dev(RescoreArgs a, int32_t* overflow_list)
+{
+    const int64_t n = a.desc->n_rows;
+    for (int64_t slot = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); slot < n;
+         slot += (int64_t)gridDim.x * 4)
+        rescore_row<E>(a, slot, overflow_list);
+}
+
 // Exact top-k of one row over every point of its instance outside its
 // component, by a full FP64 scan (one workgroup per overflowed row).
-__global__ __launch_bounds__(256) void k_fallback(RescoreArgs a, const int32_t* overflow_list,
-                                                  int n_over)
+__device__ __forceinline__ void fallback_row(const RescoreArgs& a, int64_t slot)
 {
     __shared__ double ws_s[4];
     __shared__ int ws_j[4], ws_t[4];
     __shared__ int winner;
-    const int b = blockIdx.x;
-    if (b >= n_over) return;
-    const int64_t slot = overflow_list[b];
     const int rp = a.rows ? a.rows[slot] : a.row0 + (int)slot;
     const int i = a.perm[rp];
     const int ci = a.comp[i];
@@ -261,19 +272,42 @@ __global__ __launch_bounds__(256) void k_fallback(RescoreArgs a, const int32_t* 
     }
 }
 
+__global__ __launch_bounds__(256) void k_fallback(RescoreArgs a, const int32_t* overflow_list,
+                                                  int n_over)
+{
+    if ((int)blockIdx.x < n_over) fallback_row(a, overflow_list[blockIdx.x]);
+}
+
+// device-sized: a fixed grid strides over the *n_over rows
+__global__ __launch_bounds__(256) void k_fallback_dev(RescoreArgs a, const int32_t* overflow_list,
+                                                      const int32_t* n_over)
+{
+    const int n = *n_over;
+    for (int b = blockIdx.x; b < n; b += gridDim.x) {
+        __syncthreads();   // the previous row's reads of the shared winner are done
+        fallback_row(a, overflow_list[b]);
+    }
+}
+
 }  // namespace
+
+template <int E>
+void rescore_e(const RescoreArgs& a, int32_t* overflow_list, hipStream_t s)
+{
+    if (a.desc) k_rescore_dev<E><<<2048, 256, 0, s>>>(a, overflow_list);
+    else k_rescore<E><<<(unsigned)((a.n_rows + 3) / 4), 256, 0, s>>>(a, overflow_list);
+}
 
 hipError_t launch_rescore(const RescoreArgs& a, int32_t* overflow_list, hipStream_t s)
 {
-    if (a.n_rows <= 0) return hipSuccess;
-    unsigned g = (unsigned)((a.n_rows + 3) / 4);
+    if (!a.desc && a.n_rows <= 0) return hipSuccess;
     switch (a.S / 64) {
-    case 1: k_rescore<1><<<g, 256, 0, s>>>(a, overflow_list); break;
-    case 2: k_rescore<2><<<g, 256, 0, s>>>(a, overflow_list); break;
-    case 4: k_rescore<4><<<g, 256, 0, s>>>(a, overflow_list); break;
-    case 8: k_rescore<8><<<g, 256, 0, s>>>(a, overflow_list); break;
-    case 16: k_rescore<16><<<g, 256, 0, s>>>(a, overflow_list); break;
-    case 32: k_rescore<32><<<g, 256, 0, s>>>(a, overflow_list); break;
+    case 1: rescore_e<1>(a, overflow_list, s); break;
+    case 2: rescore_e<2>(a, overflow_list, s); break;
+    case 4: rescore_e<4>(a, overflow_list, s); break;
+    case 8: rescore_e<8>(a, overflow_list, s); break;
+    case 16: rescore_e<16>(a, overflow_list, s); break;
+    case 32: rescore_e<32>(a, overflow_list, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -284,6 +318,13 @@ hipError_t launch_fallback(const RescoreArgs& a, const int32_t* overflow_list, i
 {
     if (n_over <= 0) return hipSuccess;
     k_fallback<<<(unsigned)n_over, 256, 0, s>>>(a, overflow_list, n_over);
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback_dev(const RescoreArgs& a, const int32_t* overflow_list,
+                               const int32_t* n_over, hipStream_t s)
+{
+    k_fallback_dev<<<1024, 256, 0, s>>>(a, overflow_list, n_over);
     return hipGetLastError();
 }
 

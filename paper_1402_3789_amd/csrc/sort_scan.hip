@@ -205,6 +205,51 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t* p, int32_t v, int64_t
     if (i < n) p[i] = v;
 }
 
+// p[0 .. d->n_rows) = v over a fixed grid
+__global__ __launch_bounds__(256) void k_fill_i32_desc(int32_t* p, int32_t v, const LaunchDesc* d)
+{
+    const int64_t n = d->n_rows;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Column splits per row tile for a launch of `tiles` tiles: enough
+// workgroups for `target` in all, at most one split per 65536 columns and
+// at most 64 (the host's rule for host-sized launches).
+__device__ __forceinline__ int32_t splits_for(int64_t tiles, int64_t np, int32_t target, int32_t fixed)
+{
+    if (fixed > 0) return fixed;
+    if (tiles < 1) tiles = 1;
+    int64_t want = (target + tiles - 1) / tiles;
+    const int64_t cap = np / 65536;
+    if (want > cap) want = cap;
+    if (want < 1) want = 1;
+    if (want > 64) want = 64;
+    return (int32_t)want;
+}
+
+__global__ __launch_bounds__(64) void k_desc_rows(LaunchDesc* d, const int32_t* count, int32_t off,
+                                                  int32_t cap, int64_t np, int32_t target,
+                                                  int32_t fixed)
+{
+    if (threadIdx.x != 0) return;
+    int32_t n = *count - off;
+    n = n < 0 ? 0 : (n > cap ? cap : n);
+    d->n_rows = n;
+    d->n_tiles = (n + 255) / 256;
+    d->splits = splits_for(d->n_tiles, np, target, fixed);
+    d->queue = 0;
+    d->over = 0;
+}
+
+__global__ __launch_bounds__(64) void k_desc_splits(LaunchDesc* d, int64_t np, int32_t target,
+                                                    int32_t fixed)
+{
+    if (threadIdx.x != 0) return;
+    d->splits = splits_for(d->n_tiles, np, target, fixed);
+}
+
 __global__ __launch_bounds__(256) void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t n)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -301,6 +346,26 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     k_fill_i32<<<g256(n), 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32_desc(int32_t* p, int32_t v, const LaunchDesc* d, hipStream_t s)
+{
+    k_fill_i32_desc<<<1024, 256, 0, s>>>(p, v, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_desc_rows(LaunchDesc* d, const int32_t* count, int32_t off, int32_t cap,
+                            int64_t np, int32_t target, int32_t fixed_splits, hipStream_t s)
+{
+    k_desc_rows<<<1, 64, 0, s>>>(d, count, off, cap, np, target, fixed_splits);
+    return hipGetLastError();
+}
+
+hipError_t launch_desc_splits(LaunchDesc* d, int64_t np, int32_t target, int32_t fixed_splits,
+                              hipStream_t s)
+{
+    k_desc_splits<<<1, 64, 0, s>>>(d, np, target, fixed_splits);
     return hipGetLastError();
 }
 

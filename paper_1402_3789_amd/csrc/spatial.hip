@@ -592,12 +592,23 @@ __global__ __launch_bounds__(256) void k_inst_records(const int32_t* __restrict_
     rec[q] = r;
 }
 
+// nb rows, or (desc) the first desc->n_rows of the nb row slots; the rest
+// of the slots are flagged 0
 __global__ __launch_bounds__(256) void k_tile_flags(const int32_t* __restrict__ rows, int32_t row0,
                                                     int64_t nb, const int32_t* __restrict__ off,
-                                                    int ninst, int bm, int32_t* __restrict__ flag)
+                                                    int ninst, int bm, int32_t* __restrict__ flag,
+                                                    const LaunchDesc* __restrict__ desc)
 {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= nb) return;
+    if (desc) {
+        const int64_t nr = desc->n_rows;
+        if (r >= nr) {
+            flag[r] = 0;
+            return;
+        }
+        nb = nr;
+    }
     const int64_t p = rows ? rows[r] : row0 + r;
     const int b = instance_of(off, ninst, p);
     const int64_t st = first_row_at(rows, row0, nb, off[b]);
@@ -607,9 +618,14 @@ __global__ __launch_bounds__(256) void k_tile_flags(const int32_t* __restrict__ 
 __global__ __launch_bounds__(256) void k_tile_desc(const int32_t* __restrict__ tstart, int ntiles,
                                                    const int32_t* __restrict__ rows, int32_t row0,
                                                    int64_t nb, const int32_t* __restrict__ off,
-                                                   int ninst, int bm, int4* __restrict__ tiles)
+                                                   int ninst, int bm, int4* __restrict__ tiles,
+                                                   const LaunchDesc* __restrict__ desc)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (desc) {
+        ntiles = desc->n_tiles;
+        nb = desc->n_rows;
+    }
     if (t >= ntiles) return;
     const int64_t rbeg = tstart[t];
     const int64_t p = rows ? rows[rbeg] : row0 + rbeg;
@@ -683,8 +699,24 @@ hipError_t launch_tiles(const int32_t* rows, int32_t row0, int64_t nb, const int
                         int bm, int32_t* flag, int32_t* tstart, int32_t* ntiles_dev, void* scan_temp,
                         hipStream_t s)
 {
-    k_tile_flags<<<g256(nb), 256, 0, s>>>(rows, row0, nb, off, ninst, bm, flag);
+    k_tile_flags<<<g256(nb), 256, 0, s>>>(rows, row0, nb, off, ninst, bm, flag, nullptr);
     return launch_compact(flag, nb, tstart, ntiles_dev, scan_temp, s);
+}
+
+hipError_t launch_tiles_dev(const int32_t* rows, int64_t cap, const int32_t* off, int ninst, int bm,
+                            int32_t* flag, int32_t* tstart, LaunchDesc* d, void* scan_temp,
+                            hipStream_t s)
+{
+    k_tile_flags<<<g256(cap), 256, 0, s>>>(rows, 0, cap, off, ninst, bm, flag, d);
+    return launch_compact(flag, cap, tstart, &d->n_tiles, scan_temp, s);
+}
+
+hipError_t launch_tile_desc_dev(const int32_t* tstart, int max_tiles, const int32_t* rows,
+                                const int32_t* off, int ninst, int bm, int4* tiles,
+                                const LaunchDesc* d, hipStream_t s)
+{
+    k_tile_desc<<<g256(max_tiles), 256, 0, s>>>(tstart, max_tiles, rows, 0, 0, off, ninst, bm, tiles, d);
+    return hipGetLastError();
 }
 
 hipError_t launch_tile_desc(const int32_t* tstart, int ntiles, const int32_t* rows, int32_t row0,
@@ -692,7 +724,8 @@ hipError_t launch_tile_desc(const int32_t* tstart, int ntiles, const int32_t* ro
                             hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    k_tile_desc<<<g256(ntiles), 256, 0, s>>>(tstart, ntiles, rows, row0, nb, off, ninst, bm, tiles);
+    k_tile_desc<<<g256(ntiles), 256, 0, s>>>(tstart, ntiles, rows, row0, nb, off, ninst, bm, tiles,
+                                             nullptr);
     return hipGetLastError();
 }
 
