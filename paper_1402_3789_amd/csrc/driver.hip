@@ -67,6 +67,7 @@ struct Plan {
     int64_t rmax = 0;               // rows per candidate launch
     int op_bytes = 64;
     bool mst = true;
+    int S_global = 256;             // survivor cap of the global frame
     int L1 = 1, L2 = 1;             // fine / coarse landmarks of the spatial order
     int ninst = 1;                  // instances in the point set (batched calls)
     bool local = false;             // BF16 operands built per tile from FP32 (not exact data)
@@ -244,10 +245,15 @@ nnm_status plan_common(int64_t n, int32_t d, int32_t k, const nnm_options* opt, 
     if (S < 64) S = 64;
     if (S > SMAX) S = SMAX;
     S = pow2_at_least(S);
+    p->S_global = S;
+    // BF16 on data that is not an integer grid builds its operands per tile
+    // (see stage); its margin is wider, so it keeps 4x the survivors per row
+    if (o.precision == NNM_PREC_BF16 && o.survivor_cap <= 0) S = S * 4 < SMAX ? S * 4 : SMAX;
     p->S = S;
-    // survivor buffers of 2^29 entries (4 GB): 2M rows at S = 256 in one
-    // launch (a split launch pays two tails and narrower column splits)
-    int64_t rmax = ((int64_t)1 << 29) / S;
+    // survivor buffers of at most 2^30 entries (8 GB; 12 GB with the BF16
+    // bounds): 4M rows at S = 256 in one launch (a split launch pays two
+    // tails and narrower column splits)
+    int64_t rmax = ((int64_t)1 << 30) / S;
     if (rmax > n) rmax = n;
     if (rmax < 1) rmax = 1;
     p->rmax = rmax;
@@ -356,14 +362,9 @@ nnm_status stage(Run& R, const float* X)
     // BF16 keeps 8 bits: relative to the data's centre its error would swamp
     // nearest-neighbour distances, so its operands are built per tile
     p.local = p.opkind == OP_BF16 && !p.exact;
-    if (p.local && R.o.survivor_cap <= 0) {
-        // BF16's margin is wider: keep 4x the survivors per row (the
-        // survivor buffers hold 2^29 entries whatever the split into rows)
-        const int S4 = p.S * 4 < SMAX ? p.S * 4 : SMAX;
-        p.rmax = p.rmax * p.S / S4;
-        if (p.rmax < 1) p.rmax = 1;
-        p.S = S4;
-    }
+    // BF16 on an integer grid is exact in the global frame: the global cap
+    // (the buffers were sized for the larger per-tile one)
+    if (!p.local) p.S = p.S_global;
     p.op_bytes = (p.opkind == OP_FP8) ? 32 : 64;
     R.bc = BoundConst{};
     R.sigma = 1.f;
@@ -734,7 +735,9 @@ nnm_status scan_batch_dev(Run& R, const float* X, const int32_t* rows, const int
     LaunchDesc* D = w.desc;
     const int32_t cap = (int32_t)p.rmax;
     const int32_t target = u0 ? 8192 : 4096;
-    HIP_TRY(launch_desc_rows(D, count, off, cap, p.n, target, R.o.col_splits, R.s));
+    const bool use_tfin = !use32 && !p.local;
+    HIP_TRY(launch_prep_launch(D, count, off, cap, p.n, target, R.o.col_splits, w.surv_cnt,
+                               use_tfin ? w.tfin : nullptr, w.gT, w.gU, R.s));
     const int32_t* lrows = rows + off;
     CandArgs a{};
     a.opR = w.opRs;
@@ -777,12 +780,7 @@ nnm_status scan_batch_dev(Run& R, const float* X, const int32_t* rows, const int
     a.share = 1;
     a.gT = w.gT;
     a.gU = w.gU;
-    const bool use_tfin = !use32 && !p.local;
     a.tfin = use_tfin ? w.tfin : nullptr;
-    HIP_TRY(launch_fill_i32_desc(w.surv_cnt, 0, D, R.s));
-    if (use_tfin) HIP_TRY(launch_fill_i32_desc((int32_t*)w.tfin, 0x7F800000, D, R.s));
-    HIP_TRY(launch_fill_i32_desc((int32_t*)w.gT, 0x7F800000, D, R.s));
-    HIP_TRY(launch_fill_i32_desc((int32_t*)w.gU, 0x7F800000, D, R.s));
     if (use32) HIP_TRY(launch_cand_fp32(a, R.s));
     else HIP_TRY(launch_cand_mfma(p.opkind, a, R.s));
     RescoreArgs r{};
@@ -840,21 +838,18 @@ nnm_status scan_rows_dev(Run& R, const float* X, const int32_t* rows, const int3
     Plan& p = R.p;
     WS& w = R.w;
     int32_t* on = &w.ctr->dc[3];
+    // oflag is all zero here and after every compaction below
     for (int64_t b0 = 0; b0 < p.n; b0 += p.rmax) {
-        HIP_TRY(launch_fill_i32(w.oflag, 0, p.n, R.s));
         nnm_status st = scan_batch_dev(R, X, rows, count, (int32_t)b0, kk, use_u0 ? w.u0s : nullptr,
                                        p.opkind == OP_FP32, 1);
         if (st != NNM_OK) return st;
         if (R.o.force_fallback) continue;
         for (int pass = 1; pass <= DEV_PASSES; ++pass) {
-            HIP_TRY(launch_compact(w.oflag, p.n, w.olist, on, w.scan_temp, R.s));
-            HIP_TRY(launch_fill_i32(w.oflag, 0, p.n, R.s));
+            HIP_TRY(launch_compact_clear(w.oflag, p.n, w.olist, on, w.scan_temp, R.s));
+            // the rows overflowed in this batch: at most rmax of them
             const bool use32 = p.opkind == OP_FP32 || (!p.exact && pass >= 2);
-            for (int64_t c0 = 0; c0 < p.n; c0 += p.rmax) {
-                st = scan_batch_dev(R, X, w.olist, on, (int32_t)c0, kk, w.u0b, use32,
-                                    pass == DEV_PASSES ? 2 : 1);
-                if (st != NNM_OK) return st;
-            }
+            st = scan_batch_dev(R, X, w.olist, on, 0, kk, w.u0b, use32, pass == DEV_PASSES ? 2 : 1);
+            if (st != NNM_OK) return st;
         }
     }
     return NNM_OK;

@@ -302,6 +302,11 @@ hipError_t launch_fallback_dev(const RescoreArgs& a, const int32_t* overflow_lis
 // queue and overflow count cleared.
 hipError_t launch_desc_rows(LaunchDesc* d, const int32_t* count, int32_t off, int32_t cap,
                             int64_t np, int32_t target, int32_t fixed_splits, hipStream_t s);
+// launch_desc_rows, and the first n_rows entries of surv_cnt (0) and of
+// tfin (if not NULL), gT and gU (+inf) set, in one launch
+hipError_t launch_prep_launch(LaunchDesc* d, const int32_t* count, int32_t off, int32_t cap,
+                              int64_t np, int32_t target, int32_t fixed_splits, int32_t* surv_cnt,
+                              uint32_t* tfin, uint32_t* gT, uint32_t* gU, hipStream_t s);
 // After tile descriptors were built: splits from d->n_tiles.
 hipError_t launch_desc_splits(LaunchDesc* d, int64_t np, int32_t target, int32_t fixed_splits,
                               hipStream_t s);
@@ -365,6 +370,9 @@ hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n,
                                  void* temp, int32_t* total, hipStream_t s);
 hipError_t launch_compact(const int32_t* flags, int64_t n, int32_t* out_list,
                           int32_t* out_count, void* temp, hipStream_t s);
+// the same, leaving every flag zero
+hipError_t launch_compact_clear(int32_t* flags, int64_t n, int32_t* out_list,
+                                int32_t* out_count, void* temp, hipStream_t s);
 size_t radix_temp_bytes(int64_t n);
 // Stable LSD sort of records by the listed key fields (0: k0, 1: k1, 2: k2),
 // least significant first; bits = significant bits of each field.

@@ -86,12 +86,16 @@ __global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(256) void k_compact_scatter(const int32_t* __restrict__ flags,
+// clear (may alias flags): the flags, zeroed once read
+__global__ __launch_bounds__(256) void k_compact_scatter(const int32_t* flags,
                                                          const int32_t* __restrict__ pos, int64_t n,
-                                                         int32_t* __restrict__ out)
+                                                         int32_t* __restrict__ out, int32_t* clear)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n && flags[i]) out[pos[i]] = (int32_t)i;
+    if (i < n && flags[i]) {
+        out[pos[i]] = (int32_t)i;
+        if (clear) clear[i] = 0;
+    }
 }
 
 __device__ __forceinline__ uint32_t digit_of(const SortRec& r, int field, int shift)
@@ -243,6 +247,31 @@ __global__ __launch_bounds__(64) void k_desc_rows(LaunchDesc* d, const int32_t* 
     d->over = 0;
 }
 
+// k_desc_rows and the clearing of a launch's per-row buffers in one kernel:
+// every thread derives n_rows from *count itself
+__global__ __launch_bounds__(256) void k_prep_launch(LaunchDesc* d, const int32_t* count, int32_t off,
+                                                     int32_t cap, int64_t np, int32_t target,
+                                                     int32_t fixed, int32_t* surv_cnt, uint32_t* tfin,
+                                                     uint32_t* gT, uint32_t* gU)
+{
+    int32_t n = *count - off;
+    n = n < 0 ? 0 : (n > cap ? cap : n);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d->n_rows = n;
+        d->n_tiles = (n + 255) / 256;
+        d->splits = splits_for(d->n_tiles, np, target, fixed);
+        d->queue = 0;
+        d->over = 0;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        surv_cnt[i] = 0;
+        if (tfin) tfin[i] = 0x7F800000u;
+        gT[i] = 0x7F800000u;
+        gU[i] = 0x7F800000u;
+    }
+}
+
 __global__ __launch_bounds__(64) void k_desc_splits(LaunchDesc* d, int64_t np, int32_t target,
                                                     int32_t fixed)
 {
@@ -285,7 +314,18 @@ hipError_t launch_compact(const int32_t* flags, int64_t n, int32_t* out_list, in
     int32_t* pos = (int32_t*)temp + (nb + 64);
     hipError_t e = launch_exclusive_scan(flags, pos, n, temp, out_count, s);
     if (e != hipSuccess) return e;
-    k_compact_scatter<<<g256(n), 256, 0, s>>>(flags, pos, n, out_list);
+    k_compact_scatter<<<g256(n), 256, 0, s>>>(flags, pos, n, out_list, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_clear(int32_t* flags, int64_t n, int32_t* out_list, int32_t* out_count,
+                                void* temp, hipStream_t s)
+{
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    int32_t* pos = (int32_t*)temp + (nb + 64);
+    hipError_t e = launch_exclusive_scan(flags, pos, n, temp, out_count, s);
+    if (e != hipSuccess) return e;
+    k_compact_scatter<<<g256(n), 256, 0, s>>>(flags, pos, n, out_list, flags);
     return hipGetLastError();
 }
 
@@ -359,6 +399,15 @@ hipError_t launch_desc_rows(LaunchDesc* d, const int32_t* count, int32_t off, in
                             int64_t np, int32_t target, int32_t fixed_splits, hipStream_t s)
 {
     k_desc_rows<<<1, 64, 0, s>>>(d, count, off, cap, np, target, fixed_splits);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_launch(LaunchDesc* d, const int32_t* count, int32_t off, int32_t cap,
+                              int64_t np, int32_t target, int32_t fixed_splits, int32_t* surv_cnt,
+                              uint32_t* tfin, uint32_t* gT, uint32_t* gU, hipStream_t s)
+{
+    k_prep_launch<<<1024, 256, 0, s>>>(d, count, off, cap, np, target, fixed_splits, surv_cnt, tfin,
+                                       gT, gU);
     return hipGetLastError();
 }
 
