@@ -129,7 +129,11 @@ typedef struct {
                                read per round); the graph is kept for later
                                calls with the same buffers, sizes and
                                settings.  Results are identical.             */
-    int32_t reserved[8];
+    int32_t split_target0;  /* workgroups the column splits aim at in the
+                               first round (0: 4096)                          */
+    int32_t split_target;   /* ... and in the bounded scans of later rounds
+                               (0: 8192)                                      */
+    int32_t reserved[6];
 } nnm_options;
 
 /* Per-call measurements (all optional to read; filled when non-NULL). */
@@ -271,6 +275,40 @@ nnm_status mst_batched_workspace_size(const nnm_instance *inst, int32_t count,
 nnm_status mst_build_batched(const nnm_instance *inst, int32_t count,
                              const nnm_options *opt, void *ws_dev,
                              size_t ws_bytes, void *stream, nnm_report *reps);
+
+/*
+ * Autotuner of the run options, on the caller's own data: the paper's aim of
+ * keeping the GPU fully loaded whatever the size of the task (section
+ * "Overall idea of the algorithm") depends on how the work is cut, so the
+ * cut is measured rather than fixed.  One instance (count = 1: mst_build on
+ * inst[0]) or a batch (count > 1: mst_build_batched) is built with *base and
+ * then, by coordinate descent, with each value of each knob in turn, keeping
+ * a value when it is faster:
+ *   knn_k          4, 6, 8, 12
+ *   split_target0  2048, 4096, 8192
+ *   split_target   4096, 8192, 16384
+ *   graph          0, 1
+ * Every trial's trees are compared with the first trial's, byte for byte.
+ *   inst, count   as for mst_build_batched (edges_dev receive the trees);
+ *   base          starting options (NULL = defaults; precision and the debug
+ *                 knobs are kept as given);
+ *   ws_dev        at least mst_autotune_workspace_size() bytes;
+ *   reps          timed calls per trial (the minimum counts), 1..16, after
+ *                 one untimed call;
+ *   best          host output: the fastest options found;
+ *   trial_ms      NULL, or host [NNM_TUNE_MAX_TRIALS]: wall time of each
+ *                 trial (trial 0: *base), ms;
+ *   n_trials      NULL, or host output: trials run.
+ * Errors: as for mst_build / mst_build_batched; NNM_EDEVICE also when two
+ * trials' trees differ.
+ */
+#define NNM_TUNE_MAX_TRIALS 32
+nnm_status mst_autotune_workspace_size(const nnm_instance *inst, int32_t count,
+                                       const nnm_options *base, size_t *bytes);
+nnm_status mst_autotune(const nnm_instance *inst, int32_t count,
+                        const nnm_options *base, void *ws_dev, size_t ws_bytes,
+                        void *stream, int32_t reps, nnm_options *best,
+                        double *trial_ms, int32_t *n_trials);
 
 /*
  * Constrained cut of a sorted tree (host code, synchronous).

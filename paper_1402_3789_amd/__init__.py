@@ -20,7 +20,7 @@ from . import _native as N
 from ._native import NNMError, NativeMissing, PREC  # noqa: F401
 
 __all__ = ["mst_build", "mst_build_noalloc", "knn_build", "cluster_cut", "mst_build_batched", "Tree",
-           "options", "NNMError", "NativeMissing"]
+           "options", "autotune", "NNMError", "NativeMissing"]
 
 
 def _torch():
@@ -29,7 +29,8 @@ def _torch():
 
 
 def options(precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
-            force_fallback=False, col_splits=0, fixed_chunks=False, graph=False) -> N.Options:
+            force_fallback=False, col_splits=0, fixed_chunks=False, graph=False,
+            split_target0=0, split_target=0) -> N.Options:
     o = N.Options()
     N.lib().nnm_default_options(ctypes.byref(o))
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
@@ -40,7 +41,24 @@ def options(precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
     o.col_splits = int(col_splits)
     o.fixed_chunks = int(bool(fixed_chunks))
     o.graph = int(bool(graph))
+    o.split_target0 = int(split_target0)
+    o.split_target = int(split_target)
     return o
+
+
+def _tuned(tuned, n, d, precision, count, kw):
+    """Fill the knobs the caller left at 0 from the autotuner's cache."""
+    if not tuned:
+        return kw
+    from . import autotune
+    ent = autotune.lookup(n, d, precision, count=count, cache=None if tuned is True else tuned)
+    if ent is None:
+        return kw
+    out = dict(kw)
+    for key in autotune.KNOBS:
+        if not out.get(key):
+            out[key] = ent[key]
+    return out
 
 
 def _stream(stream=None):
@@ -116,15 +134,22 @@ class Tree:
 
 def mst_build(X, precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
               force_fallback=False, col_splits=0, stream=None, workspace=None,
-              fixed_chunks=False, graph=False) -> Tree:
+              fixed_chunks=False, graph=False, split_target0=0, split_target=0,
+              tuned=False) -> Tree:
     """Exact key-ordered minimum spanning tree of the rows of X (device).
     graph=True replays the merge rounds after the first from a captured
-    hipGraph (kept for later calls with the same buffers and settings)."""
+    hipGraph (kept for later calls with the same buffers and settings).
+    tuned=True (or a cache path) takes k, the split targets and graph replay
+    from the autotuner's cache entry for this size, where the caller left
+    them at 0."""
     torch = _torch()
     n, d, ld = _check_x(X)
     L = N.lib()
-    o = options(precision, knn_k, survivor_cap, disable_prune, force_fallback, col_splits,
-                fixed_chunks, graph)
+    kw = _tuned(tuned, n, d, precision, 1, dict(knn_k=knn_k, graph=graph,
+                                                  split_target0=split_target0,
+                                                  split_target=split_target))
+    o = options(precision, kw["knn_k"], survivor_cap, disable_prune, force_fallback, col_splits,
+                fixed_chunks, kw["graph"], kw["split_target0"], kw["split_target"])
     nb = ctypes.c_size_t(0)
     N.check("mst_workspace_size", L.mst_workspace_size(n, d, ctypes.byref(o), ctypes.byref(nb)))
     ws = (workspace or _WS).get(nb.value, X.device)
@@ -180,12 +205,9 @@ def knn_build(X, k=16, precision="auto", survivor_cap=0, force_fallback=False,
     return idx, s, ln
 
 
-def mst_build_batched(Xs, precision="auto", knn_k=0, survivor_cap=0, force_fallback=False,
-                      stream=None, workspace=None, col_splits=0, graph=False):
-    """Independent trees of many instances in one call; list of Tree."""
+def _instances(Xs):
+    """Instance descriptors and output buffers for a list of inputs."""
     torch = _torch()
-    L = N.lib()
-    o = options(precision, knn_k, survivor_cap, False, force_fallback, col_splits, False, graph)
     inst = (N.Instance * len(Xs))()
     outs = []
     for b, X in enumerate(Xs):
@@ -197,6 +219,23 @@ def mst_build_batched(Xs, precision="auto", knn_k=0, survivor_cap=0, force_fallb
         inst[b].d = d
         inst[b].ld = ld
         inst[b].edges_dev = e.data_ptr()
+    return inst, outs
+
+
+def mst_build_batched(Xs, precision="auto", knn_k=0, survivor_cap=0, force_fallback=False,
+                      stream=None, workspace=None, col_splits=0, graph=False, split_target0=0,
+                      split_target=0, tuned=False):
+    """Independent trees of many instances in one call; list of Tree."""
+    torch = _torch()
+    L = N.lib()
+    ntot = sum(int(X.shape[0]) for X in Xs)
+    dmax = max((int(X.shape[1]) for X in Xs), default=1)
+    kw = _tuned(tuned, ntot, dmax, precision, len(Xs), dict(knn_k=knn_k, graph=graph,
+                                                            split_target0=split_target0,
+                                                            split_target=split_target))
+    o = options(precision, kw["knn_k"], survivor_cap, False, force_fallback, col_splits, False,
+                kw["graph"], kw["split_target0"], kw["split_target"])
+    inst, outs = _instances(Xs)
     nb = ctypes.c_size_t(0)
     N.check("mst_batched_workspace_size",
             L.mst_batched_workspace_size(inst, len(Xs), ctypes.byref(o), ctypes.byref(nb)))

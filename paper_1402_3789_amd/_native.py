@@ -17,6 +17,7 @@ NNM_ENONFINITE = -4
 NNM_EUNSUPPORTED = -5
 NNM_ETOOLARGE = -6
 NOALLOC_SCRATCH_BYTES = 128 << 20
+TUNE_MAX_TRIALS = 32
 
 PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "auto": 3, "fp16": 4}
 PREC_NAME = {v: k for k, v in PREC.items()}
@@ -38,7 +39,8 @@ class Options(ctypes.Structure):
                 ("survivor_cap", ctypes.c_int32), ("disable_prune", ctypes.c_int32),
                 ("force_fallback", ctypes.c_int32), ("col_splits", ctypes.c_int32),
                 ("fixed_chunks", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("split_target0", ctypes.c_int32), ("split_target", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class Report(ctypes.Structure):
@@ -105,6 +107,14 @@ _SIG = {
                                          ctypes.POINTER(Options), ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_void_p,
                                          ctypes.POINTER(Report)]),
+    "mst_autotune_workspace_size": (ctypes.c_int, [ctypes.POINTER(Instance), ctypes.c_int32,
+                                                   ctypes.POINTER(Options),
+                                                   ctypes.POINTER(ctypes.c_size_t)]),
+    "mst_autotune": (ctypes.c_int, [ctypes.POINTER(Instance), ctypes.c_int32,
+                                    ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Options),
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int32)]),
     "cluster_cut": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(CutParams),
                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
 }

@@ -500,7 +500,8 @@ int pick_splits(const Run& R, int64_t rows, bool bounded)
     if (R.o.col_splits > 0) return R.o.col_splits;
     const int64_t bm = 256;
     const int64_t tiles = (rows + bm - 1) / bm;
-    const int64_t target = bounded ? 8192 : 4096;
+    const int64_t target = bounded ? (R.o.split_target > 0 ? R.o.split_target : 8192)
+                                   : (R.o.split_target0 > 0 ? R.o.split_target0 : 4096);
     int64_t want = (target + tiles - 1) / tiles;
     int64_t cap = R.p.n / 65536;
     if (want > cap) want = cap;
@@ -734,7 +735,8 @@ nnm_status scan_batch_dev(Run& R, const float* X, const int32_t* rows, const int
     WS& w = R.w;
     LaunchDesc* D = w.desc;
     const int32_t cap = (int32_t)p.rmax;
-    const int32_t target = u0 ? 8192 : 4096;
+    const int32_t target = u0 ? (R.o.split_target > 0 ? R.o.split_target : 8192)
+                              : (R.o.split_target0 > 0 ? R.o.split_target0 : 4096);
     const bool use_tfin = !use32 && !p.local;
     HIP_TRY(launch_prep_launch(D, count, off, cap, p.n, target, R.o.col_splits, w.surv_cnt,
                                use_tfin ? w.tfin : nullptr, w.gT, w.gU, R.s));

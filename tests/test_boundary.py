@@ -231,3 +231,45 @@ def test_cut_large_forest_path_matches_oracle():
     got, k = nnm.cluster_cut((u, v, s, w), n, kl1=100, kl4=3)
     exp, ke = oracle.cut(u, v, s, w, n, 100, -1, -1, 3, math.inf)
     assert k == ke and np.array_equal(got, exp)
+
+
+def test_autotune_rejects_bad_arguments_before_device_work():
+    L = N.lib()
+    o = nnm.options("fp16")
+    inst = (N.Instance * 1)()
+    inst[0].X_dev = 1234
+    inst[0].n = 100
+    inst[0].d = 4
+    inst[0].ld = 4
+    inst[0].edges_dev = 5678
+    best = N.Options()
+    nb = ctypes.c_size_t(0)
+    assert L.mst_autotune_workspace_size(inst, 1, ctypes.byref(o), ctypes.byref(nb)) == N.NNM_OK
+    assert nb.value > 0
+    # null workspace, reps out of range, short workspace, empty batch
+    assert L.mst_autotune(inst, 1, ctypes.byref(o), None, nb.value, None, 1, ctypes.byref(best),
+                          None, None) == N.NNM_EINVAL
+    assert L.mst_autotune(inst, 1, ctypes.byref(o), ctypes.c_void_p(1), nb.value, None, 0,
+                          ctypes.byref(best), None, None) == N.NNM_EINVAL
+    assert L.mst_autotune(inst, 1, ctypes.byref(o), ctypes.c_void_p(1), nb.value - 1, None, 1,
+                          ctypes.byref(best), None, None) == N.NNM_EINVAL
+    assert L.mst_autotune(inst, 0, ctypes.byref(o), ctypes.c_void_p(1), nb.value, None, 1,
+                          ctypes.byref(best), None, None) == N.NNM_EINVAL
+    inst[0].d = 40
+    assert L.mst_autotune_workspace_size(inst, 1, ctypes.byref(o), ctypes.byref(nb)) == N.NNM_EINVAL
+
+
+def test_autotune_cache_keys_and_store(tmp_path):
+    from paper_1402_3789_amd import autotune as A
+    k1 = A.bucket_key(2_000_000, 25, "fp16", 1, "gfx950")
+    assert k1 == "gfx950|fp16|n1048576|d26|single"
+    assert A.bucket_key(3_000, 4, "bf16", 10, "gfx950") == "gfx950|bf16|n4096|d8|batch"
+    assert A.bucket_key(1, 32, "fp32", 1, "gfx950") == "gfx950|fp32|n1|d32|single"
+    path = str(tmp_path / "c.json")
+    assert A.lookup(2_000_000, 25, "fp16", cache=path, arch_name="gfx950") is None
+    ent = {"knn_k": 8, "split_target0": 2048, "split_target": 16384, "graph": 1, "ms": 1.0}
+    A._store(path, k1, ent)
+    A._store(path, A.bucket_key(5000, 9, "fp16", 1, "gfx950"), dict(ent, knn_k=4))
+    assert A.lookup(1_900_000, 26, "fp16", cache=path, arch_name="gfx950") == ent
+    assert A.lookup(1_900_000, 26, "fp16", cache=path, arch_name="gfx942") is None
+    assert A.lookup(4096, 12, "fp16", cache=path, arch_name="gfx950")["knn_k"] == 4
