@@ -98,6 +98,51 @@ def cpu_baseline(X, seconds):
                       f"evaluated once), {t1:.1f} s"}
 
 
+def batch_section(nnm, torch, steps):
+    """The batching workload: 256 instances (N log-uniform in [1024, 65536],
+    D in 4..25) in one mst_build_batched call, trees left in HBM; default
+    options and the autotuner's entries (cache, else the shipped table), each
+    compared with the oracle's per-instance tree digests."""
+    import numpy as np
+    from workloads import batch256
+    from paper_1402_3789_amd import autotune
+    Xs = batch256(0)
+    Xd = [torch.from_numpy(x).to("cuda:0") for x in Xs]
+    pairs = sum(x.shape[0] * (x.shape[0] - 1) / 2.0 for x in Xs)
+    gp = os.path.join(ROOT, "tests", "golden", "batch256_oracle.json")
+    want = json.load(open(gp))["instances"] if os.path.exists(gp) else None
+    ntot = sum(x.shape[0] for x in Xs)
+    dmax = max(x.shape[1] for x in Xs)
+    out = {"workload": "batch256 seed 0", "instances": len(Xs), "points": ntot,
+           "timed": "mst_build_batched (all 256 trees, in HBM)"}
+    for prec, tuned in (("fp16", False), ("fp16", True), ("bf16", False), ("bf16", True)):
+        def run():
+            return nnm.mst_build_batched(Xd, precision=prec, tuned=tuned)
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            trees = run()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        match = None
+        if want is not None:
+            match = True
+            for t, w in zip(trees, want):
+                u, v, s_, w_ = t.to_numpy()
+                h = hashlib.sha256()
+                for a, ty in ((u, "<i4"), (v, "<i4"), (s_, "<f8"), (w_, "<f8")):
+                    h.update(np.ascontiguousarray(a, dtype=ty).tobytes())
+                match = match and h.hexdigest() == w["tree_sha256"]
+        ent = autotune.lookup(ntot, dmax, prec, count=len(Xs)) if tuned else None
+        name = prec + ("_tuned" if tuned else "")
+        out[name] = {"ms_per_step": round(ms, 3), "value": pairs / (ms * 1e-3),
+                     "unit": "pair-distances/s", "oracle_match": match,
+                     "options": {k: ent[k] for k in autotune.KNOBS} if ent else None}
+        log(f"[bench] batch256 {name}: {ms:.1f} ms/step, oracle digests match: {match}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +154,8 @@ def main():
                     help="timed steps of each comparison path (0 = none)")
     ap.add_argument("--compare", default="fp32,bf16",
                     help="other candidate precisions timed on the same data")
+    ap.add_argument("--batch-steps", type=int, default=2,
+                    help="timed steps of the 256-instance batched call (0 = none)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -203,6 +250,8 @@ def main():
                             "max_err_ratio": tr2.report["max_err_ratio"]}
             log(f"[bench] {prec}: {ms2:.1f} ms/step, identical tree: {same}")
 
+    batch = batch_section(nnm, torch, args.batch_steps) if args.batch_steps > 0 else None
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(X, args.cpu_seconds)
@@ -230,6 +279,7 @@ def main():
         "cpu_baseline": cpu,
         "oracle_match": match,
         "fp32_path": others.get("fp32"),
+        "batch256": batch,
         "other_paths": {k2: v2 for k2, v2 in others.items() if k2 != "fp32"},
         "report": {k2: last[k2] for k2 in ("rounds", "rows_scanned", "pairs_evaluated",
                                             "survivors", "overflow_rows", "max_abs_err",

@@ -6,7 +6,8 @@ bucket and shape (one instance or a batch).
     tree = mst_build(X, precision="fp16", tuned=True)
 
 The cache is a JSON file (``$NNM_AUTOTUNE_CACHE``, else
-``~/.cache/paper_1402_3789_amd/autotune.json``) keyed by
+``~/.cache/paper_1402_3789_amd/autotune.json``; ``tuned.json`` beside this
+module holds entries measured on an MI355X for buckets the cache lacks) keyed by
 ``arch|precision|n-bucket|d-bucket|single-or-batch``: n rounded to a power
 of four, d to 8, 16, 26 or 32.  Every result is exact whatever the options,
 so a stale or foreign entry can only cost time.
@@ -62,10 +63,20 @@ def _store(path: str, key: str, entry: dict) -> None:
     os.replace(tmp, path)
 
 
+# entries measured with this package's tuner on an MI355X (gfx950), used
+# where the cache has no entry of its own for a bucket
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
 def lookup(n: int, d: int, precision: str = "auto", count: int = 1, cache: str | None = None,
-           arch_name: str | None = None):
-    """The cached entry for this size and shape, or None."""
-    return _load(cache or default_cache()).get(bucket_key(n, d, precision, count, arch_name))
+           arch_name: str | None = None, shipped: bool = True):
+    """The cached entry for this size and shape (the cache file first, then
+    the shipped table), or None."""
+    key = bucket_key(n, d, precision, count, arch_name)
+    ent = _load(cache or default_cache()).get(key)
+    if ent is None and shipped:
+        ent = _load(SHIPPED).get(key)
+    return ent
 
 
 def tune(X, precision: str = "auto", reps: int = 3, cache: str | None = None, save: bool = True,

@@ -266,10 +266,16 @@ def test_autotune_cache_keys_and_store(tmp_path):
     assert A.bucket_key(3_000, 4, "bf16", 10, "gfx950") == "gfx950|bf16|n4096|d8|batch"
     assert A.bucket_key(1, 32, "fp32", 1, "gfx950") == "gfx950|fp32|n1|d32|single"
     path = str(tmp_path / "c.json")
-    assert A.lookup(2_000_000, 25, "fp16", cache=path, arch_name="gfx950") is None
+    assert A.lookup(2_000_000, 25, "fp16", cache=path, arch_name="gfx950", shipped=False) is None
     ent = {"knn_k": 8, "split_target0": 2048, "split_target": 16384, "graph": 1, "ms": 1.0}
     A._store(path, k1, ent)
     A._store(path, A.bucket_key(5000, 9, "fp16", 1, "gfx950"), dict(ent, knn_k=4))
     assert A.lookup(1_900_000, 26, "fp16", cache=path, arch_name="gfx950") == ent
     assert A.lookup(1_900_000, 26, "fp16", cache=path, arch_name="gfx942") is None
+    # the shipped table: every entry names a knob value of the tuner's grid
+    import json
+    for key, e in json.load(open(A.SHIPPED)).items():
+        assert key.startswith("gfx950|") and e["knn_k"] in (0, 4, 6, 8, 12)
+        assert e["split_target0"] in (0, 2048, 4096, 8192)
+        assert e["split_target"] in (0, 4096, 8192, 16384) and e["graph"] in (0, 1)
     assert A.lookup(4096, 12, "fp16", cache=path, arch_name="gfx950")["knn_k"] == 4

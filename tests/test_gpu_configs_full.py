@@ -106,15 +106,18 @@ def _labels_digest(labels):
     return hashlib.sha256(np.ascontiguousarray(labels, "<i4").tobytes()).hexdigest()
 
 
-@pytest.mark.parametrize("prec", ["auto", "fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["auto", "fp32", "bf16", "fp16-graph", "bf16-tuned"])
 def test_batch256_full_size(nnm, batch, prec):
     """All 256 instances in one batched call: every tree, and every cut at
     KL1 = the instance's own component count, identical to the oracle's
-    (digests written by tests/golden/make_fullsize_digests.py)."""
+    (digests written by tests/golden/make_fullsize_digests.py); also with the
+    rounds replayed from the round graph, and with the autotuner's options."""
     Xs, want = batch
     sizes = np.array([x.shape[0] for x in Xs])
     _say("batch256", prec, len(Xs), "instances,", int(sizes.sum()), "points")
-    trees = nnm.mst_build_batched([torch.from_numpy(x).to("cuda:0") for x in Xs], precision=prec)
+    p, _, how = prec.partition("-")
+    trees = nnm.mst_build_batched([torch.from_numpy(x).to("cuda:0") for x in Xs], precision=p,
+                                  graph=how == "graph", tuned=how == "tuned")
     torch.cuda.synchronize()
     host = [t.to_numpy() for t in trees]
     bad = [b for b, (h, wi) in enumerate(zip(host, want)) if _tree_digest(*h) != wi["tree_sha256"]]
