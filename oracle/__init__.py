@@ -51,6 +51,9 @@ def _load():
     lib.oracle_cut.argtypes = [vp, vp, vp, vp, i64, i64, i64, i64, i64, dbl, _i32p,
                                ctypes.POINTER(i64)]
     lib.oracle_cut.restype = c_int
+    lib.oracle_cut_allpairs.argtypes = [_f32p, i64, i32, i64, i64, i64, i64, i64, dbl, _i32p,
+                                         ctypes.POINTER(i64)]
+    lib.oracle_cut_allpairs.restype = c_int
     lib.oracle_knn.argtypes = [_f32p, i64, i32, i64, vp, i64, i32, _i32p, _f64p, _i32p, c_int]
     lib.oracle_knn.restype = c_int
     lib.oracle_nn_outside.argtypes = [_f32p, i64, i32, i64, vp, vp, i64, _i32p, _f64p, c_int]
@@ -107,6 +110,20 @@ def cut(u, v, s, w, n, kl1=0, kl2=-1, kl3=-1, kl4=0, dmax=float("inf")):
                             int(kl3), int(kl4), float(dmax), labels, ctypes.byref(k))
     if rc != 0:
         raise ValueError(f"oracle_cut failed ({rc})")
+    return labels[: int(n)], int(k.value)
+
+
+def cut_allpairs(X, kl1=0, kl2=-1, kl3=-1, kl4=0, dmax=float("inf")):
+    """The constrained process over all pairs of points (not only tree
+    edges); returns (labels int32, K).  O(n^2) memory: small n only."""
+    X = _as_x(X)
+    n, d = X.shape
+    labels = np.zeros(max(int(n), 1), np.int32)
+    k = ctypes.c_int64(0)
+    rc = _load().oracle_cut_allpairs(X, int(n), int(d), int(d), int(kl1), int(kl2), int(kl3),
+                                     int(kl4), float(dmax), labels, ctypes.byref(k))
+    if rc != 0:
+        raise ValueError(f"oracle_cut_allpairs failed ({rc})")
     return labels[: int(n)], int(k.value)
 
 

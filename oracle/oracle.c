@@ -39,6 +39,10 @@
  *      4. otherwise the two clusters are united.
  *    Labels are numbered 0..K-1 in order of first appearance over i = 0..N-1.
  *
+ *  - The same settings applied to every pair of points (the process itself
+ *    rather than a cut of its tree): oracle_cut_allpairs.  It equals the
+ *    cut of the tree whenever KL2 and KL3 are off.
+ *
  *  - Exact k nearest neighbours and the exact nearest neighbour outside a
  *    given labelling, both by the same key, used to check samples of large
  *    runs one row at a time.
@@ -313,6 +317,92 @@ int oracle_cut(const int32_t *eu, const int32_t *ev, const double *es,
     }
     *n_clusters = next;
     free(par); free(sz); free(heap); free(map);
+    return ORACLE_OK;
+}
+
+/* ---- the constrained process over all pairs ----------------------------- */
+
+/*
+ * The clustering process of the section "General description of the
+ * algorithm for constructing the set of minimum distances" with the
+ * settings of "Problem settings" applied to every pair of points, not only
+ * to tree edges: at each step the admissible pair of points in two
+ * different clusters with the smallest (class, key) is taken and its two
+ * clusters are united, until the number of clusters is <= KL1 (KL1 <= 0:
+ * off) or no admissible pair is left.  A pair of clusters A, B is
+ * admissible when sqrt(s) <= dmax, max(|A|, |B|) <= KL2 (KL2 < 0: off) and
+ * |A| + |B| <= KL3 (KL3 < 0: off); with KL4 > 1 its class is 0 when
+ * min(|A|, |B|) < KL4, else 1.  Labels as for oracle_cut.
+ *
+ * All n(n-1)/2 pairs are sorted by key once.  Each step scans that list
+ * for the first pair that qualifies; a pair skipped because its points are
+ * in one cluster, or because it is not admissible, never qualifies again
+ * (clusters only grow, so sizes only grow and the tests above only get
+ * stricter), and a pair skipped by the class-0 search because its class is
+ * 1 never has class 0 again.  So each search resumes where it stopped.
+ * Memory: 16 bytes per pair (n up to a few thousand).
+ */
+int oracle_cut_allpairs(const float *X, int64_t n, int32_t d, int64_t ld,
+                        int64_t kl1, int64_t kl2, int64_t kl3, int64_t kl4,
+                        double dmax, int32_t *labels, int64_t *n_clusters)
+{
+    if (!X || n < 1 || d < 1 || ld < d || !labels || !n_clusters) return ORACLE_EINVAL;
+    if (n > 200000) return ORACLE_EINVAL;
+    int64_t np = n * (n - 1) / 2;
+    okey *pairs = malloc(sizeof(okey) * (size_t)(np > 0 ? np : 1));
+    int64_t *par = malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *sz = malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *map = malloc(sizeof(int64_t) * (size_t)n);
+    if (!pairs || !par || !sz || !map) {
+        free(pairs); free(par); free(sz); free(map);
+        return ORACLE_ENOMEM;
+    }
+    int64_t q = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) {
+            pairs[q].s = sq_dist(X + i * ld, X + j * ld, d);
+            pairs[q].lo = (int32_t)i;
+            pairs[q].hi = (int32_t)j;
+            ++q;
+        }
+    qsort(pairs, (size_t)np, sizeof(okey), okey_cmp);
+    for (int64_t i = 0; i < n; ++i) { par[i] = i; sz[i] = 1; }
+    int64_t clusters = n;
+    int prio = kl4 > 1;
+    int64_t p0 = 0, p1 = 0;          /* where the class-0 and the any-class searches resume */
+    for (;;) {
+        if (kl1 > 0 && clusters <= kl1) break;
+        int64_t take = -1;
+        for (int pass = prio ? 0 : 1; pass <= 1 && take < 0; ++pass) {
+            int64_t *p = pass == 0 ? &p0 : &p1;
+            for (; *p < np; ++*p) {
+                const okey *e = &pairs[*p];
+                int64_t ra = uf_find(par, e->lo), rb = uf_find(par, e->hi);
+                if (ra == rb) continue;
+                int64_t sa = sz[ra], sb = sz[rb];
+                if (sqrt(e->s) > dmax) continue;
+                if (kl2 >= 0 && (sa > sb ? sa : sb) > kl2) continue;
+                if (kl3 >= 0 && sa + sb > kl3) continue;
+                if (pass == 0 && (sa < sb ? sa : sb) >= kl4) continue;
+                take = *p;
+                break;
+            }
+        }
+        if (take < 0) break;
+        int64_t ra = uf_find(par, pairs[take].lo), rb = uf_find(par, pairs[take].hi);
+        if (sz[ra] < sz[rb]) { par[ra] = rb; sz[rb] += sz[ra]; }
+        else { par[rb] = ra; sz[ra] += sz[rb]; }
+        --clusters;
+    }
+    for (int64_t i = 0; i < n; ++i) map[i] = -1;
+    int64_t next = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t r = uf_find(par, i);
+        if (map[r] < 0) map[r] = next++;
+        labels[i] = (int32_t)map[r];
+    }
+    *n_clusters = next;
+    free(pairs); free(par); free(sz); free(map);
     return ORACLE_OK;
 }
 

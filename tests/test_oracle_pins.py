@@ -355,3 +355,61 @@ def test_nn_outside_matches_brute_force():
         assert j[i] == js[o] and s[i] == S[i, js[o]]
     j, s = oracle.nn_outside(X, np.zeros(200, np.int32))
     assert np.all(j == -1) and np.all(np.isinf(s))
+
+
+# ---- the constrained process over all pairs ("Problem settings", KL1..KL4;
+# "General description of the algorithm for constructing the set of minimum
+# distances") -------------------------------------------------------------
+
+def test_allpairs_process_equals_brute_force_with_size_caps():
+    """oracle_cut_allpairs against the step-by-step brute force (every
+    cluster pair's single-link key recomputed at every step), with KL2 and
+    KL3 on as well as KL1, KL4 and dmax."""
+    rng = np.random.default_rng(31)
+    for trial in range(120):
+        n = int(rng.integers(2, 26))
+        X = rng.standard_normal((n, 2)).astype(np.float32)
+        if trial % 3 == 0:
+            X = np.round(X * 2).astype(np.float32)   # ties
+        kl1 = int(rng.integers(0, 5))
+        kl2 = int(rng.choice([-1, 1, 2, 3, 5, 8]))
+        kl3 = int(rng.choice([-1, 2, 3, 4, 6, 10]))
+        kl4 = int(rng.choice([0, 2, 3, 4]))
+        dmax = float(rng.choice([np.inf, 0.7, 1.5, 3.0]))
+        got, k = oracle.cut_allpairs(X, kl1=kl1, kl2=kl2, kl3=kl3, kl4=kl4, dmax=dmax)
+        exp, ke = checks.agglo_allpairs(X, kl1=kl1, kl2=kl2, kl3=kl3, kl4=kl4, dmax=dmax)
+        assert k == ke and np.array_equal(got, exp), (trial, kl1, kl2, kl3, kl4, dmax)
+
+
+def test_allpairs_process_equals_tree_cut_without_size_caps():
+    """With KL2 and KL3 off the process takes only tree edges (cut
+    property), so it equals the cut of the tree."""
+    rng = np.random.default_rng(32)
+    for trial in range(12):
+        n = int(rng.integers(50, 400))
+        X = rng.standard_normal((n, 3)).astype(np.float32)
+        kl1 = int(rng.integers(0, 12))
+        kl4 = int(rng.choice([0, 2, 5, 20]))
+        dmax = float(rng.choice([np.inf, 0.3, 0.8]))
+        u, v, s, w = oracle.prim_mst(X)
+        exp, ke = oracle.cut(u, v, s, w, n, kl1=kl1, kl4=kl4, dmax=dmax)
+        got, k = oracle.cut_allpairs(X, kl1=kl1, kl4=kl4, dmax=dmax)
+        assert k == ke and np.array_equal(got, exp), (trial, kl1, kl4, dmax)
+
+
+def test_allpairs_process_bypasses_a_blocked_tree_edge():
+    """Hand example on a line (KL3 = 3).  B = {0, 0.125, 0.25} unites first
+    (keys 1/64); the tree edges A-B (A = -0.75, key 0.5625) and c-B
+    (c = 1.125, key 0.765625) are then blocked (4 > 3 points); the pair A-c
+    (key 1.875^2 = 3.515625) is not a tree edge, but the process over all
+    pairs takes it: clusters {A, c} and B.  The cut of the tree keeps A and c
+    apart."""
+    X = np.array([[-0.75], [0.0], [0.125], [0.25], [1.125]], np.float32)
+    got, k = oracle.cut_allpairs(X, kl3=3)
+    assert k == 2 and got.tolist() == [0, 1, 1, 1, 0]
+    u, v, s, w = oracle.prim_mst(X)
+    assert (0, 4) not in set(zip(u.tolist(), v.tolist()))
+    tl, tk = oracle.cut(u, v, s, w, 5, kl3=3)
+    assert tk == 3 and tl.tolist() == [0, 1, 1, 1, 2]
+    # KL1 = 2 stops there as well; KL1 = 3 stops before the bypass
+    assert oracle.cut_allpairs(X, kl1=3, kl3=3)[1] == 3
