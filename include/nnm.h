@@ -325,6 +325,40 @@ nnm_status cluster_cut(const nnm_edge *edges_host, int64_t n,
                        const nnm_cut_params *params, int32_t *labels_host,
                        int64_t *n_clusters);
 
+/*
+ * The clustering process itself under the settings, over all pairs of
+ * points: the section "General description of the algorithm for
+ * constructing the set of minimum distances" unites, step by step, the two
+ * clusters of the smallest admissible pair of points in different clusters
+ * ("Problem settings": KL1..KL4; "Problem statement": the distance
+ * threshold).  A pair of clusters A, B is admissible when sqrt(s) <= dmax,
+ * max(|A|, |B|) <= KL2 (KL2 < 0: off) and |A| + |B| <= KL3 (KL3 < 0: off);
+ * with KL4 > 1 pairs with min(|A|, |B|) < KL4 come first (class 0), each
+ * class in key order; the process stops at KL1 clusters (KL1 <= 0: off) or
+ * when no pair is admissible.  With KL2 and KL3 off this is exactly
+ * cluster_cut of the tree; with them on a blocked pair can be bypassed by a
+ * longer pair that is not a tree edge, which only this entry point follows.
+ *   X_dev      [n][ld] FP32 device (as for mst_build);
+ *   params     the settings (as for cluster_cut);
+ *   k          neighbour prefix kept per point, 1..32 (0: 16); points that
+ *              use theirs up get the next one from an exact FP64 scan;
+ *   opt        candidate precision of the first prefixes (as for knn_build);
+ *   ws_dev     at least allpairs_cut_workspace_size() bytes;
+ *   labels_host, n_clusters: as for cluster_cut;
+ *   stats      NULL, or host [4]: unions, GPU scans for next prefixes, points
+ *              rescanned, k used.
+ * Synchronous; host memory O(n k).  Errors: as for knn_build and
+ * cluster_cut (a NaN or negative dmax is NNM_EINVAL).
+ */
+nnm_status allpairs_cut_workspace_size(int64_t n, int32_t d, int32_t k,
+                                       const nnm_options *opt, size_t *bytes);
+nnm_status cluster_cut_allpairs(const float *X_dev, int64_t n, int32_t d,
+                                int64_t ld, const nnm_cut_params *params,
+                                int32_t k, const nnm_options *opt,
+                                void *ws_dev, size_t ws_bytes, void *stream,
+                                int32_t *labels_host, int64_t *n_clusters,
+                                int64_t *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,8 @@ import numpy as np
 from . import _native as N
 from ._native import NNMError, NativeMissing, PREC  # noqa: F401
 
-__all__ = ["mst_build", "mst_build_noalloc", "knn_build", "cluster_cut", "mst_build_batched", "Tree",
+__all__ = ["mst_build", "mst_build_noalloc", "knn_build", "cluster_cut", "cluster_cut_allpairs",
+           "mst_build_batched", "Tree",
            "options", "autotune", "NNMError", "NativeMissing"]
 
 
@@ -296,3 +297,31 @@ def cluster_cut(tree, n=None, kl1=0, kl2=-1, kl3=-1, kl4=0, dmax=math.inf):
                                ctypes.c_void_p(labels.ctypes.data), ctypes.byref(k))
     N.check("cluster_cut", code)
     return labels[:n], int(k.value)
+
+
+def cluster_cut_allpairs(X, kl1=0, kl2=-1, kl3=-1, kl4=0, dmax=math.inf, k=0,
+                         precision="auto", stream=None, workspace=None, with_stats=False):
+    """The clustering process under the settings over all pairs of points of
+    X (a float32 CUDA tensor): (labels int32 [n], K), and with
+    with_stats=True also {unions, scans, rows_rescanned, k}.  Equal to
+    cluster_cut of mst_build's tree when kl2 and kl3 are off."""
+    n, d, ld = _check_x(X)
+    L = N.lib()
+    o = options(precision)
+    nb = ctypes.c_size_t(0)
+    N.check("allpairs_cut_workspace_size",
+            L.allpairs_cut_workspace_size(n, d, int(k), ctypes.byref(o), ctypes.byref(nb)))
+    ws = (workspace or _WS).get(nb.value, X.device)
+    p = N.CutParams(int(kl1), int(kl2), int(kl3), int(kl4), float(dmax))
+    labels = np.empty(max(n, 1), np.int32)
+    kk = ctypes.c_int64(0)
+    st = (ctypes.c_int64 * 4)()
+    code = L.cluster_cut_allpairs(ctypes.c_void_p(X.data_ptr()), n, d, ld, ctypes.byref(p), int(k),
+                                  ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), nb.value,
+                                  _stream(stream), ctypes.c_void_p(labels.ctypes.data),
+                                  ctypes.byref(kk), st)
+    N.check("cluster_cut_allpairs", code)
+    if with_stats:
+        return labels[:n], int(kk.value), {"unions": st[0], "scans": st[1],
+                                          "rows_rescanned": st[2], "k": st[3]}
+    return labels[:n], int(kk.value)

@@ -1,0 +1,550 @@
+// allpairs.hip -- the constrained clustering process over all pairs of
+// points (not only the tree edges), exactly.
+//
+// The section "General description of the algorithm for constructing the
+// set of minimum distances" unites clusters along the smallest pairs of
+// points in different clusters; the settings of "Problem settings" (KL1..
+// KL4) and the distance threshold of the "Problem statement" decide which
+// pairs may be taken.  With the size caps KL2 / KL3 on, a pair blocked at one
+// time can be bypassed by a longer pair between other clusters, which need
+// not be a tree edge; cluster_cut (tree edges only) then differs from the
+// process.  This entry point follows the process itself:
+//
+//   * a pair of clusters A, B is admissible when sqrt(s) <= dmax,
+//     max(|A|, |B|) <= KL2 and |A| + |B| <= KL3; its class is 0 when
+//     min(|A|, |B|) < KL4 (KL4 > 1), else 1; each step takes the admissible
+//     pair with the smallest (class, key) and unites its clusters, until
+//     KL1 clusters remain or no pair is admissible.
+//   * Clusters only grow, so a pair that is not admissible never becomes
+//     admissible again.  The smallest (class, key) over all pairs is the
+//     smallest over clusters X of (class of X, best(X)), best(X) being the
+//     smallest admissible pair leaving X and the class of X 0 when
+//     |X| < KL4: a class-0 pair touches a small cluster, whose own best is
+//     no larger.
+//   * best(X) is the smallest over X's points of each point's first
+//     admissible neighbour.  Every point keeps an exact prefix of its
+//     neighbours by key (from knn_build) and a cursor; an entry that is
+//     inside the point's cluster or not admissible is skipped for good.  A
+//     point whose prefix is used up gets the next prefix from the GPU: the k
+//     smallest keys beyond its last one over the columns admissible for its
+//     cluster now (an exact FP64 scan of every column), which stays an exact
+//     prefix of the admissible columns later on, since those only shrink.
+//   * Host side: union-find, one meldable heap of points per cluster keyed
+//     by a lower bound of each point's next pair, and one heap of clusters
+//     keyed by a lower bound of (class, best); bounds are made exact when
+//     they reach the top.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <queue>
+#include <random>
+#include <vector>
+
+#include "nnm_common.h"
+
+namespace nnm {
+namespace {
+
+// ---- GPU: the next k admissible neighbours of a batch of points ---------
+
+struct NextArgs {
+    const float* X;
+    int64_t ld;
+    int32_t d;
+    int32_t k;
+    int64_t n;
+    const int32_t* rows;      // [nr] points
+    int32_t nr;
+    const double* lb_s;       // [nr] key of the last neighbour already known
+    const int32_t* lb_j;      // [nr] and its index ((s, j) order)
+    const int32_t* limit;     // [nr] largest admissible size of the other cluster (-1: none)
+    const int32_t* comp;      // [n] cluster of each point
+    const int32_t* csize;     // [n] size of each point's cluster
+    double dmax;
+    int32_t* out_j;           // [nr][k]
+    double* out_s;            // [nr][k]
+    int32_t* out_len;         // [nr]
+};
+
+// One workgroup per point of the batch (grid-stride): every thread keeps
+// the k smallest admissible (s, j) of its columns, then k rounds of a
+// workgroup arg-min merge the 256 lists.
+__global__ __launch_bounds__(256) void k_next_admissible(NextArgs a)
+{
+    __shared__ double rs[4];
+    __shared__ int rj[4], rt[4];
+    __shared__ int win;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int q = blockIdx.x; q < a.nr; q += gridDim.x) {
+        __syncthreads();
+        const int i = a.rows[q];
+        const int ci = a.comp[i];
+        const int lim = a.limit[q];
+        const double ls0 = a.lb_s[q];
+        const int lj0 = a.lb_j[q];
+        const float* xi = a.X + (int64_t)i * a.ld;
+        double hs[KMAX];
+        int hj[KMAX];
+        for (int e = 0; e < KMAX; ++e) { hs[e] = __builtin_huge_val(); hj[e] = 0x7FFFFFFF; }
+        const int k = a.k;
+        if (lim >= 0) {
+            for (int64_t j = tid; j < a.n; j += 256) {
+                if (a.comp[j] == ci || a.csize[j] > lim) continue;
+                const double s = sqdist_fp64(xi, a.X + j * a.ld, a.d);
+                if (!sj_less(ls0, lj0, s, (int)j)) continue;          // not beyond the known prefix
+                if (__builtin_sqrt(s) > a.dmax) continue;
+                if (!sj_less(s, (int)j, hs[k - 1], hj[k - 1])) continue;
+                int p = k - 1;
+                while (p > 0 && sj_less(s, (int)j, hs[p - 1], hj[p - 1])) {
+                    hs[p] = hs[p - 1];
+                    hj[p] = hj[p - 1];
+                    --p;
+                }
+                hs[p] = s;
+                hj[p] = (int)j;
+            }
+        }
+        int head = 0, kept = 0;
+        for (int r = 0; r < k; ++r) {
+            double bs = head < k ? hs[head] : __builtin_huge_val();
+            int bj = head < k ? hj[head] : 0x7FFFFFFF;
+            int bt = tid;
+            for (int off = 32; off > 0; off >>= 1) {
+                const double os = __shfl_xor(bs, off);
+                const int oj = __shfl_xor(bj, off);
+                const int ot = __shfl_xor(bt, off);
+                if (sj_less(os, oj, bs, bj)) { bs = os; bj = oj; bt = ot; }
+            }
+            if (lane == 0) { rs[wave] = bs; rj[wave] = bj; rt[wave] = bt; }
+            __syncthreads();
+            if (tid == 0) {
+                double s0 = rs[0];
+                int j0 = rj[0], t0 = rt[0];
+                for (int w = 1; w < 4; ++w)
+                    if (sj_less(rs[w], rj[w], s0, j0)) { s0 = rs[w]; j0 = rj[w]; t0 = rt[w]; }
+                win = s0 < __builtin_huge_val() ? t0 : -1;
+                if (win >= 0) {
+                    a.out_j[(int64_t)q * k + r] = j0;
+                    a.out_s[(int64_t)q * k + r] = s0;
+                }
+            }
+            __syncthreads();
+            const int wt = win;
+            __syncthreads();
+            if (wt < 0) break;
+            if (tid == wt) ++head;
+            ++kept;
+        }
+        if (tid == 0) a.out_len[q] = kept;
+    }
+}
+
+#define HIP_OK(x)                                  \
+    do {                                           \
+        if ((x) != hipSuccess) return NNM_EDEVICE; \
+    } while (0)
+
+// ---- host side ----------------------------------------------------------
+
+struct PairKey {
+    double s;
+    int32_t lo, hi;
+    bool operator<(const PairKey& o) const
+    {
+        if (s != o.s) return s < o.s;
+        if (lo != o.lo) return lo < o.lo;
+        return hi < o.hi;
+    }
+};
+
+struct Workspace {
+    size_t knn_bytes;
+    void* knn_ws;
+    int32_t* idx;             // [n][k]
+    double* sd;               // [n][k]
+    int32_t* len;             // [n]
+    int32_t* rows;            // [n]
+    double* lb_s;             // [n]
+    int32_t* lb_j;            // [n]
+    int32_t* limit;           // [n]
+    int32_t* comp;            // [n]
+    int32_t* csize;           // [n]
+    int32_t* out_j;           // [n][k]
+    double* out_s;            // [n][k]
+    int32_t* out_len;         // [n]
+};
+
+size_t carve_ap(int64_t n, int32_t k, size_t knn_bytes, char* base, Workspace* w)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        off = (off + 255) & ~(size_t)255;
+        void* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const size_t N = (size_t)n, K = (size_t)k;
+    w->knn_bytes = knn_bytes;
+    w->knn_ws = take(knn_bytes);
+    w->idx = (int32_t*)take(N * K * 4);
+    w->sd = (double*)take(N * K * 8);
+    w->len = (int32_t*)take(N * 4);
+    w->rows = (int32_t*)take(N * 4);
+    w->lb_s = (double*)take(N * 8);
+    w->lb_j = (int32_t*)take(N * 4);
+    w->limit = (int32_t*)take(N * 4);
+    w->comp = (int32_t*)take(N * 4);
+    w->csize = (int32_t*)take(N * 4);
+    w->out_j = (int32_t*)take(N * K * 4);
+    w->out_s = (double*)take(N * K * 8);
+    w->out_len = (int32_t*)take(N * 4);
+    return off + 256;
+}
+
+constexpr int32_t DEFAULT_DEPTH = 16;
+
+struct Process {
+    int64_t n;
+    int32_t K;
+    int64_t kl1, kl2, kl3, kl4;
+    double dmax;
+    // points: neighbour prefix and cursor
+    std::vector<int32_t> lj;
+    std::vector<double> ls;
+    std::vector<int32_t> len, cur;
+    std::vector<uint8_t> state;      // 0 candidate at cur, 1 prefix used up, 2 no pair left
+    std::vector<uint8_t> queued;     // in `spent`
+    std::vector<int32_t> spent;      // points in state 1 awaiting the next prefix
+    // clusters
+    std::vector<int32_t> par, size, ver;
+    // per-cluster meldable heaps of points (randomised meld)
+    std::vector<int32_t> hl, hr, hroot;
+    std::vector<PairKey> hkey;
+    std::mt19937 coin{12345};
+    int64_t refills = 0, refilled_rows = 0, merges = 0;
+
+    int32_t find(int32_t x)
+    {
+        while (par[x] != x) {
+            par[x] = par[par[x]];
+            x = par[x];
+        }
+        return x;
+    }
+    int32_t meld(int32_t a, int32_t b)
+    {
+        if (a < 0) return b;
+        if (b < 0) return a;
+        if (hkey[b] < hkey[a]) std::swap(a, b);
+        if (coin() & 1) hl[a] = meld(hl[a], b);
+        else hr[a] = meld(hr[a], b);
+        return a;
+    }
+    void push(int32_t c, int32_t r)
+    {
+        hl[r] = hr[r] = -1;
+        hroot[c] = meld(hroot[c], r);
+    }
+    void pop(int32_t c)
+    {
+        const int32_t r = hroot[c];
+        hroot[c] = meld(hl[r], hr[r]);
+    }
+    // largest admissible size of the other cluster for a cluster of size sx
+    int32_t limit_of(int64_t sx) const
+    {
+        int64_t lim = INT32_MAX;
+        if (kl2 >= 0) {
+            if (sx > kl2) return -1;
+            lim = std::min<int64_t>(lim, kl2);
+        }
+        if (kl3 >= 0) lim = std::min<int64_t>(lim, kl3 - sx);
+        return lim < 0 ? -1 : (int32_t)lim;
+    }
+    bool admissible(int64_t sa, int64_t sb, double s) const
+    {
+        if (sqrt(s) > dmax) return false;
+        if (kl2 >= 0 && std::max(sa, sb) > kl2) return false;
+        if (kl3 >= 0 && sa + sb > kl3) return false;
+        return true;
+    }
+    PairKey key_at(int32_t r) const
+    {
+        const int32_t j = lj[(size_t)r * K + cur[r]];
+        return PairKey{ls[(size_t)r * K + cur[r]], std::min(r, j), std::max(r, j)};
+    }
+    // the prefix of r is used up: no pair left if it held every admissible
+    // column, else wait for the next prefix (lower bound: its last key)
+    void use_up(int32_t r)
+    {
+        if (len[r] < K) {
+            state[r] = 2;
+            return;
+        }
+        state[r] = 1;
+        hkey[r] = PairKey{ls[(size_t)r * K + K - 1], -1, -1};
+        if (!queued[r]) {
+            queued[r] = 1;
+            spent.push_back(r);
+        }
+    }
+};
+
+// The next prefixes of every point in p.spent, from the GPU.
+nnm_status refill(Process& p, const float* X, int32_t d, int64_t ld, Workspace& w, hipStream_t s)
+{
+    const int32_t nr = (int32_t)p.spent.size();
+    if (nr == 0) return NNM_OK;
+    std::vector<int32_t> comp((size_t)p.n), csz((size_t)p.n), lim((size_t)nr), lbj((size_t)nr);
+    std::vector<double> lbs((size_t)nr);
+    for (int64_t i = 0; i < p.n; ++i) {
+        comp[(size_t)i] = p.find((int32_t)i);
+        csz[(size_t)i] = p.size[(size_t)comp[(size_t)i]];
+    }
+    for (int32_t q = 0; q < nr; ++q) {
+        const int32_t r = p.spent[(size_t)q];
+        lbs[(size_t)q] = p.ls[(size_t)r * p.K + p.K - 1];
+        lbj[(size_t)q] = p.lj[(size_t)r * p.K + p.K - 1];
+        lim[(size_t)q] = p.limit_of(csz[(size_t)r]);
+    }
+    HIP_OK(hipMemcpyAsync(w.comp, comp.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(w.csize, csz.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(w.rows, p.spent.data(), 4 * (size_t)nr, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(w.lb_s, lbs.data(), 8 * (size_t)nr, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(w.lb_j, lbj.data(), 4 * (size_t)nr, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(w.limit, lim.data(), 4 * (size_t)nr, hipMemcpyHostToDevice, s));
+    NextArgs a;
+    a.X = X;
+    a.ld = ld;
+    a.d = d;
+    a.k = p.K;
+    a.n = p.n;
+    a.rows = w.rows;
+    a.nr = nr;
+    a.lb_s = w.lb_s;
+    a.lb_j = w.lb_j;
+    a.limit = w.limit;
+    a.comp = w.comp;
+    a.csize = w.csize;
+    a.dmax = p.dmax;
+    a.out_j = w.out_j;
+    a.out_s = w.out_s;
+    a.out_len = w.out_len;
+    k_next_admissible<<<(unsigned)std::min(nr, 4096), 256, 0, s>>>(a);
+    HIP_OK(hipGetLastError());
+    std::vector<int32_t> oj((size_t)nr * p.K), ol((size_t)nr);
+    std::vector<double> os((size_t)nr * p.K);
+    HIP_OK(hipMemcpyAsync(oj.data(), w.out_j, 4 * oj.size(), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(os.data(), w.out_s, 8 * os.size(), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(ol.data(), w.out_len, 4 * ol.size(), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int32_t q = 0; q < nr; ++q) {
+        const int32_t r = p.spent[(size_t)q];
+        p.queued[(size_t)r] = 0;
+        const int32_t L = ol[(size_t)q];
+        for (int32_t e = 0; e < L; ++e) {
+            p.lj[(size_t)r * p.K + e] = oj[(size_t)q * p.K + e];
+            p.ls[(size_t)r * p.K + e] = os[(size_t)q * p.K + e];
+        }
+        p.len[(size_t)r] = L;
+        p.cur[(size_t)r] = 0;
+        p.state[(size_t)r] = L > 0 ? 0 : 2;
+    }
+    p.refills += 1;
+    p.refilled_rows += nr;
+    p.spent.clear();
+    return NNM_OK;
+}
+
+// best(X): the smallest admissible pair leaving cluster X (false: none, ever).
+nnm_status best_of(Process& p, int32_t X, const float* Xd, int32_t d, int64_t ld, Workspace& w,
+                   hipStream_t s, PairKey* out, int32_t* partner, bool* found)
+{
+    for (;;) {
+        const int32_t r = p.hroot[(size_t)X];
+        if (r < 0) {
+            *found = false;
+            return NNM_OK;
+        }
+        if (p.state[(size_t)r] == 2) {
+            p.pop(X);
+            continue;
+        }
+        if (p.state[(size_t)r] == 1) {
+            nnm_status st = refill(p, Xd, d, ld, w, s);
+            if (st != NNM_OK) return st;
+            continue;
+        }
+        const int32_t j = p.lj[(size_t)r * p.K + p.cur[(size_t)r]];
+        const double sv = p.ls[(size_t)r * p.K + p.cur[(size_t)r]];
+        const int32_t Y = p.find(j);
+        if (Y == X || !p.admissible(p.size[(size_t)X], p.size[(size_t)Y], sv)) {
+            p.pop(X);
+            if (sqrt(sv) > p.dmax) {
+                p.state[(size_t)r] = 2;            // every later key is larger
+                continue;
+            }
+            if (++p.cur[(size_t)r] >= p.len[(size_t)r]) p.use_up(r);
+            else p.hkey[(size_t)r] = p.key_at(r);
+            if (p.state[(size_t)r] != 2) p.push(X, r);
+            continue;
+        }
+        const PairKey kc = p.key_at(r);
+        if (p.hkey[(size_t)r] < kc) {           // a stale lower bound: re-key
+            p.pop(X);
+            p.hkey[(size_t)r] = kc;
+            p.push(X, r);
+            continue;
+        }
+        *out = kc;
+        *partner = Y;
+        *found = true;
+        return NNM_OK;
+    }
+}
+
+struct Entry {
+    int32_t cls;
+    PairKey key;
+    int32_t c, ver;
+    bool operator>(const Entry& o) const
+    {
+        if (cls != o.cls) return cls > o.cls;
+        return o.key < key;
+    }
+};
+
+}  // namespace
+}  // namespace nnm
+
+using namespace nnm;
+
+extern "C" nnm_status allpairs_cut_workspace_size(int64_t n, int32_t d, int32_t k,
+                                                  const nnm_options* opt, size_t* bytes)
+{
+    if (!bytes || n < 1 || d < 1 || d > DMAX || k < 0 || k > KMAX) return NNM_EINVAL;
+    const int32_t K = k > 0 ? k : DEFAULT_DEPTH;
+    size_t kb = 0;
+    nnm_status st = knn_workspace_size(n, d, K, opt, &kb);
+    if (st != NNM_OK) return st;
+    Workspace w;
+    *bytes = carve_ap(n, K, kb, nullptr, &w);
+    return NNM_OK;
+}
+
+extern "C" nnm_status cluster_cut_allpairs(const float* X_dev, int64_t n, int32_t d, int64_t ld,
+                                           const nnm_cut_params* prm, int32_t k,
+                                           const nnm_options* opt, void* ws_dev, size_t ws_bytes,
+                                           void* stream, int32_t* labels_host, int64_t* n_clusters,
+                                           int64_t* stats)
+{
+    if (!X_dev || !prm || !ws_dev || !labels_host || !n_clusters) return NNM_EINVAL;
+    if (n < 1 || n > (int64_t)0x7FFFFFF0 || d < 1 || d > DMAX || ld < d || k < 0 || k > KMAX)
+        return NNM_EINVAL;
+    if (std::isnan(prm->dmax) || prm->dmax < 0.0) return NNM_EINVAL;
+    const int32_t K = k > 0 ? k : DEFAULT_DEPTH;
+    size_t need = 0;
+    nnm_status st = allpairs_cut_workspace_size(n, d, K, opt, &need);
+    if (st != NNM_OK) return st;
+    if (ws_bytes < need) return NNM_EINVAL;
+    Workspace w;
+    size_t kb = 0;
+    st = knn_workspace_size(n, d, K, opt, &kb);
+    if (st != NNM_OK) return st;
+    carve_ap(n, K, kb, (char*)ws_dev, &w);
+    hipStream_t s = (hipStream_t)stream;
+    Process p;
+    p.n = n;
+    p.K = K;
+    p.kl1 = prm->kl1_max_clusters;
+    p.kl2 = prm->kl2_max_size;
+    p.kl3 = prm->kl3_max_merged;
+    p.kl4 = prm->kl4_min_size;
+    p.dmax = prm->dmax;
+    const size_t N = (size_t)n;
+    p.lj.assign(N * K, -1);
+    p.ls.assign(N * K, 0.0);
+    p.len.assign(N, 0);
+    p.cur.assign(N, 0);
+    p.state.assign(N, 0);
+    p.queued.assign(N, 0);
+    p.par.resize(N);
+    p.size.assign(N, 1);
+    p.ver.assign(N, 0);
+    p.hl.assign(N, -1);
+    p.hr.assign(N, -1);
+    p.hroot.assign(N, -1);
+    p.hkey.resize(N);
+    for (size_t i = 0; i < N; ++i) p.par[i] = (int32_t)i;
+    if (n > 1) {
+        // every point's exact neighbour prefix
+        st = knn_build(X_dev, n, d, ld, K, opt, w.knn_ws, w.knn_bytes, w.idx, w.sd, w.len, stream,
+                       nullptr);
+        if (st != NNM_OK) return st;
+        HIP_OK(hipMemcpyAsync(p.lj.data(), w.idx, 4 * N * K, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(p.ls.data(), w.sd, 8 * N * K, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(p.len.data(), w.len, 4 * N, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
+    const bool prio = p.kl4 > 1;
+    std::priority_queue<Entry, std::vector<Entry>, std::greater<Entry>> G;
+    for (size_t i = 0; i < N; ++i) {
+        if (p.len[i] == 0) {
+            p.state[i] = 2;
+            continue;
+        }
+        p.hkey[i] = p.key_at((int32_t)i);
+        p.push((int32_t)i, (int32_t)i);
+        G.push(Entry{prio ? 0 : 1, p.hkey[i], (int32_t)i, 0});
+    }
+    int64_t clusters = n;
+    while (!G.empty()) {
+        if (p.kl1 > 0 && clusters <= p.kl1) break;
+        const Entry e = G.top();
+        G.pop();
+        if (p.find(e.c) != e.c || p.ver[(size_t)e.c] != e.ver) continue;
+        PairKey b;
+        int32_t Y = -1;
+        bool found = false;
+        st = best_of(p, e.c, X_dev, d, ld, w, s, &b, &Y, &found);
+        if (st != NNM_OK) return st;
+        if (!found) continue;                    // no admissible pair, ever
+        const int32_t cls = (prio && p.size[(size_t)e.c] < p.kl4) ? 0 : 1;
+        const Entry now{cls, b, e.c, e.ver};
+        if (!G.empty() && now > G.top()) {      // another cluster may come first
+            G.push(now);
+            continue;
+        }
+        // unite X and Y (the larger keeps its id)
+        int32_t X = e.c;
+        int32_t Z = X, o = Y;
+        if (p.size[(size_t)Y] > p.size[(size_t)X]) std::swap(Z, o);
+        p.par[(size_t)o] = Z;
+        p.size[(size_t)Z] += p.size[(size_t)o];
+        p.hroot[(size_t)Z] = p.meld(p.hroot[(size_t)Z], p.hroot[(size_t)o]);
+        p.hroot[(size_t)o] = -1;
+        p.ver[(size_t)Z] += 1;
+        p.ver[(size_t)o] += 1;
+        --clusters;
+        ++p.merges;
+        // (class, key) of the pair just taken bounds the new cluster's from below
+        G.push(Entry{cls, b, Z, p.ver[(size_t)Z]});
+    }
+    std::vector<int64_t> map(N, -1);
+    int64_t next = 0;
+    for (size_t i = 0; i < N; ++i) {
+        const int32_t r = p.find((int32_t)i);
+        if (map[(size_t)r] < 0) map[(size_t)r] = next++;
+        labels_host[i] = (int32_t)map[(size_t)r];
+    }
+    *n_clusters = next;
+    if (stats) {
+        stats[0] = p.merges;
+        stats[1] = p.refills;
+        stats[2] = p.refilled_rows;
+        stats[3] = K;
+    }
+    return NNM_OK;
+}

@@ -279,3 +279,28 @@ def test_autotune_cache_keys_and_store(tmp_path):
         assert e["split_target0"] in (0, 2048, 4096, 8192)
         assert e["split_target"] in (0, 4096, 8192, 16384) and e["graph"] in (0, 1)
     assert A.lookup(4096, 12, "fp16", cache=path, arch_name="gfx950")["knn_k"] == 4
+
+
+def test_allpairs_cut_rejects_bad_arguments_before_device_work():
+    L = N.lib()
+    o = nnm.options("fp16")
+    p = N.CutParams(0, 5, -1, 0, math.inf)
+    nb = ctypes.c_size_t(0)
+    assert L.allpairs_cut_workspace_size(1000, 8, 0, ctypes.byref(o), ctypes.byref(nb)) == N.NNM_OK
+    assert nb.value > 0
+    assert L.allpairs_cut_workspace_size(1000, 8, 33, ctypes.byref(o), ctypes.byref(nb)) == N.NNM_EINVAL
+    labels = np.zeros(1000, np.int32)
+    k = ctypes.c_int64(0)
+
+    def call(X=1234, n=1000, d=8, ld=8, prm=p, kk=0, ws=1, wsb=None):
+        return L.cluster_cut_allpairs(ctypes.c_void_p(X), n, d, ld, ctypes.byref(prm), kk,
+                                      ctypes.byref(o), ctypes.c_void_p(ws),
+                                      nb.value if wsb is None else wsb, None,
+                                      ctypes.c_void_p(labels.ctypes.data), ctypes.byref(k), None)
+    assert call(X=0) == N.NNM_EINVAL
+    assert call(ws=0) == N.NNM_EINVAL
+    assert call(kk=40) == N.NNM_EINVAL
+    assert call(ld=4) == N.NNM_EINVAL
+    assert call(wsb=nb.value - 1) == N.NNM_EINVAL
+    assert call(prm=N.CutParams(0, 5, -1, 0, float("nan"))) == N.NNM_EINVAL
+    assert call(prm=N.CutParams(0, 5, -1, 0, -1.0)) == N.NNM_EINVAL
