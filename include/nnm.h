@@ -338,22 +338,30 @@ nnm_status cluster_cut(const nnm_edge *edges_host, int64_t n,
  * when no pair is admissible.  With KL2 and KL3 off this is exactly
  * cluster_cut of the tree; with them on a blocked pair can be bypassed by a
  * longer pair that is not a tree edge, which only this entry point follows.
+ * A cluster whose smallest outgoing tree edge is admissible takes that edge
+ * (the smallest pair leaving it); only clusters whose smallest outgoing
+ * tree edge is blocked search their points' neighbours.
  *   X_dev      [n][ld] FP32 device (as for mst_build);
+ *   edges_host [n-1] host: the tree mst_build returned for this X_dev
+ *              (another set of edges gives undefined labels);
  *   params     the settings (as for cluster_cut);
- *   k          neighbour prefix kept per point, 1..32 (0: 16); points that
- *              use theirs up get the next one from an exact FP64 scan;
+ *   k          neighbour prefix kept per point, 1..32 (0: 16), built when
+ *              first needed; points that use theirs up get the next one
+ *              from an exact FP64 scan over the columns admissible for their
+ *              cluster;
  *   opt        candidate precision of the first prefixes (as for knn_build);
  *   ws_dev     at least allpairs_cut_workspace_size() bytes;
  *   labels_host, n_clusters: as for cluster_cut;
- *   stats      NULL, or host [4]: unions, GPU scans for next prefixes, points
- *              rescanned, k used.
+ *   stats      NULL, or host [5]: unions, GPU scans for next prefixes, points
+ *              rescanned, k used, microseconds spent in those scans.
  * Synchronous; host memory O(n k).  Errors: as for knn_build and
  * cluster_cut (a NaN or negative dmax is NNM_EINVAL).
  */
 nnm_status allpairs_cut_workspace_size(int64_t n, int32_t d, int32_t k,
                                        const nnm_options *opt, size_t *bytes);
 nnm_status cluster_cut_allpairs(const float *X_dev, int64_t n, int32_t d,
-                                int64_t ld, const nnm_cut_params *params,
+                                int64_t ld, const nnm_edge *edges_host,
+                                const nnm_cut_params *params,
                                 int32_t k, const nnm_options *opt,
                                 void *ws_dev, size_t ws_bytes, void *stream,
                                 int32_t *labels_host, int64_t *n_clusters,

@@ -299,13 +299,17 @@ def cluster_cut(tree, n=None, kl1=0, kl2=-1, kl3=-1, kl4=0, dmax=math.inf):
     return labels[:n], int(k.value)
 
 
-def cluster_cut_allpairs(X, kl1=0, kl2=-1, kl3=-1, kl4=0, dmax=math.inf, k=0,
+def cluster_cut_allpairs(X, tree=None, kl1=0, kl2=-1, kl3=-1, kl4=0, dmax=math.inf, k=0,
                          precision="auto", stream=None, workspace=None, with_stats=False):
     """The clustering process under the settings over all pairs of points of
-    X (a float32 CUDA tensor): (labels int32 [n], K), and with
-    with_stats=True also {unions, scans, rows_rescanned, k}.  Equal to
-    cluster_cut of mst_build's tree when kl2 and kl3 are off."""
+    X (a float32 CUDA tensor), given mst_build's tree of X (built here when
+    None): (labels int32 [n], K), and with with_stats=True also {unions,
+    scans, rows_rescanned, k, scan_ms}.  Equal to cluster_cut of the tree when kl2 and
+    kl3 are off."""
     n, d, ld = _check_x(X)
+    if tree is None:
+        tree = mst_build(X, precision=precision, stream=stream)
+    buf, _ = _edges_host(tree, n)
     L = N.lib()
     o = options(precision)
     nb = ctypes.c_size_t(0)
@@ -315,13 +319,16 @@ def cluster_cut_allpairs(X, kl1=0, kl2=-1, kl3=-1, kl4=0, dmax=math.inf, k=0,
     p = N.CutParams(int(kl1), int(kl2), int(kl3), int(kl4), float(dmax))
     labels = np.empty(max(n, 1), np.int32)
     kk = ctypes.c_int64(0)
-    st = (ctypes.c_int64 * 4)()
-    code = L.cluster_cut_allpairs(ctypes.c_void_p(X.data_ptr()), n, d, ld, ctypes.byref(p), int(k),
+    st = (ctypes.c_int64 * 5)()
+    code = L.cluster_cut_allpairs(ctypes.c_void_p(X.data_ptr()), n, d, ld,
+                                  ctypes.c_void_p(buf.ctypes.data if n > 1 else None),
+                                  ctypes.byref(p), int(k),
                                   ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), nb.value,
                                   _stream(stream), ctypes.c_void_p(labels.ctypes.data),
                                   ctypes.byref(kk), st)
     N.check("cluster_cut_allpairs", code)
     if with_stats:
         return labels[:n], int(kk.value), {"unions": st[0], "scans": st[1],
-                                          "rows_rescanned": st[2], "k": st[3]}
+                                          "rows_rescanned": st[2], "k": st[3],
+                                          "scan_ms": st[4] / 1000.0}
     return labels[:n], int(kk.value)

@@ -119,7 +119,8 @@ _SIG = {
                                                    ctypes.POINTER(Options),
                                                    ctypes.POINTER(ctypes.c_size_t)]),
     "cluster_cut_allpairs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
-                                            ctypes.c_int64, ctypes.POINTER(CutParams),
+                                            ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.POINTER(CutParams),
                                             ctypes.c_int32, ctypes.POINTER(Options),
                                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),

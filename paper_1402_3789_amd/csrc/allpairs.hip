@@ -21,7 +21,11 @@
 //     smallest admissible pair leaving X and the class of X 0 when
 //     |X| < KL4: a class-0 pair touches a small cluster, whose own best is
 //     no larger.
-//   * best(X) is the smallest over X's points of each point's first
+//   * By the cut property the smallest pair leaving X is a tree edge; when
+//     that edge is admissible it is best(X).  So every cluster keeps a heap
+//     of the tree edges at its points, and only a cluster whose smallest
+//     outgoing tree edge is blocked looks further:
+//   * then best(X) is the smallest over X's points of each point's first
 //     admissible neighbour.  Every point keeps an exact prefix of its
 //     neighbours by key (from knn_build) and a cursor; an entry that is
 //     inside the point's cluster or not admissible is skipped for good.  A
@@ -29,14 +33,15 @@
 //     smallest keys beyond its last one over the columns admissible for its
 //     cluster now (an exact FP64 scan of every column), which stays an exact
 //     prefix of the admissible columns later on, since those only shrink.
-//   * Host side: union-find, one meldable heap of points per cluster keyed
-//     by a lower bound of each point's next pair, and one heap of clusters
-//     keyed by a lower bound of (class, best); bounds are made exact when
-//     they reach the top.
+//   * Host side: cluster ids relabelled smaller-into-larger, one meldable
+//     heap of points per cluster keyed by a lower bound of each point's next
+//     pair, and one heap of clusters keyed by a lower bound of (class,
+//     best); bounds are made exact when they reach the top.
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <queue>
 #include <random>
@@ -50,49 +55,90 @@ namespace {
 // ---- GPU: the next k admissible neighbours of a batch of points ---------
 
 struct NextArgs {
-    const float* X;
-    int64_t ld;
+    const float* xp;          // [n][DMAX] padded copy of the points
     int32_t d;
     int32_t k;
     int64_t n;
     const int32_t* rows;      // [nr] points
     int32_t nr;
+    int32_t splits;           // column ranges per point
     const double* lb_s;       // [nr] key of the last neighbour already known
     const int32_t* lb_j;      // [nr] and its index ((s, j) order)
     const int32_t* limit;     // [nr] largest admissible size of the other cluster (-1: none)
     const int32_t* comp;      // [n] cluster of each point
-    const int32_t* csize;     // [n] size of each point's cluster
+    const int32_t* csize;     // [n] size of each cluster, by cluster id
     double dmax;
+    int32_t* part_j;          // [nr][splits][k] per column range
+    double* part_s;
+    int32_t* part_len;        // [nr][splits]
     int32_t* out_j;           // [nr][k]
     double* out_s;            // [nr][k]
     int32_t* out_len;         // [nr]
 };
 
-// One workgroup per point of the batch (grid-stride): every thread keeps
+__global__ __launch_bounds__(256) void k_pad_points(const float* __restrict__ X, int64_t ld, int d,
+                                                    int64_t n, float* __restrict__ xp)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n * DMAX) return;
+    const int64_t i = t / DMAX;
+    const int f = (int)(t % DMAX);
+    xp[t] = f < d ? X[i * ld + f] : 0.f;
+}
+
+// One workgroup per (point, column range), grid-stride: every thread keeps
 // the k smallest admissible (s, j) of its columns, then k rounds of a
-// workgroup arg-min merge the 256 lists.
+// workgroup arg-min merge the 256 lists into the range's list.
 __global__ __launch_bounds__(256) void k_next_admissible(NextArgs a)
 {
     __shared__ double rs[4];
     __shared__ int rj[4], rt[4];
     __shared__ int win;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int q = blockIdx.x; q < a.nr; q += gridDim.x) {
+    const int nq = (a.d + 3) / 4;
+    for (int item = blockIdx.x; item < a.nr * a.splits; item += gridDim.x) {
         __syncthreads();
+        const int q = item / a.splits, sp = item % a.splits;
         const int i = a.rows[q];
         const int ci = a.comp[i];
         const int lim = a.limit[q];
         const double ls0 = a.lb_s[q];
         const int lj0 = a.lb_j[q];
-        const float* xi = a.X + (int64_t)i * a.ld;
+        float xi[DMAX];
+        {
+            const float4* src = reinterpret_cast<const float4*>(a.xp + (int64_t)i * DMAX);
+#pragma unroll
+            for (int f4 = 0; f4 < DMAX / 4; ++f4) {
+                const float4 v = src[f4];
+                xi[4 * f4] = v.x; xi[4 * f4 + 1] = v.y; xi[4 * f4 + 2] = v.z; xi[4 * f4 + 3] = v.w;
+            }
+        }
         double hs[KMAX];
         int hj[KMAX];
         for (int e = 0; e < KMAX; ++e) { hs[e] = __builtin_huge_val(); hj[e] = 0x7FFFFFFF; }
         const int k = a.k;
+        const int64_t c0 = a.n * sp / a.splits, c1 = a.n * (sp + 1) / a.splits;
         if (lim >= 0) {
-            for (int64_t j = tid; j < a.n; j += 256) {
-                if (a.comp[j] == ci || a.csize[j] > lim) continue;
-                const double s = sqdist_fp64(xi, a.X + j * a.ld, a.d);
+            for (int64_t j = c0 + tid; j < c1; j += 256) {
+                const int cj = a.comp[j];
+                if (cj == ci || a.csize[cj] > lim) continue;
+                // the key of eq. (1): FP64 differences and squares, summed in
+                // feature order
+                const float4* yp = reinterpret_cast<const float4*>(a.xp + j * DMAX);
+                double s = 0.0;
+                for (int f4 = 0; f4 < nq; ++f4) {
+                    const float4 y = yp[f4];
+                    const float yv[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        const int f = 4 * f4 + h;
+                        if (f < a.d) {
+                            const double df = __dsub_rn((double)xi[f], (double)yv[h]);
+                            const double sq = __dmul_rn(df, df);
+                            s = f == 0 ? sq : __dadd_rn(s, sq);
+                        }
+                    }
+                }
                 if (!sj_less(ls0, lj0, s, (int)j)) continue;          // not beyond the known prefix
                 if (__builtin_sqrt(s) > a.dmax) continue;
                 if (!sj_less(s, (int)j, hs[k - 1], hj[k - 1])) continue;
@@ -126,8 +172,8 @@ __global__ __launch_bounds__(256) void k_next_admissible(NextArgs a)
                     if (sj_less(rs[w], rj[w], s0, j0)) { s0 = rs[w]; j0 = rj[w]; t0 = rt[w]; }
                 win = s0 < __builtin_huge_val() ? t0 : -1;
                 if (win >= 0) {
-                    a.out_j[(int64_t)q * k + r] = j0;
-                    a.out_s[(int64_t)q * k + r] = s0;
+                    a.part_j[(int64_t)item * k + r] = j0;
+                    a.part_s[(int64_t)item * k + r] = s0;
                 }
             }
             __syncthreads();
@@ -137,8 +183,36 @@ __global__ __launch_bounds__(256) void k_next_admissible(NextArgs a)
             if (tid == wt) ++head;
             ++kept;
         }
-        if (tid == 0) a.out_len[q] = kept;
+        if (tid == 0) a.part_len[item] = kept;
     }
+}
+
+// The k smallest of a point's per-range lists (each ascending), one thread
+// per point.
+__global__ __launch_bounds__(256) void k_merge_ranges(NextArgs a)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.nr) return;
+    int pos[64];
+    for (int sp = 0; sp < a.splits; ++sp) pos[sp] = 0;
+    int kept = 0;
+    for (; kept < a.k; ++kept) {
+        int bsp = -1;
+        double bs = __builtin_huge_val();
+        int bj = 0x7FFFFFFF;
+        for (int sp = 0; sp < a.splits; ++sp) {
+            const int64_t it = (int64_t)q * a.splits + sp;
+            if (pos[sp] >= a.part_len[it]) continue;
+            const double s = a.part_s[it * a.k + pos[sp]];
+            const int j = a.part_j[it * a.k + pos[sp]];
+            if (sj_less(s, j, bs, bj)) { bs = s; bj = j; bsp = sp; }
+        }
+        if (bsp < 0) break;
+        ++pos[bsp];
+        a.out_j[(int64_t)q * a.k + kept] = bj;
+        a.out_s[(int64_t)q * a.k + kept] = bs;
+    }
+    a.out_len[q] = kept;
 }
 
 #define HIP_OK(x)                                  \
@@ -174,7 +248,15 @@ struct Workspace {
     int32_t* out_j;           // [n][k]
     double* out_s;            // [n][k]
     int32_t* out_len;         // [n]
+    float* xp;                // [n][DMAX]
+    int32_t* part_j;          // [max(n, PART_MIN)][k]
+    double* part_s;
+    int32_t* part_len;        // [max(n, PART_MIN)]
 };
+
+// per-range lists: a batch of nr points uses nr * splits <= max(nr, PART_MIN)
+constexpr int64_t PART_MIN = 8192;
+constexpr int64_t TARGET_GROUPS = 4096;
 
 size_t carve_ap(int64_t n, int32_t k, size_t knn_bytes, char* base, Workspace* w)
 {
@@ -200,6 +282,11 @@ size_t carve_ap(int64_t n, int32_t k, size_t knn_bytes, char* base, Workspace* w
     w->out_j = (int32_t*)take(N * K * 4);
     w->out_s = (double*)take(N * K * 8);
     w->out_len = (int32_t*)take(N * 4);
+    w->xp = (float*)take(N * DMAX * 4);
+    const size_t P = (size_t)std::max<int64_t>(n, PART_MIN);
+    w->part_j = (int32_t*)take(P * K * 4);
+    w->part_s = (double*)take(P * K * 8);
+    w->part_len = (int32_t*)take(P * 4);
     return off + 256;
 }
 
@@ -217,22 +304,23 @@ struct Process {
     std::vector<uint8_t> state;      // 0 candidate at cur, 1 prefix used up, 2 no pair left
     std::vector<uint8_t> queued;     // in `spent`
     std::vector<int32_t> spent;      // points in state 1 awaiting the next prefix
-    // clusters
-    std::vector<int32_t> par, size, ver;
+    // clusters: the cluster id of every point, kept current (members of the
+    // smaller side are relabelled at each union), sizes and versions by id
+    std::vector<int32_t> size, ver;
+    std::vector<int32_t> cid, mnext, mhead, mtail;
     // per-cluster meldable heaps of points (randomised meld)
     std::vector<int32_t> hl, hr, hroot;
     std::vector<PairKey> hkey;
+    // per-cluster meldable heaps of tree edges: node 2e and 2e + 1 are edge
+    // e at its two ends (after a union both copies sit in one heap)
+    const nnm_edge* tree = nullptr;
+    const nnm_options* opt = nullptr;
+    bool rows_ready = false;         // neighbour prefixes built
+    std::vector<int32_t> tl, tr, troot;
     std::mt19937 coin{12345};
     int64_t refills = 0, refilled_rows = 0, merges = 0;
+    double refill_ms = 0.0;
 
-    int32_t find(int32_t x)
-    {
-        while (par[x] != x) {
-            par[x] = par[par[x]];
-            x = par[x];
-        }
-        return x;
-    }
     int32_t meld(int32_t a, int32_t b)
     {
         if (a < 0) return b;
@@ -251,6 +339,23 @@ struct Process {
     {
         const int32_t r = hroot[c];
         hroot[c] = meld(hl[r], hr[r]);
+    }
+    bool tless(int32_t a, int32_t b) const
+    {
+        const nnm_edge& x = tree[a >> 1];
+        const nnm_edge& y = tree[b >> 1];
+        if (x.s != y.s) return x.s < y.s;
+        if (x.u != y.u) return x.u < y.u;
+        return x.v < y.v;
+    }
+    int32_t tmeld(int32_t a, int32_t b)
+    {
+        if (a < 0) return b;
+        if (b < 0) return a;
+        if (tless(b, a)) std::swap(a, b);
+        if (coin() & 1) tl[a] = tmeld(tl[a], b);
+        else tr[a] = tmeld(tr[a], b);
+        return a;
     }
     // largest admissible size of the other cluster for a cluster of size sx
     int32_t limit_of(int64_t sx) const
@@ -297,27 +402,23 @@ nnm_status refill(Process& p, const float* X, int32_t d, int64_t ld, Workspace& 
 {
     const int32_t nr = (int32_t)p.spent.size();
     if (nr == 0) return NNM_OK;
-    std::vector<int32_t> comp((size_t)p.n), csz((size_t)p.n), lim((size_t)nr), lbj((size_t)nr);
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<int32_t> lim((size_t)nr), lbj((size_t)nr);
     std::vector<double> lbs((size_t)nr);
-    for (int64_t i = 0; i < p.n; ++i) {
-        comp[(size_t)i] = p.find((int32_t)i);
-        csz[(size_t)i] = p.size[(size_t)comp[(size_t)i]];
-    }
     for (int32_t q = 0; q < nr; ++q) {
         const int32_t r = p.spent[(size_t)q];
         lbs[(size_t)q] = p.ls[(size_t)r * p.K + p.K - 1];
         lbj[(size_t)q] = p.lj[(size_t)r * p.K + p.K - 1];
-        lim[(size_t)q] = p.limit_of(csz[(size_t)r]);
+        lim[(size_t)q] = p.limit_of(p.size[(size_t)p.cid[(size_t)r]]);
     }
-    HIP_OK(hipMemcpyAsync(w.comp, comp.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(w.csize, csz.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(w.comp, p.cid.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(w.csize, p.size.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(w.rows, p.spent.data(), 4 * (size_t)nr, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(w.lb_s, lbs.data(), 8 * (size_t)nr, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(w.lb_j, lbj.data(), 4 * (size_t)nr, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(w.limit, lim.data(), 4 * (size_t)nr, hipMemcpyHostToDevice, s));
     NextArgs a;
-    a.X = X;
-    a.ld = ld;
+    a.xp = w.xp;
     a.d = d;
     a.k = p.K;
     a.n = p.n;
@@ -332,7 +433,14 @@ nnm_status refill(Process& p, const float* X, int32_t d, int64_t ld, Workspace& 
     a.out_j = w.out_j;
     a.out_s = w.out_s;
     a.out_len = w.out_len;
-    k_next_admissible<<<(unsigned)std::min(nr, 4096), 256, 0, s>>>(a);
+    // enough workgroups for the chip: few points get more column ranges
+    a.splits = nr >= TARGET_GROUPS / 2 ? 1 : (int32_t)std::min<int64_t>(64, (TARGET_GROUPS + nr - 1) / nr);
+    a.part_j = w.part_j;
+    a.part_s = w.part_s;
+    a.part_len = w.part_len;
+    const int64_t items = (int64_t)nr * a.splits;
+    k_next_admissible<<<(unsigned)std::min<int64_t>(items, 8192), 256, 0, s>>>(a);
+    k_merge_ranges<<<(unsigned)((nr + 255) / 256), 256, 0, s>>>(a);
     HIP_OK(hipGetLastError());
     std::vector<int32_t> oj((size_t)nr * p.K), ol((size_t)nr);
     std::vector<double> os((size_t)nr * p.K);
@@ -355,6 +463,69 @@ nnm_status refill(Process& p, const float* X, int32_t d, int64_t ld, Workspace& 
     p.refills += 1;
     p.refilled_rows += nr;
     p.spent.clear();
+    p.refill_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return NNM_OK;
+}
+
+// Every point's exact neighbour prefix (first needed when some cluster's
+// smallest outgoing tree edge is blocked); each point joins the heap of its
+// cluster as it is now.
+nnm_status build_prefixes(Process& p, const float* X, int32_t d, int64_t ld, Workspace& w,
+                          hipStream_t s)
+{
+    const size_t N = (size_t)p.n, K = (size_t)p.K;
+    nnm_status st = knn_build(X, p.n, d, ld, p.K, p.opt, w.knn_ws, w.knn_bytes, w.idx, w.sd, w.len,
+                              s, nullptr);
+    if (st != NNM_OK) return st;
+    k_pad_points<<<(unsigned)((p.n * DMAX + 255) / 256), 256, 0, s>>>(X, ld, d, p.n, w.xp);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(p.lj.data(), w.idx, 4 * N * K, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(p.ls.data(), w.sd, 8 * N * K, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(p.len.data(), w.len, 4 * N, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (size_t i = 0; i < N; ++i) {
+        if (p.len[i] == 0) {
+            p.state[i] = 2;
+            continue;
+        }
+        p.hkey[i] = p.key_at((int32_t)i);
+        p.push(p.cid[i], (int32_t)i);
+    }
+    p.rows_ready = true;
+    return NNM_OK;
+}
+
+// Advance every point of cluster X past the prefix entries it can no longer
+// use (inside X, not admissible, beyond dmax) and rebuild X's heap with
+// each point's current lower bound.
+nnm_status sweep(Process& p, int32_t X)
+{
+    std::vector<int32_t> rows, stack;
+    if (p.hroot[(size_t)X] >= 0) stack.push_back(p.hroot[(size_t)X]);
+    while (!stack.empty()) {
+        const int32_t r = stack.back();
+        stack.pop_back();
+        rows.push_back(r);
+        if (p.hl[(size_t)r] >= 0) stack.push_back(p.hl[(size_t)r]);
+        if (p.hr[(size_t)r] >= 0) stack.push_back(p.hr[(size_t)r]);
+    }
+    p.hroot[(size_t)X] = -1;
+    const int64_t sx = p.size[(size_t)X];
+    for (int32_t r : rows) {
+        while (p.state[(size_t)r] == 0) {
+            const int32_t j = p.lj[(size_t)r * p.K + p.cur[(size_t)r]];
+            const double sv = p.ls[(size_t)r * p.K + p.cur[(size_t)r]];
+            if (sqrt(sv) > p.dmax) {
+                p.state[(size_t)r] = 2;
+                break;
+            }
+            const int32_t cj = p.cid[(size_t)j];
+            if (cj != X && p.admissible(sx, p.size[(size_t)cj], sv)) break;
+            if (++p.cur[(size_t)r] >= p.len[(size_t)r]) p.use_up(r);
+        }
+        if (p.state[(size_t)r] == 0) p.hkey[(size_t)r] = p.key_at(r);
+        if (p.state[(size_t)r] != 2) p.push(X, r);
+    }
     return NNM_OK;
 }
 
@@ -362,6 +533,37 @@ nnm_status refill(Process& p, const float* X, int32_t d, int64_t ld, Workspace& 
 nnm_status best_of(Process& p, int32_t X, const float* Xd, int32_t d, int64_t ld, Workspace& w,
                    hipStream_t s, PairKey* out, int32_t* partner, bool* found)
 {
+    // the smallest tree edge leaving X (edges now inside X are dropped)
+    while (p.troot[(size_t)X] >= 0) {
+        const int32_t t = p.troot[(size_t)X];
+        const nnm_edge& e = p.tree[t >> 1];
+        if (p.cid[(size_t)e.u] != p.cid[(size_t)e.v]) break;
+        p.troot[(size_t)X] = p.tmeld(p.tl[(size_t)t], p.tr[(size_t)t]);
+    }
+    if (p.troot[(size_t)X] >= 0) {
+        const nnm_edge& e = p.tree[p.troot[(size_t)X] >> 1];
+        const int32_t Y = p.cid[(size_t)e.u] == X ? p.cid[(size_t)e.v] : p.cid[(size_t)e.u];
+        if (p.admissible(p.size[(size_t)X], p.size[(size_t)Y], e.s)) {
+            *out = PairKey{e.s, e.u, e.v};
+            *partner = Y;
+            *found = true;
+            return NNM_OK;
+        }
+        // every pair leaving X is at least as long as this edge: beyond
+        // dmax, none is admissible; and a cluster too large for any partner
+        // has none either
+        if (sqrt(e.s) > p.dmax || p.limit_of(p.size[(size_t)X]) < 1) {
+            *found = false;
+            return NNM_OK;
+        }
+    } else {
+        *found = false;          // X holds all its instance's points
+        return NNM_OK;
+    }
+    if (!p.rows_ready) {
+        nnm_status st = build_prefixes(p, Xd, d, ld, w, s);
+        if (st != NNM_OK) return st;
+    }
     for (;;) {
         const int32_t r = p.hroot[(size_t)X];
         if (r < 0) {
@@ -373,13 +575,17 @@ nnm_status best_of(Process& p, int32_t X, const float* Xd, int32_t d, int64_t ld
             continue;
         }
         if (p.state[(size_t)r] == 1) {
-            nnm_status st = refill(p, Xd, d, ld, w, s);
+            // a used-up prefix at the top: bring every point of X past the
+            // entries it can no longer use, then fetch all the next prefixes
+            // in one scan
+            nnm_status st = sweep(p, X);
+            if (st == NNM_OK) st = refill(p, Xd, d, ld, w, s);
             if (st != NNM_OK) return st;
             continue;
         }
         const int32_t j = p.lj[(size_t)r * p.K + p.cur[(size_t)r]];
         const double sv = p.ls[(size_t)r * p.K + p.cur[(size_t)r]];
-        const int32_t Y = p.find(j);
+        const int32_t Y = p.cid[(size_t)j];
         if (Y == X || !p.admissible(p.size[(size_t)X], p.size[(size_t)Y], sv)) {
             p.pop(X);
             if (sqrt(sv) > p.dmax) {
@@ -435,15 +641,20 @@ extern "C" nnm_status allpairs_cut_workspace_size(int64_t n, int32_t d, int32_t 
 }
 
 extern "C" nnm_status cluster_cut_allpairs(const float* X_dev, int64_t n, int32_t d, int64_t ld,
-                                           const nnm_cut_params* prm, int32_t k,
-                                           const nnm_options* opt, void* ws_dev, size_t ws_bytes,
-                                           void* stream, int32_t* labels_host, int64_t* n_clusters,
-                                           int64_t* stats)
+                                           const nnm_edge* edges_host, const nnm_cut_params* prm,
+                                           int32_t k, const nnm_options* opt, void* ws_dev,
+                                           size_t ws_bytes, void* stream, int32_t* labels_host,
+                                           int64_t* n_clusters, int64_t* stats)
 {
     if (!X_dev || !prm || !ws_dev || !labels_host || !n_clusters) return NNM_EINVAL;
     if (n < 1 || n > (int64_t)0x7FFFFFF0 || d < 1 || d > DMAX || ld < d || k < 0 || k > KMAX)
         return NNM_EINVAL;
+    if (n > 1 && !edges_host) return NNM_EINVAL;
     if (std::isnan(prm->dmax) || prm->dmax < 0.0) return NNM_EINVAL;
+    for (int64_t e = 0; e + 1 < n; ++e) {
+        const nnm_edge& x = edges_host[e];
+        if (x.u < 0 || x.u >= x.v || x.v >= n || !(x.s >= 0.0)) return NNM_EINVAL;
+    }
     const int32_t K = k > 0 ? k : DEFAULT_DEPTH;
     size_t need = 0;
     nnm_status st = allpairs_cut_workspace_size(n, d, K, opt, &need);
@@ -470,41 +681,42 @@ extern "C" nnm_status cluster_cut_allpairs(const float* X_dev, int64_t n, int32_
     p.cur.assign(N, 0);
     p.state.assign(N, 0);
     p.queued.assign(N, 0);
-    p.par.resize(N);
     p.size.assign(N, 1);
     p.ver.assign(N, 0);
     p.hl.assign(N, -1);
     p.hr.assign(N, -1);
     p.hroot.assign(N, -1);
     p.hkey.resize(N);
-    for (size_t i = 0; i < N; ++i) p.par[i] = (int32_t)i;
-    if (n > 1) {
-        // every point's exact neighbour prefix
-        st = knn_build(X_dev, n, d, ld, K, opt, w.knn_ws, w.knn_bytes, w.idx, w.sd, w.len, stream,
-                       nullptr);
-        if (st != NNM_OK) return st;
-        HIP_OK(hipMemcpyAsync(p.lj.data(), w.idx, 4 * N * K, hipMemcpyDeviceToHost, s));
-        HIP_OK(hipMemcpyAsync(p.ls.data(), w.sd, 8 * N * K, hipMemcpyDeviceToHost, s));
-        HIP_OK(hipMemcpyAsync(p.len.data(), w.len, 4 * N, hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
+    p.cid.resize(N);
+    p.mnext.assign(N, -1);
+    p.mhead.resize(N);
+    p.mtail.resize(N);
+    for (size_t i = 0; i < N; ++i) p.cid[i] = p.mhead[i] = p.mtail[i] = (int32_t)i;
+    p.tree = edges_host;
+    const size_t M = N > 0 ? 2 * (N - 1) : 0;
+    p.tl.assign(M, -1);
+    p.tr.assign(M, -1);
+    p.troot.assign(N, -1);
+    for (size_t e = 0; e + 1 < N; ++e) {
+        p.troot[(size_t)edges_host[e].u] = p.tmeld(p.troot[(size_t)edges_host[e].u], (int32_t)(2 * e));
+        p.troot[(size_t)edges_host[e].v] = p.tmeld(p.troot[(size_t)edges_host[e].v], (int32_t)(2 * e + 1));
     }
+    p.opt = opt;
     const bool prio = p.kl4 > 1;
     std::priority_queue<Entry, std::vector<Entry>, std::greater<Entry>> G;
+    // a point's smallest tree edge is its smallest pair: a lower bound of its best
     for (size_t i = 0; i < N; ++i) {
-        if (p.len[i] == 0) {
-            p.state[i] = 2;
-            continue;
-        }
-        p.hkey[i] = p.key_at((int32_t)i);
-        p.push((int32_t)i, (int32_t)i);
-        G.push(Entry{prio ? 0 : 1, p.hkey[i], (int32_t)i, 0});
+        const int32_t t = p.troot[i];
+        if (t < 0) continue;
+        const nnm_edge& e = edges_host[t >> 1];
+        G.push(Entry{prio ? 0 : 1, PairKey{e.s, e.u, e.v}, (int32_t)i, 0});
     }
     int64_t clusters = n;
     while (!G.empty()) {
         if (p.kl1 > 0 && clusters <= p.kl1) break;
         const Entry e = G.top();
         G.pop();
-        if (p.find(e.c) != e.c || p.ver[(size_t)e.c] != e.ver) continue;
+        if (p.cid[(size_t)e.c] != e.c || p.ver[(size_t)e.c] != e.ver) continue;
         PairKey b;
         int32_t Y = -1;
         bool found = false;
@@ -521,10 +733,14 @@ extern "C" nnm_status cluster_cut_allpairs(const float* X_dev, int64_t n, int32_
         int32_t X = e.c;
         int32_t Z = X, o = Y;
         if (p.size[(size_t)Y] > p.size[(size_t)X]) std::swap(Z, o);
-        p.par[(size_t)o] = Z;
         p.size[(size_t)Z] += p.size[(size_t)o];
         p.hroot[(size_t)Z] = p.meld(p.hroot[(size_t)Z], p.hroot[(size_t)o]);
         p.hroot[(size_t)o] = -1;
+        p.troot[(size_t)Z] = p.tmeld(p.troot[(size_t)Z], p.troot[(size_t)o]);
+        p.troot[(size_t)o] = -1;
+        for (int32_t x = p.mhead[(size_t)o]; x >= 0; x = p.mnext[(size_t)x]) p.cid[(size_t)x] = Z;
+        p.mnext[(size_t)p.mtail[(size_t)Z]] = p.mhead[(size_t)o];
+        p.mtail[(size_t)Z] = p.mtail[(size_t)o];
         p.ver[(size_t)Z] += 1;
         p.ver[(size_t)o] += 1;
         --clusters;
@@ -535,7 +751,7 @@ extern "C" nnm_status cluster_cut_allpairs(const float* X_dev, int64_t n, int32_
     std::vector<int64_t> map(N, -1);
     int64_t next = 0;
     for (size_t i = 0; i < N; ++i) {
-        const int32_t r = p.find((int32_t)i);
+        const int32_t r = p.cid[i];
         if (map[(size_t)r] < 0) map[(size_t)r] = next++;
         labels_host[i] = (int32_t)map[(size_t)r];
     }
@@ -545,6 +761,7 @@ extern "C" nnm_status cluster_cut_allpairs(const float* X_dev, int64_t n, int32_
         stats[1] = p.refills;
         stats[2] = p.refilled_rows;
         stats[3] = K;
+        stats[4] = (int64_t)(p.refill_ms * 1000.0);
     }
     return NNM_OK;
 }

@@ -292,12 +292,22 @@ def test_allpairs_cut_rejects_bad_arguments_before_device_work():
     labels = np.zeros(1000, np.int32)
     k = ctypes.c_int64(0)
 
-    def call(X=1234, n=1000, d=8, ld=8, prm=p, kk=0, ws=1, wsb=None):
-        return L.cluster_cut_allpairs(ctypes.c_void_p(X), n, d, ld, ctypes.byref(prm), kk,
-                                      ctypes.byref(o), ctypes.c_void_p(ws),
+    edges = np.zeros((999, 3), np.float64)
+    ev = edges.view(np.int32).reshape(-1, 6)
+    ev[:, 0] = 0
+    ev[:, 1] = np.arange(1, 1000)
+
+    def call(X=1234, n=1000, d=8, ld=8, prm=p, kk=0, ws=1, wsb=None, e=edges):
+        return L.cluster_cut_allpairs(ctypes.c_void_p(X), n, d, ld,
+                                      ctypes.c_void_p(e.ctypes.data if e is not None else None),
+                                      ctypes.byref(prm), kk, ctypes.byref(o), ctypes.c_void_p(ws),
                                       nb.value if wsb is None else wsb, None,
                                       ctypes.c_void_p(labels.ctypes.data), ctypes.byref(k), None)
     assert call(X=0) == N.NNM_EINVAL
+    assert call(e=None) == N.NNM_EINVAL
+    bad = edges.copy()
+    bad.view(np.int32).reshape(-1, 6)[5, 1] = 0          # u >= v
+    assert call(e=bad) == N.NNM_EINVAL
     assert call(ws=0) == N.NNM_EINVAL
     assert call(kk=40) == N.NNM_EINVAL
     assert call(ld=4) == N.NNM_EINVAL

@@ -77,5 +77,5 @@ def test_equals_tree_cut_without_size_caps(nnm):
     for kw in (dict(kl1=64), dict(kl1=64, kl4=50, dmax=0.2), dict(dmax=0.1)):
         _say("allpairs vs tree cut", X.shape, kw)
         want, wk = nnm.cluster_cut(tree, **kw)
-        got, gk = nnm.cluster_cut_allpairs(Xd, **kw)
+        got, gk = nnm.cluster_cut_allpairs(Xd, tree, **kw)
         assert gk == wk and np.array_equal(got, want), kw
