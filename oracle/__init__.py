@@ -51,6 +51,16 @@ def _load():
     lib.oracle_cut.argtypes = [vp, vp, vp, vp, i64, i64, i64, i64, i64, dbl, _i32p,
                                ctypes.POINTER(i64)]
     lib.oracle_cut.restype = c_int
+    lib.oracle_prim_mst_metric.argtypes = [_f32p, i64, i32, i64, i32, _i32p, _i32p, _f64p, _f64p,
+                                            c_int]
+    lib.oracle_prim_mst_metric.restype = c_int
+    lib.oracle_knn_metric.argtypes = [_f32p, i64, i32, i64, i32, vp, i64, i32, _i32p, _f64p, _i32p,
+                                       c_int]
+    lib.oracle_knn_metric.restype = c_int
+    lib.oracle_normalize_rows.argtypes = [_f32p, i64, i32, i64, _f32p]
+    lib.oracle_normalize_rows.restype = c_int
+    lib.oracle_pair_key.argtypes = [_f32p, _f32p, i32, i32]
+    lib.oracle_pair_key.restype = dbl
     lib.oracle_cut_allpairs.argtypes = [_f32p, i64, i32, i64, i64, i64, i64, i64, dbl, _i32p,
                                          ctypes.POINTER(i64)]
     lib.oracle_cut_allpairs.restype = c_int
@@ -78,20 +88,47 @@ def sqdist(a, b) -> float:
     return float(_load().oracle_sqdist(a, b, a.shape[0]))
 
 
-def prim_mst(X, threads: int = 0):
+# metric names -> the oracle's metric codes; "cosine" is the Euclidean
+# metric on rows scaled to unit length
+METRICS = {"euclidean": 0, "l1": 1, "linf": 2, "cosine": 0}
+
+
+def normalize_rows(X):
+    """Rows scaled to unit Euclidean length (FP64 norm, one rounding per
+    feature; zero rows stay zero)."""
+    X = _as_x(X)
+    n, d = X.shape
+    out = np.zeros((max(n, 1), d), np.float32)
+    rc = _load().oracle_normalize_rows(X, n, d, d, out)
+    if rc != 0:
+        raise ValueError(f"oracle_normalize_rows failed ({rc})")
+    return out[:n]
+
+
+def pair_key(a, b, metric="euclidean") -> float:
+    """The FP64 key of one pair under a metric (cosine: of the given rows)."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    return float(_load().oracle_pair_key(a, b, a.shape[0], METRICS[metric]))
+
+
+def prim_mst(X, threads: int = 0, metric: str = "euclidean"):
     """Key-ordered minimum spanning tree by dense Prim.
 
     Returns (u int32, v int32, s float64, w float64), n-1 edges sorted by
-    (s, u, v), u < v, w = sqrt(s).
+    (s, u, v), u < v, w the distance (sqrt(s) for the Euclidean and cosine
+    metrics, s for L1 and L-infinity).
     """
     X = _as_x(X)
+    if metric == "cosine":
+        X = normalize_rows(X)
     n, d = X.shape
     m = max(n - 1, 0)
     u = np.zeros(max(m, 1), np.int32)
     v = np.zeros(max(m, 1), np.int32)
     s = np.zeros(max(m, 1), np.float64)
     w = np.zeros(max(m, 1), np.float64)
-    rc = _load().oracle_prim_mst(X, n, d, d, u, v, s, w, int(threads))
+    rc = _load().oracle_prim_mst_metric(X, n, d, d, METRICS[metric], u, v, s, w, int(threads))
     if rc != 0:
         raise ValueError(f"oracle_prim_mst failed ({rc})")
     return u[:m], v[:m], s[:m], w[:m]
@@ -127,9 +164,11 @@ def cut_allpairs(X, kl1=0, kl2=-1, kl3=-1, kl4=0, dmax=float("inf")):
     return labels[: int(n)], int(k.value)
 
 
-def knn(X, k: int, rows=None, threads: int = 0):
+def knn(X, k: int, rows=None, threads: int = 0, metric: str = "euclidean"):
     """Exact k nearest neighbours by key (s, j), j != i, for the query rows."""
     X = _as_x(X)
+    if metric == "cosine":
+        X = normalize_rows(X)
     n, d = X.shape
     if rows is None:
         rows_a = np.arange(n, dtype=np.int64)
@@ -139,8 +178,9 @@ def knn(X, k: int, rows=None, threads: int = 0):
     idx = np.zeros((max(q, 1), k), np.int32)
     s = np.zeros((max(q, 1), k), np.float64)
     ln = np.zeros(max(q, 1), np.int32)
-    rc = _load().oracle_knn(X, n, d, d, rows_a.ctypes.data_as(ctypes.c_void_p), q, int(k),
-                            idx, s, ln, int(threads))
+    rc = _load().oracle_knn_metric(X, n, d, d, METRICS[metric],
+                                   rows_a.ctypes.data_as(ctypes.c_void_p), q, int(k), idx, s, ln,
+                                   int(threads))
     if rc != 0:
         raise ValueError(f"oracle_knn failed ({rc})")
     return idx[:q], s[:q], ln[:q]

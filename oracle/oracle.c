@@ -43,6 +43,9 @@
  *    rather than a cut of its tree): oracle_cut_allpairs.  It equals the
  *    cut of the tree whenever KL2 and KL3 are off.
  *
+ *  - Other metrics (L1, L-infinity; cosine as the Euclidean metric on rows
+ *    scaled to unit length) for the tree and the neighbour lists.
+ *
  *  - Exact k nearest neighbours and the exact nearest neighbour outside a
  *    given labelling, both by the same key, used to check samples of large
  *    runs one row at a time.
@@ -74,6 +77,71 @@ static double sq_dist(const float *a, const float *b, int32_t d)
 double oracle_sqdist(const float *a, const float *b, int32_t d)
 {
     return sq_dist(a, b, d);
+}
+
+/*
+ * Other metrics ("Overall idea of the algorithm": after eq. (1) the paper
+ * allows another metric to be chosen).  The key of a pair under
+ *   metric 0  Euclidean: the squared distance above (distance = sqrt(key));
+ *   metric 1  L1 (city block): sum over f of |x_f - y_f|, each term exact in
+ *             FP64, added left to right (distance = key);
+ *   metric 2  L-infinity (Chebyshev): max over f of |x_f - y_f|, exact
+ *             (distance = key).
+ * Cosine dissimilarity is the Euclidean metric on rows scaled to unit
+ * length (oracle_normalize_rows), with distance sqrt(2 - 2 cos).
+ */
+static double pair_key(const float *a, const float *b, int32_t d, int metric)
+{
+    if (metric == 1) {
+        double s = 0.0;
+        for (int32_t f = 0; f < d; ++f) {
+            double t = fabs((double)a[f] - (double)b[f]);
+            s = (f == 0) ? t : s + t;
+        }
+        return s;
+    }
+    if (metric == 2) {
+        double s = 0.0;
+        for (int32_t f = 0; f < d; ++f) {
+            double t = fabs((double)a[f] - (double)b[f]);
+            if (t > s) s = t;
+        }
+        return s;
+    }
+    return sq_dist(a, b, d);
+}
+
+static double key_to_distance(double s, int metric)
+{
+    return (metric == 1 || metric == 2) ? s : sqrt(s);
+}
+
+double oracle_pair_key(const float *a, const float *b, int32_t d, int32_t metric)
+{
+    return pair_key(a, b, d, metric);
+}
+
+/*
+ * Rows scaled to unit Euclidean length: the norm is the square root of the
+ * FP64 sum of squares in feature order; every feature is divided by it in
+ * FP64 and rounded once to FP32.  A zero row stays zero.
+ */
+int oracle_normalize_rows(const float *X, int64_t n, int32_t d, int64_t ld, float *out)
+{
+    if (!X || !out || n < 1 || d < 1 || ld < d) return ORACLE_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        const float *x = X + i * ld;
+        double q = 0.0;
+        for (int32_t f = 0; f < d; ++f) {
+            double v = (double)x[f];
+            double sq = v * v;
+            q = (f == 0) ? sq : q + sq;
+        }
+        double nrm = sqrt(q);
+        for (int32_t f = 0; f < d; ++f)
+            out[i * d + f] = nrm > 0.0 ? (float)((double)x[f] / nrm) : 0.0f;
+    }
+    return ORACLE_OK;
 }
 
 /* Lexicographic (s, lo, hi) order. */
@@ -110,10 +178,23 @@ static int n_threads(int want)
  * Dense Prim over the complete graph.  out_u/out_v/out_s/out_w hold n-1
  * edges on return, u < v, sorted by key; out_w = sqrt(out_s).
  */
+int oracle_prim_mst_metric(const float *X, int64_t n, int32_t d, int64_t ld,
+                           int32_t metric, int32_t *out_u, int32_t *out_v,
+                           double *out_s, double *out_w, int nthreads);
+
 int oracle_prim_mst(const float *X, int64_t n, int32_t d, int64_t ld,
                     int32_t *out_u, int32_t *out_v, double *out_s,
                     double *out_w, int nthreads)
 {
+    return oracle_prim_mst_metric(X, n, d, ld, 0, out_u, out_v, out_s, out_w, nthreads);
+}
+
+/* The same under metric 0, 1 or 2 (keys and distances as for pair_key). */
+int oracle_prim_mst_metric(const float *X, int64_t n, int32_t d, int64_t ld,
+                           int32_t metric, int32_t *out_u, int32_t *out_v,
+                           double *out_s, double *out_w, int nthreads)
+{
+    if (metric < 0 || metric > 2) return ORACLE_EINVAL;
     if (!X || n < 1 || d < 1 || ld < d) return ORACLE_EINVAL;
     if (n == 1) return ORACLE_OK;
     if (!out_u || !out_v || !out_s || !out_w) return ORACLE_EINVAL;
@@ -158,7 +239,7 @@ int oracle_prim_mst(const float *X, int64_t n, int32_t d, int64_t ld,
             int64_t bpos = -1;
 #pragma omp for schedule(static)
             for (int64_t r = 0; r < m; ++r) {
-                double s = sq_dist(ax, rx + r * d, d);
+                double s = pair_key(ax, rx + r * d, d, metric);
                 int32_t v = rid[r];
                 int32_t lo = a < v ? a : v;
                 int32_t hi = a < v ? v : a;
@@ -202,7 +283,7 @@ int oracle_prim_mst(const float *X, int64_t n, int32_t d, int64_t ld,
         out_u[e] = edges[e].lo;
         out_v[e] = edges[e].hi;
         out_s[e] = edges[e].s;
-        out_w[e] = sqrt(edges[e].s);
+        out_w[e] = key_to_distance(edges[e].s, metric);
     }
     free(rid); free(rx); free(bs); free(blo); free(bhi); free(ax);
     free(tloc); free(tpos); free(edges);
@@ -412,12 +493,27 @@ int oracle_cut_allpairs(const float *X, int64_t n, int32_t d, int64_t ld,
  * For each query row i = rows[q]: the k smallest keys (s, j) over j != i,
  * ascending; out_idx/out_s are [nrows][k]; out_len[q] = min(k, n-1).
  */
+int oracle_knn_metric(const float *X, int64_t n, int32_t d, int64_t ld,
+                      int32_t metric, const int64_t *rows, int64_t nrows,
+                      int32_t k, int32_t *out_idx, double *out_s,
+                      int32_t *out_len, int nthreads);
+
 int oracle_knn(const float *X, int64_t n, int32_t d, int64_t ld,
                const int64_t *rows, int64_t nrows, int32_t k,
                int32_t *out_idx, double *out_s, int32_t *out_len,
                int nthreads)
 {
+    return oracle_knn_metric(X, n, d, ld, 0, rows, nrows, k, out_idx, out_s, out_len, nthreads);
+}
+
+/* The same under metric 0, 1 or 2 (keys as for pair_key). */
+int oracle_knn_metric(const float *X, int64_t n, int32_t d, int64_t ld,
+                      int32_t metric, const int64_t *rows, int64_t nrows,
+                      int32_t k, int32_t *out_idx, double *out_s,
+                      int32_t *out_len, int nthreads)
+{
     if (!X || n < 1 || d < 1 || ld < d || k < 1 || nrows < 0) return ORACLE_EINVAL;
+    if (metric < 0 || metric > 2) return ORACLE_EINVAL;
     int nt = n_threads(nthreads);
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
@@ -429,7 +525,7 @@ int oracle_knn(const float *X, int64_t n, int32_t d, int64_t ld,
         int32_t len = 0;
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
-            double s = sq_dist(X + i * ld, X + j * ld, d);
+            double s = pair_key(X + i * ld, X + j * ld, d, metric);
             /* insert (s, j) into the ascending list if it belongs there */
             if (len == k && !(s < bsv[k - 1] || (s == bsv[k - 1] && j < bi[k - 1])))
                 continue;

@@ -413,3 +413,86 @@ def test_allpairs_process_bypasses_a_blocked_tree_edge():
     assert tk == 3 and tl.tolist() == [0, 1, 1, 1, 2]
     # KL1 = 2 stops there as well; KL1 = 3 stops before the bypass
     assert oracle.cut_allpairs(X, kl1=3, kl3=3)[1] == 3
+
+
+# ---- other metrics ("Overall idea of the algorithm": another metric may be
+# chosen in place of eq. (1)) ------------------------------------------------
+
+@pytest.mark.parametrize("metric,name", [("l1", "cityblock"), ("linf", "chebyshev")])
+def test_metric_keys_match_scipy(metric, name):
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(41)
+    X = (rng.standard_normal((60, 7)) * rng.uniform(0.01, 100, size=7)).astype(np.float32)
+    D = cdist(X.astype(np.float64), X.astype(np.float64), name)
+    for i in range(0, 60, 7):
+        for j in range(60):
+            got = oracle.pair_key(X[i], X[j], metric)
+            if metric == "linf":
+                assert got == D[i, j]                       # a max of exact terms
+            else:
+                assert abs(got - D[i, j]) <= 8 * 2.0 ** -53 * D[i, j]
+    # integer data: every key exact
+    Xi = rng.integers(-50, 50, size=(30, 5)).astype(np.float32)
+    Di = cdist(Xi.astype(np.float64), Xi.astype(np.float64), name)
+    for i in range(30):
+        for j in range(30):
+            assert oracle.pair_key(Xi[i], Xi[j], metric) == Di[i, j]
+
+
+@pytest.mark.parametrize("metric,name", [("l1", "cityblock"), ("linf", "chebyshev"),
+                                         ("euclidean", "euclidean")])
+def test_metric_tree_weights_match_scipy_single_linkage(metric, name):
+    from scipy.cluster.hierarchy import linkage
+    rng = np.random.default_rng(42)
+    X = rng.standard_normal((300, 6)).astype(np.float32)
+    u, v, s, w = oracle.prim_mst(X, metric=metric)
+    Z = linkage(X.astype(np.float64), method="single", metric=name)
+    assert np.allclose(np.sort(w), np.sort(Z[:, 2]), rtol=1e-12, atol=0)
+    if metric != "euclidean":
+        assert np.array_equal(s, w)
+
+
+@pytest.mark.parametrize("metric", ["l1", "linf"])
+def test_metric_tree_equals_kruskal(metric):
+    """Prim under L1 / L-infinity against Kruskal over every pair's key
+    (scipy's union-find-free minimum_spanning_tree on the dense matrix gives
+    the same edge set when the keys are distinct)."""
+    from scipy.sparse.csgraph import minimum_spanning_tree
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(43)
+    X = rng.uniform(0, 1, size=(200, 5)).astype(np.float32)
+    u, v, s, w = oracle.prim_mst(X, metric=metric)
+    D = np.array([[oracle.pair_key(X[i], X[j], metric) for j in range(200)] for i in range(200)])
+    T = minimum_spanning_tree(D).tocoo()
+    # the tree's weights are unique whatever the ties; its edges are when
+    # the keys are distinct
+    assert np.array_equal(np.sort(T.data), s)
+    if len(np.unique(D[np.triu_indices(200, 1)])) == 200 * 199 // 2:
+        want = sorted((min(a, b), max(a, b)) for a, b in zip(T.row.tolist(), T.col.tolist()))
+        assert sorted(zip(u.tolist(), v.tolist())) == want
+    name = "cityblock" if metric == "l1" else "chebyshev"
+    Dc = cdist(X.astype(np.float64), X.astype(np.float64), name)
+    assert np.allclose(D, Dc, rtol=1e-14, atol=0)
+
+
+def test_cosine_rows_and_tree():
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(44)
+    X = rng.standard_normal((150, 8)).astype(np.float32)
+    X[7] = 0.0                                   # a zero row stays zero
+    Xn = oracle.normalize_rows(X)
+    ref = X.astype(np.float64) / np.linalg.norm(X.astype(np.float64), axis=1, keepdims=True)
+    ref[7] = 0.0
+    assert np.array_equal(Xn, ref.astype(np.float32))
+    norms = np.linalg.norm(Xn.astype(np.float64), axis=1)
+    assert np.all(np.abs(norms[np.arange(150) != 7] - 1.0) < 1e-6) and norms[7] == 0.0
+    u, v, s, w = oracle.prim_mst(X, metric="cosine")
+    keep = np.arange(150) != 7
+    C = cdist(X[keep].astype(np.float64), X[keep].astype(np.float64), "cosine")
+    # tree edges between non-zero rows: s = |x^ - y^|^2 = 2 (1 - cos) up to rounding
+    idx = np.cumsum(keep) - 1
+    for a, b, sv in zip(u.tolist(), v.tolist(), s.tolist()):
+        if a != 7 and b != 7:
+            assert abs(sv - 2.0 * C[idx[a], idx[b]]) < 1e-6
+    uu, vv, ss, ww = oracle.prim_mst(Xn)
+    assert np.array_equal(uu, u) and np.array_equal(ss, s)
