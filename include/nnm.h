@@ -133,8 +133,33 @@ typedef struct {
                                first round (0: 4096)                          */
     int32_t split_target;   /* ... and in the bounded scans of later rounds
                                (0: 8192)                                      */
-    int32_t reserved[6];
+    int32_t metric;         /* nnm_metric (0: Euclidean, eq. (1))            */
+    int32_t reserved[5];
 } nnm_options;
+
+/*
+ * The pair metric ("Overall idea of the algorithm": another metric may take
+ * the place of eq. (1)).  Keys and reported distances w:
+ *   EUCLIDEAN  s = the squared distance above, w = sqrt(s);
+ *   L1         s = sum over f of |x_f - y_f| (each term exact in FP64, added
+ *              left to right), w = s;
+ *   LINF       s = max over f of |x_f - y_f| (exact), w = s;
+ *   COSINE     every row is first scaled to unit Euclidean length (norm: the
+ *              square root of the FP64 sum of squares in feature order;
+ *              each feature divided by it in FP64 and rounded once to FP32;
+ *              a zero row stays zero), then EUCLIDEAN on those rows:
+ *              w = sqrt(2 - 2 cos) up to that rounding.
+ * L1 and LINF have no dot-product form: their candidates always come from
+ * the FP32 vector path (AUTO picks it; BF16 / FP16 / FP8 give
+ * NNM_EUNSUPPORTED).  Pairs are ordered by (s, min index, max index) in
+ * every metric.
+ */
+typedef enum {
+    NNM_METRIC_EUCLIDEAN = 0,
+    NNM_METRIC_L1 = 1,
+    NNM_METRIC_LINF = 2,
+    NNM_METRIC_COSINE = 3
+} nnm_metric;
 
 /* Per-call measurements (all optional to read; filled when non-NULL). */
 typedef struct {

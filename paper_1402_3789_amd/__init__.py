@@ -31,7 +31,7 @@ def _torch():
 
 def options(precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
             force_fallback=False, col_splits=0, fixed_chunks=False, graph=False,
-            split_target0=0, split_target=0) -> N.Options:
+            split_target0=0, split_target=0, metric="euclidean") -> N.Options:
     o = N.Options()
     N.lib().nnm_default_options(ctypes.byref(o))
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
@@ -44,6 +44,7 @@ def options(precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
     o.graph = int(bool(graph))
     o.split_target0 = int(split_target0)
     o.split_target = int(split_target)
+    o.metric = N.METRIC[metric] if isinstance(metric, str) else int(metric)
     return o
 
 
@@ -136,7 +137,7 @@ class Tree:
 def mst_build(X, precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
               force_fallback=False, col_splits=0, stream=None, workspace=None,
               fixed_chunks=False, graph=False, split_target0=0, split_target=0,
-              tuned=False) -> Tree:
+              tuned=False, metric="euclidean") -> Tree:
     """Exact key-ordered minimum spanning tree of the rows of X (device).
     graph=True replays the merge rounds after the first from a captured
     hipGraph (kept for later calls with the same buffers and settings).
@@ -150,7 +151,7 @@ def mst_build(X, precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
                                                   split_target0=split_target0,
                                                   split_target=split_target))
     o = options(precision, kw["knn_k"], survivor_cap, disable_prune, force_fallback, col_splits,
-                fixed_chunks, kw["graph"], kw["split_target0"], kw["split_target"])
+                fixed_chunks, kw["graph"], kw["split_target0"], kw["split_target"], metric)
     nb = ctypes.c_size_t(0)
     N.check("mst_workspace_size", L.mst_workspace_size(n, d, ctypes.byref(o), ctypes.byref(nb)))
     ws = (workspace or _WS).get(nb.value, X.device)
@@ -182,12 +183,12 @@ def mst_build_noalloc(X, precision="auto", knn_k=0, survivor_cap=0, disable_prun
 
 
 def knn_build(X, k=16, precision="auto", survivor_cap=0, force_fallback=False,
-              col_splits=0, stream=None, workspace=None, with_report=False):
+              col_splits=0, stream=None, workspace=None, with_report=False, metric="euclidean"):
     """Exact k nearest neighbours of every row: (idx int32, s float64, len int32)."""
     torch = _torch()
     n, d, ld = _check_x(X)
     L = N.lib()
-    o = options(precision, k, survivor_cap, False, force_fallback, col_splits)
+    o = options(precision, k, survivor_cap, False, force_fallback, col_splits, metric=metric)
     nb = ctypes.c_size_t(0)
     N.check("knn_workspace_size",
             L.knn_workspace_size(n, d, int(k), ctypes.byref(o), ctypes.byref(nb)))
@@ -225,7 +226,7 @@ def _instances(Xs):
 
 def mst_build_batched(Xs, precision="auto", knn_k=0, survivor_cap=0, force_fallback=False,
                       stream=None, workspace=None, col_splits=0, graph=False, split_target0=0,
-                      split_target=0, tuned=False):
+                      split_target=0, tuned=False, metric="euclidean"):
     """Independent trees of many instances in one call; list of Tree."""
     torch = _torch()
     L = N.lib()
@@ -235,7 +236,7 @@ def mst_build_batched(Xs, precision="auto", knn_k=0, survivor_cap=0, force_fallb
                                                             split_target0=split_target0,
                                                             split_target=split_target))
     o = options(precision, kw["knn_k"], survivor_cap, False, force_fallback, col_splits, False,
-                kw["graph"], kw["split_target0"], kw["split_target"])
+                kw["graph"], kw["split_target0"], kw["split_target"], metric)
     inst, outs = _instances(Xs)
     nb = ctypes.c_size_t(0)
     N.check("mst_batched_workspace_size",

@@ -21,6 +21,7 @@ TUNE_MAX_TRIALS = 32
 
 PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "auto": 3, "fp16": 4}
 PREC_NAME = {v: k for k, v in PREC.items()}
+METRIC = {"euclidean": 0, "l1": 1, "linf": 2, "cosine": 3}
 
 
 class Edge(ctypes.Structure):
@@ -40,7 +41,7 @@ class Options(ctypes.Structure):
                 ("force_fallback", ctypes.c_int32), ("col_splits", ctypes.c_int32),
                 ("fixed_chunks", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("split_target0", ctypes.c_int32), ("split_target", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("metric", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class Report(ctypes.Structure):

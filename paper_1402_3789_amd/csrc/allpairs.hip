@@ -651,6 +651,7 @@ extern "C" nnm_status cluster_cut_allpairs(const float* X_dev, int64_t n, int32_
         return NNM_EINVAL;
     if (n > 1 && !edges_host) return NNM_EINVAL;
     if (std::isnan(prm->dmax) || prm->dmax < 0.0) return NNM_EINVAL;
+    if (opt && opt->metric != NNM_METRIC_EUCLIDEAN) return NNM_EUNSUPPORTED;
     for (int64_t e = 0; e + 1 < n; ++e) {
         const nnm_edge& x = edges_host[e];
         if (x.u < 0 || x.u >= x.v || x.v >= n || !(x.s >= 0.0)) return NNM_EINVAL;

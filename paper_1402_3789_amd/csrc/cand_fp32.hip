@@ -8,17 +8,41 @@
 // which is within a relative (D + 3) 2^-24 (plus an underflow floor) of the
 // exact FP64 key.  One row per thread (features in registers); column
 // chunks are broadcast from LDS.
+//
+// The L1 and L-infinity metrics (nnm_metric) run here too, with the FP32
+// sum or maximum of |x_if - x_jf|: one rounding per difference and per
+// addition, within the same relative bound of their FP64 keys.  The chunk
+// balls are Euclidean; since the L1 distance is at least the Euclidean one
+// and the L-infinity distance at least 1/sqrt(D) of it, a ball whose squared
+// Euclidean gap exceeds U^2 (L1) or D U^2 (L-infinity) holds no candidate.
 #include "cand_common.h"
 
 namespace nnm {
 namespace {
+
+template <int M>
+__device__ __forceinline__ float prune_bound(float U, int d)
+{
+    if constexpr (M == NNM_METRIC_L1) return U * U * (1.0f + 0x1p-20f);
+    else if constexpr (M == NNM_METRIC_LINF) return (float)d * U * U * (1.0f + 0x1p-20f);
+    else return U;
+}
+
+// one feature's contribution to the candidate t
+template <int M>
+__device__ __forceinline__ float acc_term(float t, float diff)
+{
+    if constexpr (M == NNM_METRIC_L1) return t + __builtin_fabsf(diff);
+    else if constexpr (M == NNM_METRIC_LINF) return fmaxf(t, __builtin_fabsf(diff));
+    else return __builtin_fmaf(diff, diff, t);
+}
 
 constexpr int BM = 256;
 constexpr int BN = CHUNK;
 
 // One work item (row tile, column split); share: the row thresholds are
 // shared with the item's other column splits through gT / gU.
-template <int DP, bool TAB>
+template <int DP, bool TAB, int M>
 __device__ __forceinline__ void cand_fp32_item(const CandArgs& a, const Item& it, const bool share)
 {
     constexpr int F4 = DP / 4;
@@ -74,10 +98,10 @@ __device__ __forceinline__ void cand_fp32_item(const CandArgs& a, const Item& it
                 const float4 y = src[f4];
                 const float d0 = xr[4 * f4 + 0] - y.x, d1 = xr[4 * f4 + 1] - y.y;
                 const float d2 = xr[4 * f4 + 2] - y.z, d3 = xr[4 * f4 + 3] - y.w;
-                sq = __builtin_fmaf(d0, d0, sq);
-                sq = __builtin_fmaf(d1, d1, sq);
-                sq = __builtin_fmaf(d2, d2, sq);
-                sq = __builtin_fmaf(d3, d3, sq);
+                sq = acc_term<M>(sq, d0);
+                sq = acc_term<M>(sq, d1);
+                sq = acc_term<M>(sq, d2);
+                sq = acc_term<M>(sq, d3);
             }
             const float ub = __builtin_fmaf(sq, (float)(a.d + 6) * 0x1p-24f, sq) + 0x1p-126f;
             if (ub < tk[k - 1]) {
@@ -109,7 +133,7 @@ __device__ __forceinline__ void cand_fp32_item(const CandArgs& a, const Item& it
     const int lo_r = sh.lo, hi_r = sh.hi;
 
     unsigned long long pairs = 0;
-    wave_max_store(sh, valid ? U : 0.f);
+    wave_max_store(sh, valid ? prune_bound<M>(U, a.d) : 0.f);
     __syncthreads();
     const float umax0 = fmaxf(fmaxf(sh.wmax[0], sh.wmax[1]), fmaxf(sh.wmax[2], sh.wmax[3]));
 
@@ -133,7 +157,7 @@ __device__ __forceinline__ void cand_fp32_item(const CandArgs& a, const Item& it
                 float4 x4[F4];
 #pragma unroll
                 for (int q = 0; q < F4; ++q) x4[q] = make_float4(xr[4 * q], xr[4 * q + 1], xr[4 * q + 2], xr[4 * q + 3]);
-                need = point_ball_lb2(x4, a.balls + (int64_t)ci * BALL_STRIDE) <= U;
+                need = point_ball_lb2(x4, a.balls + (int64_t)ci * BALL_STRIDE) <= prune_bound<M>(U, a.d);
             }
             const unsigned long long b = __ballot(need);
             if ((tid & 63) == 0) sh.wneed[tid >> 6] = b != 0ull;
@@ -150,7 +174,7 @@ __device__ __forceinline__ void cand_fp32_item(const CandArgs& a, const Item& it
         ccomp[tid] = (tid < ncols && c0 + tid >= cl && c0 + tid < ch) ? a.compS[c0 + tid] : -1;
         __syncthreads();
         if (!wrun) {
-            wave_max_store(sh, valid ? U : 0.f);
+            wave_max_store(sh, valid ? prune_bound<M>(U, a.d) : 0.f);
             return;
         }
         pairs += (unsigned long long)ncols;
@@ -163,10 +187,10 @@ __device__ __forceinline__ void cand_fp32_item(const CandArgs& a, const Item& it
                 const float d1 = xr[4 * q + 1] - y.y;
                 const float d2 = xr[4 * q + 2] - y.z;
                 const float d3 = xr[4 * q + 3] - y.w;
-                t = __builtin_fmaf(d0, d0, t);
-                t = __builtin_fmaf(d1, d1, t);
-                t = __builtin_fmaf(d2, d2, t);
-                t = __builtin_fmaf(d3, d3, t);
+                t = acc_term<M>(t, d0);
+                t = acc_term<M>(t, d1);
+                t = acc_term<M>(t, d2);
+                t = acc_term<M>(t, d3);
             }
             if (t <= T && !own) {
                 // same component, or a column this tile must not pair with
@@ -198,7 +222,7 @@ __device__ __forceinline__ void cand_fp32_item(const CandArgs& a, const Item& it
                 }
             }
         }
-        wave_max_store(sh, valid ? U : 0.f);
+        wave_max_store(sh, valid ? prune_bound<M>(U, a.d) : 0.f);
     });
     if (!share && valid) a.surv_cnt[slot] = cnt;
     const int wrows = sh.rows - (tid >> 6) * 64;
@@ -207,25 +231,39 @@ __device__ __forceinline__ void cand_fp32_item(const CandArgs& a, const Item& it
                   pairs * (unsigned long long)(wrows < 64 ? wrows : 64));
 }
 
-template <int DP, bool TAB>
+template <int DP, bool TAB, int M>
 __global__ __launch_bounds__(256, 2) void k_cand_fp32(CandArgs a)
 {
-    cand_fp32_item<DP, TAB>(a, grid_item(a), a.share != 0);
+    cand_fp32_item<DP, TAB, M>(a, grid_item(a), a.share != 0);
 }
 
 // device-sized launch: a fixed grid pops (tile, split) items
-template <int DP>
+template <int DP, int M>
 __global__ __launch_bounds__(256, 2) void k_cand_fp32_q(CandArgs a)
 {
     __shared__ int slot;
     Item it;
-    while (pop_item(a, slot, it)) cand_fp32_item<DP, false>(a, it, it.nsp > 1);
+    while (pop_item(a, slot, it)) cand_fp32_item<DP, false, M>(a, it, it.nsp > 1);
 }
 
 template <int DP>
 void launch_q(const CandArgs& a, size_t shm, hipStream_t s)
 {
-    k_cand_fp32_q<DP><<<QGRID, 256, shm, s>>>(a);
+    switch (a.metric) {
+    case NNM_METRIC_L1: k_cand_fp32_q<DP, NNM_METRIC_L1><<<QGRID, 256, shm, s>>>(a); break;
+    case NNM_METRIC_LINF: k_cand_fp32_q<DP, NNM_METRIC_LINF><<<QGRID, 256, shm, s>>>(a); break;
+    default: k_cand_fp32_q<DP, NNM_METRIC_EUCLIDEAN><<<QGRID, 256, shm, s>>>(a); break;
+    }
+}
+
+template <int DP, bool TAB>
+void launch_m(const CandArgs& a, dim3 grid, size_t shm, hipStream_t s)
+{
+    switch (a.metric) {
+    case NNM_METRIC_L1: k_cand_fp32<DP, TAB, NNM_METRIC_L1><<<grid, 256, shm, s>>>(a); break;
+    case NNM_METRIC_LINF: k_cand_fp32<DP, TAB, NNM_METRIC_LINF><<<grid, 256, shm, s>>>(a); break;
+    default: k_cand_fp32<DP, TAB, NNM_METRIC_EUCLIDEAN><<<grid, 256, shm, s>>>(a); break;
+    }
 }
 
 hipError_t launch_dp_q(const CandArgs& a, int dp, size_t shm, hipStream_t s)
@@ -248,14 +286,14 @@ template <bool TAB>
 hipError_t launch_dp(const CandArgs& a, int dp, dim3 grid, size_t shm, hipStream_t s)
 {
     switch (dp) {
-    case 4: k_cand_fp32<4, TAB><<<grid, 256, shm, s>>>(a); break;
-    case 8: k_cand_fp32<8, TAB><<<grid, 256, shm, s>>>(a); break;
-    case 12: k_cand_fp32<12, TAB><<<grid, 256, shm, s>>>(a); break;
-    case 16: k_cand_fp32<16, TAB><<<grid, 256, shm, s>>>(a); break;
-    case 20: k_cand_fp32<20, TAB><<<grid, 256, shm, s>>>(a); break;
-    case 24: k_cand_fp32<24, TAB><<<grid, 256, shm, s>>>(a); break;
-    case 28: k_cand_fp32<28, TAB><<<grid, 256, shm, s>>>(a); break;
-    case 32: k_cand_fp32<32, TAB><<<grid, 256, shm, s>>>(a); break;
+    case 4: launch_m<4, TAB>(a, grid, shm, s); break;
+    case 8: launch_m<8, TAB>(a, grid, shm, s); break;
+    case 12: launch_m<12, TAB>(a, grid, shm, s); break;
+    case 16: launch_m<16, TAB>(a, grid, shm, s); break;
+    case 20: launch_m<20, TAB>(a, grid, shm, s); break;
+    case 24: launch_m<24, TAB>(a, grid, shm, s); break;
+    case 28: launch_m<28, TAB>(a, grid, shm, s); break;
+    case 32: launch_m<32, TAB>(a, grid, shm, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -72,6 +72,10 @@ struct Plan {
     int ninst = 1;                  // instances in the point set (batched calls)
     bool local = false;             // BF16 operands built per tile from FP32 (not exact data)
     bool keep_e = false;            // workspace holds t + E(t) per survivor (BF16 asked for)
+    int metric = NNM_METRIC_EUCLIDEAN;  // nnm_metric asked for
+    // the metric of the keys the kernels compute: the cosine metric runs as
+    // the Euclidean one on rows scaled to unit length
+    int key_metric() const { return metric == NNM_METRIC_COSINE ? NNM_METRIC_EUCLIDEAN : metric; }
 };
 
 struct WS {
@@ -101,6 +105,7 @@ struct WS {
     int4* tiles; int32_t* tflag; int32_t* tstart;
     float* Xcat; int32_t* inst_off; InstDev* inst; nnm_edge** outp;
     LaunchDesc* desc;
+    float* Xn;                      // cosine metric, one instance: the scaled rows [n][d]
 };
 
 struct Carver {
@@ -202,6 +207,7 @@ size_t carve(const Plan& p, void* base, WS* w)
     w->inst = multi ? c.take<InstDev>((size_t)p.ninst) : nullptr;
     w->outp = multi ? c.take<nnm_edge*>((size_t)p.ninst) : nullptr;
     w->desc = c.take<LaunchDesc>(1);
+    w->Xn = (p.metric == NNM_METRIC_COSINE && !multi) ? c.take<float>(n * (size_t)p.d) : nullptr;
     return c.off + 256;
 }
 
@@ -221,9 +227,15 @@ nnm_status plan_common(int64_t n, int32_t d, int32_t k, const nnm_options* opt, 
     p->n = n;
     p->d = d;
     p->mst = mst;
+    if (o.metric < NNM_METRIC_EUCLIDEAN || o.metric > NNM_METRIC_COSINE) return NNM_EINVAL;
+    p->metric = o.metric;
+    // L1 and L-infinity have no dot-product form: the FP32 vector path only
+    const bool vec_only = o.metric == NNM_METRIC_L1 || o.metric == NNM_METRIC_LINF;
+    if (vec_only && o.precision != NNM_PREC_FP32 && o.precision != NNM_PREC_AUTO)
+        return NNM_EUNSUPPORTED;
     // workspace is sized for the widest operand so the precision can be
     // settled after the data have been inspected
-    p->opkind = (o.precision == NNM_PREC_FP32) ? OP_FP32 : OP_FP16;
+    p->opkind = (o.precision == NNM_PREC_FP32 || vec_only) ? OP_FP32 : OP_FP16;
     if (o.precision == NNM_PREC_AUTO && d > DMAX_MFMA) p->opkind = OP_FP32;
     // cache depth: the global-frame matrix-core paths' survivor band grows
     // with k, so they keep fewer neighbours than the FP32 and the per-tile
@@ -345,7 +357,9 @@ nnm_status stage(Run& R, const float* X)
     HIP_TRY(hipStreamSynchronize(R.s));
     if (st.nonfinite) return NNM_ENONFINITE;
     const bool intgrid = !st.nonint && p.d <= DMAX_MFMA;
-    switch (R.o.precision) {
+    const int prec = (p.metric == NNM_METRIC_L1 || p.metric == NNM_METRIC_LINF) ? NNM_PREC_FP32
+                                                                               : R.o.precision;
+    switch (prec) {
     case NNM_PREC_FP32: p.opkind = OP_FP32; break;
     case NNM_PREC_BF16: p.opkind = OP_BF16; break;
     case NNM_PREC_FP16: p.opkind = OP_FP16; break;
@@ -549,6 +563,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
         a.col_splits = pick_splits(R, (int64_t)nt * 256, u0 != nullptr && R.round > 0);
     }
     a.bc = R.bc;
+    a.metric = p.key_metric();
     a.surv_cnt = w.surv_cnt;
     a.surv_j = w.surv_j;
     a.surv_t = w.surv_t;
@@ -638,6 +653,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     r.pcs = w.pcs;
     r.bc = R.bc;
     r.surv_e = w.surv_e;
+    r.metric = p.key_metric();
     int32_t over = 0;
     {
         Timer t(R.timers, R.s, R.rep ? &R.rep->ms_rescore : nullptr);
@@ -767,6 +783,7 @@ nnm_status scan_batch_dev(Run& R, const float* X, const int32_t* rows, const int
         a.tiles = w.tiles;
     }
     a.bc = R.bc;
+    a.metric = p.key_metric();
     a.surv_cnt = w.surv_cnt;
     a.surv_j = w.surv_j;
     a.surv_t = w.surv_t;
@@ -826,6 +843,7 @@ nnm_status scan_batch_dev(Run& R, const float* X, const int32_t* rows, const int
     r.pcs = w.pcs;
     r.bc = R.bc;
     r.surv_e = w.surv_e;
+    r.metric = p.key_metric();
     r.desc = D;
     HIP_TRY(launch_rescore(r, w.overflow_list, R.s));
     if (level == 2 || R.o.force_fallback)
@@ -1101,6 +1119,11 @@ extern "C" nnm_status knn_build(const float* X_dev, int64_t n, int32_t d, int64_
     Run R;
     nnm_status st = begin(R, X_dev, n, d, ld, k, opt, ws_dev, ws_bytes, stream, rep, false);
     if (st != NNM_OK) return st;
+    if (R.p.metric == NNM_METRIC_COSINE) {
+        HIP_TRY(launch_normalize_rows(X_dev, n, d, ld, R.w.Xn, R.s));
+        X_dev = R.w.Xn;
+        R.p.ld = d;
+    }
     st = stage(R, X_dev);
     if (st != NNM_OK) return st;
     if (n > 1) {
@@ -1299,6 +1322,11 @@ nnm_status mst_build_in(const float* X_dev, int64_t n, int32_t d, int64_t ld, co
     if (st != NNM_OK) return st;
     R.timers = R.timers && timers;
     R.max_inst = n;
+    if (R.p.metric == NNM_METRIC_COSINE) {
+        HIP_TRY(launch_normalize_rows(X_dev, n, d, ld, R.w.Xn, R.s));
+        X_dev = R.w.Xn;
+        R.p.ld = d;
+    }
     st = stage(R, X_dev);
     if (st != NNM_OK) return st;
     if (n == 1) return finish_report(R, t0);
@@ -1311,7 +1339,7 @@ nnm_status mst_build_in(const float* X_dev, int64_t n, int32_t d, int64_t ld, co
         SortRec* res = nullptr;
         st = sort_edges(R, &res);
         if (st != NNM_OK) return st;
-        HIP_TRY(launch_write_edges(res, n - 1, edges_dev, R.s));
+        HIP_TRY(launch_write_edges(res, n - 1, edges_dev, R.p.key_metric(), R.s));
         HIP_TRY(hipStreamSynchronize(R.s));
     }
     return finish_report(R, t0);
@@ -1460,6 +1488,9 @@ extern "C" nnm_status mst_build_batched(const nnm_instance* inst, int32_t count,
     HIP_TRY(hipMemcpyAsync(R.w.inst, hin.data(), sizeof(InstDev) * hin.size(), hipMemcpyHostToDevice, R.s));
     HIP_TRY(hipMemcpyAsync(R.w.outp, outp.data(), sizeof(nnm_edge*) * outp.size(), hipMemcpyHostToDevice, R.s));
     HIP_TRY(launch_concat(R.w.inst, R.w.inst_off, count, tot, dm, R.w.Xcat, R.s));
+    // the zero padding leaves every row's norm as it is
+    if (R.p.metric == NNM_METRIC_COSINE)
+        HIP_TRY(launch_normalize_rows(R.w.Xcat, tot, dm, dm, R.w.Xcat, R.s));
     const float* X = R.w.Xcat;
     st = stage(R, X);
     if (st != NNM_OK) return st;
@@ -1472,7 +1503,7 @@ extern "C" nnm_status mst_build_batched(const nnm_instance* inst, int32_t count,
         if (st != NNM_OK) return st;
         SortRec* other = (res == R.w.srtA) ? R.w.edges : R.w.srtA;
         HIP_TRY(launch_write_edges_batched(res, tot - count, R.w.inst_off, count, other, R.w.srtB,
-                                           R.w.radix_temp, R.w.outp, R.s));
+                                           R.w.radix_temp, R.w.outp, R.p.key_metric(), R.s));
     }
     HIP_TRY(hipStreamSynchronize(R.s));
     st = finish_report(R, t0);

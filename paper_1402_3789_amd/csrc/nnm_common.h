@@ -132,6 +132,56 @@ __device__ __forceinline__ double sqdist_fp64_rows(const float* a, const float* 
     return s;
 }
 
+// Keys of the L1 and L-infinity metrics (nnm_metric) for two rows of the
+// padded sorted copy: exact |differences| in FP64, summed left to right, or
+// their maximum.  metric_key_rows(m, ...) picks the metric's key (the
+// cosine metric runs as Euclidean on scaled rows).
+__device__ __forceinline__ double metric_key_rows(int metric, const float* a, const float* b, int d)
+{
+    if (metric == NNM_METRIC_L1 || metric == NNM_METRIC_LINF) {
+        const float4* a4 = reinterpret_cast<const float4*>(a);
+        const float4* b4 = reinterpret_cast<const float4*>(b);
+        double s = 0.0;
+        for (int q = 0; q * 4 < d; ++q) {
+            const float4 u = a4[q], v = b4[q];
+            const float au[4] = {u.x, u.y, u.z, u.w};
+            const float bv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int f = 4 * q + h;
+                if (f < d) {
+                    const double t = __builtin_fabs(__dsub_rn((double)au[h], (double)bv[h]));
+                    if (metric == NNM_METRIC_L1) s = (f == 0) ? t : __dadd_rn(s, t);
+                    else s = t > s ? t : s;
+                }
+            }
+        }
+        return s;
+    }
+    return sqdist_fp64_rows(a, b, d);
+}
+
+// The same for two rows of an FP32 input (row-major, any stride).
+__device__ __forceinline__ double metric_key(int metric, const float* a, const float* b, int d)
+{
+    if (metric == NNM_METRIC_L1 || metric == NNM_METRIC_LINF) {
+        double s = 0.0;
+        for (int f = 0; f < d; ++f) {
+            const double t = __builtin_fabs(__dsub_rn((double)a[f], (double)b[f]));
+            if (metric == NNM_METRIC_L1) s = (f == 0) ? t : __dadd_rn(s, t);
+            else s = t > s ? t : s;
+        }
+        return s;
+    }
+    return sqdist_fp64(a, b, d);
+}
+
+// The reported distance of a key.
+__host__ __device__ __forceinline__ bool metric_key_is_distance(int metric)
+{
+    return metric == NNM_METRIC_L1 || metric == NNM_METRIC_LINF;
+}
+
 // (s, j) order for one row: smaller s, then smaller j.
 __device__ __forceinline__ bool sj_less(double s1, int j1, double s2, int j2)
 {
@@ -236,6 +286,7 @@ struct CandArgs {
     uint32_t* gU;             // [n_rows] bound on the key of the k-th neighbour
     // device-sized launch (NULL: n_rows, n_tiles and col_splits above)
     LaunchDesc* desc;
+    int32_t metric;           // nnm_metric (the FP32 path; the matrix cores: Euclidean)
 };
 
 hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s);
@@ -287,6 +338,7 @@ struct RescoreArgs {
     BoundConst bc;            // BOUND_GLOBAL: column maxima
     const float* surv_e;      // BOUND_LOCAL: [n_rows][S] t + E(t)
     const LaunchDesc* desc;   // device-sized launch (NULL: n_rows above)
+    int32_t metric;           // nnm_metric of the keys (cosine: Euclidean on scaled rows)
 };
 
 hipError_t launch_rescore(const RescoreArgs& a, int32_t* overflow_list, hipStream_t s);
@@ -383,7 +435,8 @@ hipError_t launch_comp_records(const int32_t* comp, int64_t n, SortRec* rec,
                                hipStream_t s);
 hipError_t launch_perm_from_records(const SortRec* rec, int64_t n,
                                     int32_t* perm, hipStream_t s);
-hipError_t launch_write_edges(const SortRec* rec, int64_t ne, nnm_edge* out,
+// w = sqrt(s), or w = s for a metric whose key is the distance
+hipError_t launch_write_edges(const SortRec* rec, int64_t ne, nnm_edge* out, int metric,
                               hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 
@@ -449,7 +502,10 @@ hipError_t launch_tile_desc_dev(const int32_t* tstart, int max_tiles, const int3
                                 const LaunchDesc* d, hipStream_t s);
 hipError_t launch_write_edges_batched(const SortRec* sorted, int64_t ne, const int32_t* off, int ninst,
                                       SortRec* recA, SortRec* recB, void* radix_temp,
-                                      nnm_edge* const* out, hipStream_t s);
+                                      nnm_edge* const* out, int metric, hipStream_t s);
+// rows scaled to unit Euclidean length (the cosine metric), out [n][d]
+hipError_t launch_normalize_rows(const float* X, int64_t n, int d, int64_t ld, float* out,
+                                 hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v,
                            int64_t n, hipStream_t s);
 

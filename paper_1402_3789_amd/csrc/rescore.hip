@@ -71,7 +71,7 @@ __device__ __forceinline__ void rescore_row(const RescoreArgs& a, int64_t slot, 
         if (idx < m && !(tv > tf)) {
             const int jp = a.surv_j[slot * a.S + idx];
             const int j = a.perm[jp];
-            const double s = sqdist_fp64_rows(xi, a.xs + (int64_t)jp * DMAX, a.d);
+            const double s = metric_key_rows(a.metric, xi, a.xs + (int64_t)jp * DMAX, a.d);
             const double t = (double)tv * a.inv_sigma2;
             const double err = __builtin_fabs(t - s);
             emax = err > emax ? err : emax;
@@ -216,7 +216,7 @@ __device__ __forceinline__ void fallback_row(const RescoreArgs& a, int64_t slot)
     }
     for (int64_t j = jlo + tid; j < jhi; j += 256) {
         if (j == i || a.comp[j] == ci) continue;
-        const double s = sqdist_fp64(xi, a.X + j * a.ld, a.d);
+        const double s = metric_key(a.metric, xi, a.X + j * a.ld, a.d);
         if (!sj_less(s, (int)j, ls[k - 1], lj[k - 1])) continue;
         int p = k - 1;
         while (p > 0 && sj_less(s, (int)j, ls[p - 1], lj[p - 1])) {

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_perm_from_records(const SortRec* __rest
 }
 
 __global__ __launch_bounds__(256) void k_write_edges(const SortRec* __restrict__ rec, int64_t ne,
-                                                     nnm_edge* __restrict__ out)
+                                                     nnm_edge* __restrict__ out, int metric)
 {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= ne) return;
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_write_edges(const SortRec* __restrict__
     o.u = (int32_t)r.k1;
     o.v = (int32_t)r.k2;
     o.s = __longlong_as_double((long long)r.k0);
-    o.w = __dsqrt_rn(o.s);
+    o.w = metric_key_is_distance(metric) ? o.s : __dsqrt_rn(o.s);
     out[e] = o;
 }
 
@@ -375,10 +375,11 @@ hipError_t launch_perm_from_records(const SortRec* rec, int64_t n, int32_t* perm
     return hipGetLastError();
 }
 
-hipError_t launch_write_edges(const SortRec* rec, int64_t ne, nnm_edge* out, hipStream_t s)
+hipError_t launch_write_edges(const SortRec* rec, int64_t ne, nnm_edge* out, int metric,
+                              hipStream_t s)
 {
     if (ne <= 0) return hipSuccess;
-    k_write_edges<<<g256(ne), 256, 0, s>>>(rec, ne, out);
+    k_write_edges<<<g256(ne), 256, 0, s>>>(rec, ne, out, metric);
     return hipGetLastError();
 }
 

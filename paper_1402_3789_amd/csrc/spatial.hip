@@ -652,7 +652,8 @@ __global__ __launch_bounds__(256) void k_edge_inst_records(const SortRec* __rest
 __global__ __launch_bounds__(256) void k_write_edges_inst(const SortRec* __restrict__ sorted,
                                                           const SortRec* __restrict__ order, int64_t ne,
                                                           const int32_t* __restrict__ off,
-                                                          nnm_edge* const* __restrict__ out)
+                                                          nnm_edge* const* __restrict__ out,
+                                                          int metric)
 {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= ne) return;
@@ -663,8 +664,28 @@ __global__ __launch_bounds__(256) void k_write_edges_inst(const SortRec* __restr
     o.u = (int32_t)(r.k1 - (uint32_t)off[b]);
     o.v = (int32_t)(r.k2 - (uint32_t)off[b]);
     o.s = __longlong_as_double((long long)r.k0);
-    o.w = __dsqrt_rn(o.s);
+    o.w = metric_key_is_distance(metric) ? o.s : __dsqrt_rn(o.s);
     out[b][local] = o;
+}
+
+// The cosine metric's rows: scaled to unit Euclidean length (FP64 norm from
+// the sum of squares in feature order, one division and one rounding per
+// feature; a zero row stays zero).  One thread per row.
+__global__ __launch_bounds__(256) void k_normalize_rows(const float* __restrict__ X, int64_t n, int d,
+                                                        int64_t ld, float* __restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* x = X + i * ld;
+    double q = 0.0;
+    for (int f = 0; f < d; ++f) {
+        const double v = (double)x[f];
+        const double sq = __dmul_rn(v, v);
+        q = (f == 0) ? sq : __dadd_rn(q, sq);
+    }
+    const double nrm = __dsqrt_rn(q);
+    for (int f = 0; f < d; ++f)
+        out[i * d + f] = nrm > 0.0 ? (float)__ddiv_rn((double)x[f], nrm) : 0.0f;
 }
 
 }  // namespace
@@ -731,7 +752,7 @@ hipError_t launch_tile_desc(const int32_t* tstart, int ntiles, const int32_t* ro
 
 hipError_t launch_write_edges_batched(const SortRec* sorted, int64_t ne, const int32_t* off, int ninst,
                                       SortRec* recA, SortRec* recB, void* radix_temp,
-                                      nnm_edge* const* out, hipStream_t s)
+                                      nnm_edge* const* out, int metric, hipStream_t s)
 {
     if (ne <= 0) return hipSuccess;
     k_edge_inst_records<<<g256(ne), 256, 0, s>>>(sorted, ne, off, ninst, recA);
@@ -742,7 +763,14 @@ hipError_t launch_write_edges_batched(const SortRec* sorted, int64_t ne, const i
     SortRec* res = nullptr;
     hipError_t e = launch_radix_sort(recA, recB, ne, f1, b1, 1, radix_temp, &res, s);
     if (e != hipSuccess) return e;
-    k_write_edges_inst<<<g256(ne), 256, 0, s>>>(sorted, res, ne, off, out);
+    k_write_edges_inst<<<g256(ne), 256, 0, s>>>(sorted, res, ne, off, out, metric);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize_rows(const float* X, int64_t n, int d, int64_t ld, float* out,
+                                 hipStream_t s)
+{
+    k_normalize_rows<<<g256(n), 256, 0, s>>>(X, n, d, ld, out);
     return hipGetLastError();
 }
 

@@ -314,3 +314,21 @@ def test_allpairs_cut_rejects_bad_arguments_before_device_work():
     assert call(wsb=nb.value - 1) == N.NNM_EINVAL
     assert call(prm=N.CutParams(0, 5, -1, 0, float("nan"))) == N.NNM_EINVAL
     assert call(prm=N.CutParams(0, 5, -1, 0, -1.0)) == N.NNM_EINVAL
+
+
+def test_metric_option_checks():
+    L = N.lib()
+    nb = ctypes.c_size_t(0)
+    for name, prec, want in (("l1", "bf16", N.NNM_EUNSUPPORTED), ("linf", "fp16", N.NNM_EUNSUPPORTED),
+                             ("linf", "fp8", N.NNM_EUNSUPPORTED), ("l1", "auto", N.NNM_OK),
+                             ("linf", "fp32", N.NNM_OK), ("cosine", "bf16", N.NNM_OK)):
+        o = nnm.options(prec, metric=name)
+        assert L.mst_workspace_size(1000, 8, ctypes.byref(o), ctypes.byref(nb)) == want, (name, prec)
+    o = nnm.options("fp32")
+    o.metric = 7
+    assert L.mst_workspace_size(1000, 8, ctypes.byref(o), ctypes.byref(nb)) == N.NNM_EINVAL
+    # the cosine metric keeps its scaled rows in the workspace
+    a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    L.mst_workspace_size(1000, 8, ctypes.byref(nnm.options("fp16")), ctypes.byref(a))
+    L.mst_workspace_size(1000, 8, ctypes.byref(nnm.options("fp16", metric="cosine")), ctypes.byref(b))
+    assert b.value >= a.value + 1000 * 8 * 4
