@@ -273,6 +273,30 @@ nnm_status mst_build_noalloc(const float *X_dev, int64_t n, int32_t d,
                              nnm_edge *edges_dev, void *stream,
                              nnm_report *rep);
 
+/*
+ * The same tree by the paper's own pipeline (section "General description
+ * of the algorithm for constructing the set of minimum distances"): each
+ * pass selects the P smallest pairs of points not inside one cluster,
+ * sorts them by key and unites clusters along them in that order (pairs
+ * that are inside a cluster by then are skipped), until one cluster is
+ * left.  A pass costs a scan of every row; mst_build reaches the same tree
+ * with far less work, and this entry point exists to measure the paper's
+ * scheme on the same kernels.
+ *   P          pairs per pass (0: n / 2);
+ *   ws_dev     at least pminimal_workspace_size() bytes;
+ *   rep        as for mst_build; rounds = passes, comps_per_round = clusters
+ *              at the start of each pass, rows_per_round = pairs taken in
+ *              the pass, surv_per_round = unions it made.
+ * Other arguments and errors as for mst_build.
+ */
+nnm_status pminimal_workspace_size(int64_t n, int32_t d, const nnm_options *opt,
+                                   size_t *bytes);
+nnm_status mst_build_pminimal(const float *X_dev, int64_t n, int32_t d,
+                              int64_t ld, int64_t P, const nnm_options *opt,
+                              void *ws_dev, size_t ws_bytes,
+                              nnm_edge *edges_dev, void *stream,
+                              nnm_report *rep);
+
 /* One instance of a batched call. */
 typedef struct {
     const float *X_dev;     /* [n][ld] FP32 device                             */

@@ -19,7 +19,8 @@ import numpy as np
 from . import _native as N
 from ._native import NNMError, NativeMissing, PREC  # noqa: F401
 
-__all__ = ["mst_build", "mst_build_noalloc", "knn_build", "cluster_cut", "cluster_cut_allpairs",
+__all__ = ["mst_build", "mst_build_noalloc", "mst_build_pminimal", "knn_build", "cluster_cut",
+           "cluster_cut_allpairs",
            "mst_build_batched", "Tree",
            "options", "autotune", "NNMError", "NativeMissing"]
 
@@ -161,6 +162,27 @@ def mst_build(X, precision="auto", knn_k=0, survivor_cap=0, disable_prune=False,
                        ctypes.c_void_p(ws.data_ptr()), nb.value,
                        ctypes.c_void_p(edges.data_ptr()), _stream(stream), ctypes.byref(rep))
     N.check("mst_build", code)
+    return Tree(edges[: n - 1], n, rep.as_dict())
+
+
+def mst_build_pminimal(X, P=0, precision="auto", knn_k=0, metric="euclidean", stream=None,
+                       workspace=None) -> Tree:
+    """The same tree by the paper's pipeline of P minimal pairs per pass."""
+    torch = _torch()
+    n, d, ld = _check_x(X)
+    L = N.lib()
+    o = options(precision, knn_k, metric=metric)
+    nb = ctypes.c_size_t(0)
+    N.check("pminimal_workspace_size",
+            L.pminimal_workspace_size(n, d, ctypes.byref(o), ctypes.byref(nb)))
+    ws = (workspace or _WS).get(nb.value, X.device)
+    edges = torch.empty((max(n - 1, 1), 3), dtype=torch.float64, device=X.device)
+    rep = N.Report()
+    code = L.mst_build_pminimal(ctypes.c_void_p(X.data_ptr()), n, d, ld, int(P), ctypes.byref(o),
+                                ctypes.c_void_p(ws.data_ptr()), nb.value,
+                                ctypes.c_void_p(edges.data_ptr()), _stream(stream),
+                                ctypes.byref(rep))
+    N.check("mst_build_pminimal", code)
     return Tree(edges[: n - 1], n, rep.as_dict())
 
 

@@ -101,6 +101,13 @@ _SIG = {
     "mst_build_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                          ctypes.c_int64, ctypes.POINTER(Options), ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.POINTER(Report)]),
+    "pminimal_workspace_size": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32,
+                                               ctypes.POINTER(Options),
+                                               ctypes.POINTER(ctypes.c_size_t)]),
+    "mst_build_pminimal": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(Options),
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.POINTER(Report)]),
     "mst_batched_workspace_size": (ctypes.c_int, [ctypes.POINTER(Instance), ctypes.c_int32,
                                                   ctypes.POINTER(Options),
                                                   ctypes.POINTER(ctypes.c_size_t)]),

@@ -1345,6 +1345,58 @@ nnm_status mst_build_in(const float* X_dev, int64_t n, int32_t d, int64_t ld, co
     return finish_report(R, t0);
 }
 
+// ---- the paper's P-minimal-pairs pipeline --------------------------------
+//
+// The section "General description of the algorithm for constructing the
+// set of minimum distances": each pass selects the P smallest pairs of
+// points that are not inside one cluster, sorts them by key and unites
+// clusters along them in that order (pairs that fall inside a cluster by
+// then are skipped), until one cluster is left.  Here a pass is: every
+// row's k smallest pairs to points outside its cluster (the same candidate
+// and rescoring kernels as the merge rounds), the threshold below which
+// those lists hold every such pair, the pairs under it sorted by key, and
+// the first P of them taken on the host.  The unions are the key-ordered
+// minimum spanning tree, the same as mst_build's.
+
+struct PmWS {
+    SortRec* candA;
+    SortRec* candB;
+    void* rtemp;
+    unsigned long long* thr;
+    int32_t* count;
+};
+
+size_t pm_carve(size_t base_bytes, int64_t cap, char* base, PmWS* w)
+{
+    size_t off = (base_bytes + 255) & ~(size_t)255;
+    auto take = [&](size_t bytes) -> void* {
+        off = (off + 255) & ~(size_t)255;
+        void* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    w->candA = (SortRec*)take((size_t)cap * sizeof(SortRec));
+    w->candB = (SortRec*)take((size_t)cap * sizeof(SortRec));
+    w->rtemp = take(radix_temp_bytes(cap));
+    w->thr = (unsigned long long*)take(2 * sizeof(unsigned long long));
+    w->count = (int32_t*)take(sizeof(int32_t));
+    return off + 256;
+}
+
+nnm_status pm_sizes(int64_t n, int32_t d, const nnm_options* opt, size_t* base, int64_t* cap,
+                    size_t* total)
+{
+    nnm_status st = mst_workspace_size(n, d, opt, base);
+    if (st != NNM_OK) return st;
+    Plan p;
+    st = plan_common(n, d, 0, opt, true, &p);
+    if (st != NNM_OK) return st;
+    *cap = std::max<int64_t>(n * p.k, 1);
+    PmWS w;
+    *total = pm_carve(*base, *cap, nullptr, &w);
+    return NNM_OK;
+}
+
 // Fixed scratch of mst_build_noalloc: a file-scope device array, so the
 // entry point needs no allocation.  Every GPU the library runs on holds its
 // own copy from the time the library's code is loaded there until the
@@ -1402,6 +1454,133 @@ extern "C" nnm_status mst_build_noalloc(const float* X_dev, int64_t n, int32_t d
     if (opt) o = *opt;
     o.graph = 0;
     return mst_build_in(X_dev, n, d, ld, &o, ws, NOALLOC_SCRATCH_BYTES, edges_dev, stream, rep, false);
+}
+
+extern "C" nnm_status pminimal_workspace_size(int64_t n, int32_t d, const nnm_options* opt,
+                                              size_t* bytes)
+{
+    if (!bytes) return NNM_EINVAL;
+    size_t base = 0;
+    int64_t cap = 0;
+    return pm_sizes(n, d, opt, &base, &cap, bytes);
+}
+
+extern "C" nnm_status mst_build_pminimal(const float* X_dev, int64_t n, int32_t d, int64_t ld,
+                                         int64_t P, const nnm_options* opt, void* ws_dev,
+                                         size_t ws_bytes, nnm_edge* edges_dev, void* stream,
+                                         nnm_report* rep)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (P < 0 || (n > 1 && !edges_dev)) return NNM_EINVAL;
+    if (!X_dev || !ws_dev || n < 1 || d < 1 || d > DMAX || ld < d) return NNM_EINVAL;
+    size_t base = 0, total = 0;
+    int64_t cap = 0;
+    nnm_status st = pm_sizes(n, d, opt, &base, &cap, &total);
+    if (st != NNM_OK) return st;
+    if (ws_bytes < total) return NNM_EINVAL;
+    Run R;
+    st = begin(R, X_dev, n, d, ld, 0, opt, ws_dev, base, stream, rep, true);
+    if (st != NNM_OK) return st;
+    PmWS pw;
+    pm_carve(base, cap, (char*)ws_dev, &pw);
+    R.max_inst = n;
+    if (R.p.metric == NNM_METRIC_COSINE) {
+        HIP_TRY(launch_normalize_rows(X_dev, n, d, ld, R.w.Xn, R.s));
+        X_dev = R.w.Xn;
+        R.p.ld = d;
+    }
+    st = stage(R, X_dev);
+    if (st != NNM_OK) return st;
+    if (n == 1) return finish_report(R, t0);
+    const int32_t off[2] = {0, (int32_t)n};
+    HIP_TRY(hipMemcpyAsync(R.w.inst_off, off, sizeof(off), hipMemcpyHostToDevice, R.s));
+    MergeArgs m = merge_args(R);
+    HIP_TRY(launch_init_points(m, R.s));
+    st = spatial_order(R, X_dev);
+    if (st != NNM_OK) return st;
+    const int64_t take = P > 0 ? P : std::max<int64_t>(n / 2, 1);
+    std::vector<int32_t> par((size_t)n), comp((size_t)n);
+    std::vector<int64_t> sz((size_t)n, 1);
+    for (int64_t i = 0; i < n; ++i) par[(size_t)i] = (int32_t)i;
+    auto find = [&](int32_t x) {
+        while (par[(size_t)x] != x) {
+            par[(size_t)x] = par[(size_t)par[(size_t)x]];
+            x = par[(size_t)x];
+        }
+        return x;
+    };
+    std::vector<nnm_edge> edges;
+    edges.reserve((size_t)n - 1);
+    std::vector<SortRec> host;
+    const int lg = std::max(ceil_log2(n), 1);
+    const int fields[3] = {2, 1, 0};
+    const int bits[3] = {lg, lg, 64};
+    const int km = R.p.key_metric();
+    int64_t ncomp = n;
+    int pass = 0;
+    while (ncomp > 1) {
+        if (pass >= 1 << 20) return NNM_EDEVICE;        // cannot happen: every pass unites
+        R.round = pass;
+        if (rep && pass < 32) rep->comps_per_round[pass] = ncomp;
+        R.aligned = pass > 0 && ncomp * ALIGN_AVG <= n && !R.o.fixed_chunks;
+        st = sort_points(R, X_dev, ncomp);
+        if (st != NNM_OK) return st;
+        // every row: its k smallest pairs leaving its cluster
+        st = scan_rows(R, X_dev, nullptr, n, false);
+        if (st != NNM_OK) return st;
+        HIP_TRY(launch_fill_u64(pw.thr, ~0ull, 2, R.s));
+        HIP_TRY(launch_fill_i32(pw.count, 0, 1, R.s));
+        HIP_TRY(launch_pm_candidates(m, pw.thr, pw.candA, pw.count, cap, R.s));
+        int32_t cnt = 0;
+        HIP_TRY(hipMemcpyAsync(&cnt, pw.count, sizeof(cnt), hipMemcpyDeviceToHost, R.s));
+        HIP_TRY(hipStreamSynchronize(R.s));
+        const int64_t C = std::min<int64_t>(cnt, cap);
+        if (C <= 0) return NNM_EDEVICE;                 // cannot happen: the smallest pair is below
+        SortRec* res = nullptr;
+        HIP_TRY(launch_radix_sort(pw.candA, pw.candB, C, fields, bits, 3, pw.rtemp, &res, R.s));
+        // each pair is listed at most twice: 2P records hold the first P pairs
+        const int64_t need = std::min<int64_t>(C, 2 * take);
+        host.resize((size_t)need);
+        HIP_TRY(hipMemcpyAsync(host.data(), res, sizeof(SortRec) * (size_t)need, hipMemcpyDeviceToHost,
+                               R.s));
+        HIP_TRY(hipStreamSynchronize(R.s));
+        int64_t taken = 0, united = 0;
+        for (int64_t q = 0; q < need && taken < take; ++q) {
+            const SortRec& r = host[(size_t)q];
+            if (q > 0 && r.k0 == host[(size_t)q - 1].k0 && r.k1 == host[(size_t)q - 1].k1 &&
+                r.k2 == host[(size_t)q - 1].k2)
+                continue;
+            ++taken;
+            int32_t a = find((int32_t)r.k1), b = find((int32_t)r.k2);
+            if (a == b) continue;                        // inside one cluster by now
+            if (sz[(size_t)a] < sz[(size_t)b]) std::swap(a, b);
+            par[(size_t)b] = a;
+            sz[(size_t)a] += sz[(size_t)b];
+            nnm_edge e;
+            e.u = (int32_t)r.k1;
+            e.v = (int32_t)r.k2;
+            memcpy(&e.s, &r.k0, 8);
+            e.w = metric_key_is_distance(km) ? e.s : sqrt(e.s);
+            edges.push_back(e);
+            ++united;
+            --ncomp;
+        }
+        if (united == 0) return NNM_EDEVICE;             // cannot happen: the smallest pair unites
+        if (rep && pass < 32) {
+            rep->rows_per_round[pass] = taken;
+            rep->surv_per_round[pass] = united;
+        }
+        for (int64_t i = 0; i < n; ++i) comp[(size_t)i] = find((int32_t)i);
+        HIP_TRY(hipMemcpyAsync(R.w.comp, comp.data(), sizeof(int32_t) * (size_t)n,
+                               hipMemcpyHostToDevice, R.s));
+        ++pass;
+    }
+    if ((int64_t)edges.size() != n - 1) return NNM_EDEVICE;
+    HIP_TRY(hipMemcpyAsync(edges_dev, edges.data(), sizeof(nnm_edge) * edges.size(),
+                           hipMemcpyHostToDevice, R.s));
+    HIP_TRY(hipStreamSynchronize(R.s));
+    if (rep) rep->rounds = pass;
+    return finish_report(R, t0);
 }
 
 namespace {

@@ -148,6 +148,63 @@ __global__ __launch_bounds__(256) void k_copy_i32_dev(int32_t* __restrict__ dst,
     if (i < *count) dst[i] = src[i];
 }
 
+// ---- the P-minimal-pairs pass (mst_build_pminimal) ------------------------
+
+__device__ __forceinline__ unsigned long long pack_pair(int i, int j)
+{
+    const unsigned long long lo = (unsigned long long)(i < j ? i : j);
+    const unsigned long long hi = (unsigned long long)(i < j ? j : i);
+    return (lo << 32) | hi;
+}
+
+// The pass threshold: the smallest pair key over the last entries of the
+// lists that do not hold every outside point (any pair below it is in
+// some row's list).  Two steps: the key bits, then (lo, hi) among rows that
+// reach them.  thr[0] = s bits, thr[1] = packed (lo, hi).
+__global__ __launch_bounds__(256) void k_pm_thr_s(MergeArgs a, unsigned long long* thr)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int len = a.clen[i];
+    if ((a.cflag[i] & 1) || len <= 0) return;
+    atomicMin(&thr[0], sbits(a.cs[i * a.k + len - 1]));
+}
+
+__global__ __launch_bounds__(256) void k_pm_thr_p(MergeArgs a, unsigned long long* thr)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int len = a.clen[i];
+    if ((a.cflag[i] & 1) || len <= 0) return;
+    if (sbits(a.cs[i * a.k + len - 1]) != thr[0]) return;
+    atomicMin(&thr[1], pack_pair((int)i, a.cidx[i * a.k + len - 1]));
+}
+
+// Every listed pair below the threshold, once from each of its rows
+// (duplicates sit side by side after the key sort).
+__global__ __launch_bounds__(256) void k_pm_emit(MergeArgs a, const unsigned long long* thr,
+                                                 SortRec* out, int32_t* count, int64_t cap)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int len = a.clen[i];
+    const unsigned long long ts = thr[0], tp = thr[1];
+    for (int e = 0; e < len; ++e) {
+        const unsigned long long sb = sbits(a.cs[i * a.k + e]);
+        const int j = a.cidx[i * a.k + e];
+        const unsigned long long pp = pack_pair((int)i, j);
+        if (sb > ts || (sb == ts && pp >= tp)) break;        // lists are ascending
+        const int pos = atomicAdd(count, 1);
+        if (pos < cap) {
+            SortRec r;
+            r.k0 = sb;
+            r.k1 = (uint32_t)(pp >> 32);
+            r.k2 = (uint32_t)(pp & 0xFFFFFFFFu);
+            out[pos] = r;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_seg_starts(const int32_t* seg, int64_t n, int32_t* segstart)
 {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -320,6 +377,15 @@ hipError_t launch_pick_reps_dev(const MergeArgs& a, const int32_t* seg, int32_t*
 {
     k_seg_starts<<<g256(a.n), 256, 0, s>>>(seg, a.n, segstart);
     k_rep_flags<<<g256(a.n), 256, 0, s>>>(a, seg, segstart, 0, flag2, nseg);
+    return hipGetLastError();
+}
+
+hipError_t launch_pm_candidates(const MergeArgs& a, unsigned long long* thr, SortRec* out,
+                                int32_t* count, int64_t cap, hipStream_t s)
+{
+    k_pm_thr_s<<<g256(a.n), 256, 0, s>>>(a, thr);
+    k_pm_thr_p<<<g256(a.n), 256, 0, s>>>(a, thr);
+    k_pm_emit<<<g256(a.n), 256, 0, s>>>(a, thr, out, count, cap);
     return hipGetLastError();
 }
 

@@ -403,6 +403,12 @@ hipError_t launch_pick_reps(const MergeArgs& a, const int32_t* seg, int32_t* seg
 // the same with the segment count on the device
 hipError_t launch_pick_reps_dev(const MergeArgs& a, const int32_t* seg, int32_t* segstart,
                                 const int32_t* nseg, int32_t* flag2, hipStream_t s);
+// P-minimal-pairs pass: thr[0..1] (set to all ones before) receives the pass
+// threshold over the rows' lists; out[0 .. *count) the listed pairs below
+// it as (s bits, lo, hi), each once from each of its rows (at most cap kept;
+// *count may exceed cap).
+hipError_t launch_pm_candidates(const MergeArgs& a, unsigned long long* thr, SortRec* out,
+                                int32_t* count, int64_t cap, hipStream_t s);
 // *eff = *nrep when 0 < *nrep < *rcount, else 0 (the representatives are
 // scanned first only when they are fewer than the rows to scan)
 hipError_t launch_rep_select(const int32_t* nrep, const int32_t* rcount, int32_t* eff, hipStream_t s);

@@ -332,3 +332,22 @@ def test_metric_option_checks():
     L.mst_workspace_size(1000, 8, ctypes.byref(nnm.options("fp16")), ctypes.byref(a))
     L.mst_workspace_size(1000, 8, ctypes.byref(nnm.options("fp16", metric="cosine")), ctypes.byref(b))
     assert b.value >= a.value + 1000 * 8 * 4
+
+
+def test_pminimal_rejects_bad_arguments_before_device_work():
+    L = N.lib()
+    o = nnm.options("fp16")
+    nb = ctypes.c_size_t(0)
+    assert L.pminimal_workspace_size(5000, 10, ctypes.byref(o), ctypes.byref(nb)) == N.NNM_OK
+    mb = ctypes.c_size_t(0)
+    assert L.mst_workspace_size(5000, 10, ctypes.byref(o), ctypes.byref(mb)) == N.NNM_OK
+    assert nb.value > mb.value
+    rep = N.Report()
+    bad = [dict(P=-1), dict(X=0), dict(ws=0), dict(wsb=nb.value - 1), dict(e=0), dict(d=40)]
+    for b in bad:
+        a = dict(X=1234, P=10, ws=1, wsb=nb.value, e=5678, d=10)
+        a.update(b)
+        code = L.mst_build_pminimal(ctypes.c_void_p(a["X"]), 5000, a["d"], max(a["d"], 10), a["P"],
+                                    ctypes.byref(o), ctypes.c_void_p(a["ws"]), a["wsb"],
+                                    ctypes.c_void_p(a["e"]), None, ctypes.byref(rep))
+        assert code == N.NNM_EINVAL, b
