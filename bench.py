@@ -154,6 +154,8 @@ def main():
                     help="timed steps of each comparison path (0 = none)")
     ap.add_argument("--compare", default="fp32,bf16",
                     help="other candidate precisions timed on the same data")
+    ap.add_argument("--pipeline-steps", type=int, default=1,
+                    help="timed steps of the P-minimal-pairs pipeline on the same data (0 = none)")
     ap.add_argument("--batch-steps", type=int, default=2,
                     help="timed steps of the 256-instance batched call (0 = none)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -250,6 +252,25 @@ def main():
                             "max_err_ratio": tr2.report["max_err_ratio"]}
             log(f"[bench] {prec}: {ms2:.1f} ms/step, identical tree: {same}")
 
+    # the paper's own pipeline (P minimal pairs per pass) on the same data and kernels
+    pipeline = None
+    if args.pipeline_steps > 0:
+        def pstep():
+            return nnm.mst_build_pminimal(Xd, P=args.n // 2, precision=args.precision)
+        pstep()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.pipeline_steps):
+            pt = pstep()
+        torch.cuda.synchronize()
+        pms = 1e3 * (time.perf_counter() - t0) / args.pipeline_steps
+        pipeline = {"ms_per_step": round(pms, 3), "P": args.n // 2, "passes": pt.report["rounds"],
+                    "timed": "mst_build_pminimal (tree only, no cut)",
+                    "identical_tree": bool(np.array_equal(pt.host_bytes(), tree.host_bytes())),
+                    "vs_merge_rounds_ms": round(ms, 3)}
+        log(f"[bench] P-minimal-pairs pipeline: {pms:.1f} ms, {pt.report['rounds']} passes, "
+            f"identical tree: {pipeline['identical_tree']}")
+
     batch = batch_section(nnm, torch, args.batch_steps) if args.batch_steps > 0 else None
 
     cpu = None
@@ -280,6 +301,7 @@ def main():
         "oracle_match": match,
         "fp32_path": others.get("fp32"),
         "batch256": batch,
+        "p_minimal_pipeline": pipeline,
         "other_paths": {k2: v2 for k2, v2 in others.items() if k2 != "fp32"},
         "report": {k2: last[k2] for k2 in ("rounds", "rows_scanned", "pairs_evaluated",
                                             "survivors", "overflow_rows", "max_abs_err",
