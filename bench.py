@@ -93,9 +93,27 @@ def cpu_baseline(X, seconds):
             break
         ns = max(ns, min(int(ns * (seconds / max(t1, 1e-3)) ** 0.5), X.shape[0]))
     pairs = ns * (ns - 1) / 2.0
-    return {"value": pairs / t1, "unit": "pair-distances/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {ns} of the {X.shape[0]} points (dense FP64 Prim, every pair "
-                      f"evaluated once), {t1:.1f} s"}
+    out = {"value": pairs / t1, "unit": "pair-distances/s", "cores": cores, "kind": "oracle",
+           "sample": f"first {ns} of the {X.shape[0]} points (dense FP64 Prim, every pair "
+                     f"evaluated once), {t1:.1f} s"}
+    # one thread, on a sample of about a quarter of the time budget
+    n1 = max(2000, int(ns * 0.5 / max(cores, 1) ** 0.5))
+    n1 = min(n1, X.shape[0])
+    t0 = time.perf_counter()
+    oracle.prim_mst(X[:n1], threads=1)
+    t2 = time.perf_counter() - t0
+    out["single_thread"] = {"value": n1 * (n1 - 1) / 2.0 / t2, "cores": 1,
+                            "sample": f"first {n1} points, {t2:.1f} s"}
+    # the whole workload, as run once by the script that wrote the oracle's digests
+    gp = os.path.join(ROOT, "tests", "golden", "aniso500_oracle.json")
+    if os.path.exists(gp):
+        g = json.load(open(gp))
+        if g.get("n") == X.shape[0] and g.get("oracle_seconds"):
+            out["full_workload"] = {"seconds": g["oracle_seconds"], "threads": g.get("oracle_threads"),
+                                    "value": X.shape[0] * (X.shape[0] - 1) / 2.0 / g["oracle_seconds"],
+                                    "source": "tests/golden/aniso500_oracle.json (oracle_seconds, "
+                                              "measured on the 8-core build container)"}
+    return out
 
 
 def batch_section(nnm, torch, steps):
