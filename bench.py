@@ -102,8 +102,9 @@ def cpu_baseline(X, seconds):
     t0 = time.perf_counter()
     oracle.prim_mst(X[:n1], threads=1)
     t2 = time.perf_counter() - t0
-    out["single_thread"] = {"value": n1 * (n1 - 1) / 2.0 / t2, "cores": 1,
-                            "sample": f"first {n1} points, {t2:.1f} s"}
+    r1 = n1 * (n1 - 1) / 2.0 / t2
+    out["single_thread"] = {"value": r1, "cores": 1, "sample": f"first {n1} points, {t2:.1f} s",
+                            "n262144_seconds_at_this_rate": round(262144 * 262143 / 2.0 / r1, 1)}
     # the whole workload, as run once by the script that wrote the oracle's digests
     gp = os.path.join(ROOT, "tests", "golden", "aniso500_oracle.json")
     if os.path.exists(gp):
@@ -161,6 +162,48 @@ def batch_section(nnm, torch, steps):
     return out
 
 
+def grid_section(nnm, torch, steps, n):
+    """The tie-stress workload: integer features 0..15 (FP8 exact on the
+    matrix cores, AUTO), tree + KL1 = 64 cut, against the oracle's digests
+    when they exist."""
+    import numpy as np
+    from workloads import int16grid
+    X = int16grid(0, n=n)
+    Xd = torch.from_numpy(X).to("cuda:0")
+
+    def gstep():
+        t = nnm.mst_build(Xd, precision="auto")
+        lab, k = nnm.cluster_cut(t, n, kl1=64)
+        return t, lab, k
+    gstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t, lab, k = gstep()
+    torch.cuda.synchronize()
+    gms = 1e3 * (time.perf_counter() - t0) / steps
+    out = {"workload": f"int16grid n={n} d=25 seed 0", "ms_per_step": round(gms, 3),
+           "value": n * (n - 1) / 2.0 / (gms * 1e-3), "unit": "pair-distances/s",
+           "precision_used": t.report["precision_used"], "integer_mode": t.report["integer_mode"],
+           "max_abs_err": t.report["max_abs_err"], "clusters": k, "oracle_match": None}
+    gp = os.path.join(ROOT, "tests", "golden", "int16grid_oracle.json")
+    if os.path.exists(gp):
+        want = json.load(open(gp))
+        if want.get("n") == n:
+            u, v, s_, w_ = t.to_numpy()
+            h = hashlib.sha256()
+            for a, ty in ((u, "<i4"), (v, "<i4"), (s_, "<f8"), (w_, "<f8")):
+                h.update(np.ascontiguousarray(a, dtype=ty).tobytes())
+            cut = [c for c in want["cuts"] if set(c) == {"kl1", "clusters", "labels_sha256"}
+                   and c["kl1"] == 64]
+            lh = hashlib.sha256(np.ascontiguousarray(lab, "<i4").tobytes()).hexdigest()
+            out["oracle_match"] = bool(h.hexdigest() == want["tree_sha256"] and cut
+                                       and lh == cut[0]["labels_sha256"])
+    log(f"[bench] int16grid: {gms:.1f} ms/step ({out['precision_used']}), oracle digests match: "
+        f"{out['oracle_match']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +217,8 @@ def main():
                     help="other candidate precisions timed on the same data")
     ap.add_argument("--pipeline-steps", type=int, default=1,
                     help="timed steps of the P-minimal-pairs pipeline on the same data (0 = none)")
+    ap.add_argument("--grid-steps", type=int, default=1,
+                    help="timed steps of the integer-grid workload (FP8 exact, 0 = none)")
     ap.add_argument("--batch-steps", type=int, default=2,
                     help="timed steps of the 256-instance batched call (0 = none)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -249,6 +294,8 @@ def main():
             "pairs_evaluated_per_step": evaluated / args.steps,
             "executed_pairs_per_s": evaluated / (cand_ms * 1e-3) if cand_ms > 0 else 0.0,
             "flops_per_pair": 2 * d + 1}
+    if traffic and cand_ms > 0:
+        roof["hbm_frac"] = round(traffic / (cand_ms * 1e-3 / max(launches, 1)) / 8e12, 5)
 
     # the plain FP32 path (and other precisions) on the same data
     others = {}
@@ -262,12 +309,24 @@ def main():
             torch.cuda.synchronize()
             ms2 = 1e3 * (time.perf_counter() - t0) / args.fp32_steps
             same = np.array_equal(tr2.host_bytes(), tree.host_bytes())
+            r2 = tr2.report
             others[prec] = {"ms_per_step": round(ms2, 3), "value": pairs / (ms2 * 1e-3),
                             "speedup_of_" + args.precision: round(ms2 / ms, 3),
                             "identical_tree": bool(same),
                             "oracle_match": oracle_digest_match(tr2, n, last_labels[prec]),
-                            "ms_candidates": round(tr2.report["ms_candidates"], 3),
-                            "max_err_ratio": tr2.report["max_err_ratio"]}
+                            "ms_candidates": round(r2["ms_candidates"], 3),
+                            "max_err_ratio": r2["max_err_ratio"]}
+            if r2["ms_candidates"] > 0:
+                # that path's own candidate kernel against its own peak
+                ev = r2["pairs_evaluated"]
+                if prec == "fp32":
+                    fl, pk, un = 3 * d, FP32_VECTOR_PEAK_TFLOPS, "alu"
+                else:
+                    fl, pk, un = 2 * d + 1, MFMA_PEAK_TFLOPS.get(prec, 2500.0), "mfma"
+                ach = ev * fl / (r2["ms_candidates"] * 1e-3) / 1e12
+                others[prec]["roofline"] = {"bound": un, "achieved": round(ach, 3), "peak": pk,
+                                            "unit": "TFLOP/s", "frac": round(ach / pk, 5),
+                                            "flops_per_pair": fl}
             log(f"[bench] {prec}: {ms2:.1f} ms/step, identical tree: {same}")
 
     # the paper's own pipeline (P minimal pairs per pass) on the same data and kernels
@@ -290,6 +349,7 @@ def main():
             f"identical tree: {pipeline['identical_tree']}")
 
     batch = batch_section(nnm, torch, args.batch_steps) if args.batch_steps > 0 else None
+    grid = grid_section(nnm, torch, args.grid_steps, args.n) if args.grid_steps > 0 else None
 
     cpu = None
     if not args.no_cpu:
@@ -319,6 +379,7 @@ def main():
         "oracle_match": match,
         "fp32_path": others.get("fp32"),
         "batch256": batch,
+        "int16grid": grid,
         "p_minimal_pipeline": pipeline,
         "other_paths": {k2: v2 for k2, v2 in others.items() if k2 != "fp32"},
         "report": {k2: last[k2] for k2 in ("rounds", "rows_scanned", "pairs_evaluated",
