@@ -47,6 +47,7 @@
 #include <random>
 #include <vector>
 
+#include "bound.h"
 #include "nnm_common.h"
 
 namespace nnm {
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(256) void k_next_admissible(NextArgs a)
     __shared__ int win;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nq = (a.d + 3) / 4;
+    const double crel = fp32_crel(a.d), a0 = fp32_a0(a.d);
     for (int item = blockIdx.x; item < a.nr * a.splits; item += gridDim.x) {
         __syncthreads();
         const int q = item / a.splits, sp = item % a.splits;
@@ -122,9 +124,27 @@ __global__ __launch_bounds__(256) void k_next_admissible(NextArgs a)
             for (int64_t j = c0 + tid; j < c1; j += 256) {
                 const int cj = a.comp[j];
                 if (cj == ci || a.csize[cj] > lim) continue;
+                const float4* yp = reinterpret_cast<const float4*>(a.xp + j * DMAX);
+                // FP32 first: its sum of squares t is within crel s + a0 of
+                // the key s, so a column whose s is surely below the known
+                // prefix or above this thread's k-th key is dropped unscored
+                {
+                    float t = 0.f;
+                    for (int f4 = 0; f4 < nq; ++f4) {
+                        const float4 y = yp[f4];
+                        const float d0 = xi[4 * f4] - y.x, d1 = xi[4 * f4 + 1] - y.y;
+                        const float d2 = xi[4 * f4 + 2] - y.z, d3 = xi[4 * f4 + 3] - y.w;
+                        t = __builtin_fmaf(d0, d0, t);
+                        t = __builtin_fmaf(d1, d1, t);
+                        t = __builtin_fmaf(d2, d2, t);
+                        t = __builtin_fmaf(d3, d3, t);
+                    }
+                    const double lo = ((double)t - a0) / (1.0 + crel);
+                    const double hi = fp32_upper_from_t((double)t, crel, a0);
+                    if (hi < ls0 || lo > hs[k - 1]) continue;
+                }
                 // the key of eq. (1): FP64 differences and squares, summed in
                 // feature order
-                const float4* yp = reinterpret_cast<const float4*>(a.xp + j * DMAX);
                 double s = 0.0;
                 for (int f4 = 0; f4 < nq; ++f4) {
                     const float4 y = yp[f4];
@@ -187,32 +207,36 @@ __global__ __launch_bounds__(256) void k_next_admissible(NextArgs a)
     }
 }
 
-// The k smallest of a point's per-range lists (each ascending), one thread
-// per point.
+// The k smallest of a point's per-range lists (each ascending): one wave
+// per point, lane r holding the head of range r's list; k rounds of a wave
+// arg-min.
 __global__ __launch_bounds__(256) void k_merge_ranges(NextArgs a)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (q >= a.nr) return;
-    int pos[64];
-    for (int sp = 0; sp < a.splits; ++sp) pos[sp] = 0;
+    const int64_t it = (int64_t)q * a.splits + lane;
+    const int len = lane < a.splits ? a.part_len[it] : 0;
+    int pos = 0;
     int kept = 0;
     for (; kept < a.k; ++kept) {
-        int bsp = -1;
-        double bs = __builtin_huge_val();
-        int bj = 0x7FFFFFFF;
-        for (int sp = 0; sp < a.splits; ++sp) {
-            const int64_t it = (int64_t)q * a.splits + sp;
-            if (pos[sp] >= a.part_len[it]) continue;
-            const double s = a.part_s[it * a.k + pos[sp]];
-            const int j = a.part_j[it * a.k + pos[sp]];
-            if (sj_less(s, j, bs, bj)) { bs = s; bj = j; bsp = sp; }
+        double bs = pos < len ? a.part_s[it * a.k + pos] : __builtin_huge_val();
+        int bj = pos < len ? a.part_j[it * a.k + pos] : 0x7FFFFFFF;
+        int bl = lane;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double os = __shfl_xor(bs, off);
+            const int oj = __shfl_xor(bj, off);
+            const int ol = __shfl_xor(bl, off);
+            if (sj_less(os, oj, bs, bj) || (os == bs && oj == bj && ol < bl)) { bs = os; bj = oj; bl = ol; }
         }
-        if (bsp < 0) break;
-        ++pos[bsp];
-        a.out_j[(int64_t)q * a.k + kept] = bj;
-        a.out_s[(int64_t)q * a.k + kept] = bs;
+        if (!(bs < __builtin_huge_val())) break;
+        if (lane == 0) {
+            a.out_j[(int64_t)q * a.k + kept] = bj;
+            a.out_s[(int64_t)q * a.k + kept] = bs;
+        }
+        if (lane == bl) ++pos;
     }
-    a.out_len[q] = kept;
+    if (lane == 0) a.out_len[q] = kept;
 }
 
 #define HIP_OK(x)                                  \
@@ -440,7 +464,7 @@ nnm_status refill(Process& p, const float* X, int32_t d, int64_t ld, Workspace& 
     a.part_len = w.part_len;
     const int64_t items = (int64_t)nr * a.splits;
     k_next_admissible<<<(unsigned)std::min<int64_t>(items, 8192), 256, 0, s>>>(a);
-    k_merge_ranges<<<(unsigned)((nr + 255) / 256), 256, 0, s>>>(a);
+    k_merge_ranges<<<(unsigned)((nr + 3) / 4), 256, 0, s>>>(a);
     HIP_OK(hipGetLastError());
     std::vector<int32_t> oj((size_t)nr * p.K), ol((size_t)nr);
     std::vector<double> os((size_t)nr * p.K);
