@@ -87,6 +87,15 @@ __global__ __launch_bounds__(256) void k_pad_points(const float* __restrict__ X,
     xp[t] = f < d ? X[i * ld + f] : 0.f;
 }
 
+// dst[idx[e]] = val[e] for e < m (every index listed once with its final value)
+__global__ __launch_bounds__(256) void k_scatter_i32(const int32_t* __restrict__ idx,
+                                                     const int32_t* __restrict__ val, int64_t m,
+                                                     int32_t* __restrict__ dst)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < m) dst[idx[e]] = val[e];
+}
+
 // One workgroup per (point, column range), grid-stride: every thread keeps
 // the k smallest admissible (s, j) of its columns, then k rounds of a
 // workgroup arg-min merge the 256 lists into the range's list.
@@ -95,6 +104,8 @@ __global__ __launch_bounds__(256) void k_next_admissible(NextArgs a)
     __shared__ double rs[4];
     __shared__ int rj[4], rt[4];
     __shared__ int win;
+    __shared__ float uv[4];
+    __shared__ int ut[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nq = (a.d + 3) / 4;
     const double crel = fp32_crel(a.d), a0 = fp32_a0(a.d);
@@ -120,28 +131,75 @@ __global__ __launch_bounds__(256) void k_next_admissible(NextArgs a)
         for (int e = 0; e < KMAX; ++e) { hs[e] = __builtin_huge_val(); hj[e] = 0x7FFFFFFF; }
         const int k = a.k;
         const int64_t c0 = a.n * sp / a.splits, c1 = a.n * (sp + 1) / a.splits;
+        // FP32 sum of squares of the pair (i, j): within crel s + a0 of its key s
+        auto fp32_t = [&](const float4* yp) {
+            float t = 0.f;
+            for (int f4 = 0; f4 < nq; ++f4) {
+                const float4 y = yp[f4];
+                const float d0 = xi[4 * f4] - y.x, d1 = xi[4 * f4 + 1] - y.y;
+                const float d2 = xi[4 * f4 + 2] - y.z, d3 = xi[4 * f4 + 3] - y.w;
+                t = __builtin_fmaf(d0, d0, t);
+                t = __builtin_fmaf(d1, d1, t);
+                t = __builtin_fmaf(d2, d2, t);
+                t = __builtin_fmaf(d3, d3, t);
+            }
+            return t;
+        };
+        // A bound U on the k-th key of this range: the k-th smallest upper
+        // bound over columns that are surely admissible and beyond the known
+        // prefix (each thread keeps its k smallest, then k rounds of a
+        // workgroup minimum).  Only columns whose lower bound is <= U get the
+        // FP64 key below.
+        float U = __builtin_huge_valf();
+        if (lim >= 0) {
+            float hv[KMAX];
+            for (int e = 0; e < KMAX; ++e) hv[e] = __builtin_huge_valf();
+            for (int64_t j = c0 + tid; j < c1; j += 256) {
+                const int cj = a.comp[j];
+                if (cj == ci || a.csize[cj] > lim) continue;
+                const float t = fp32_t(reinterpret_cast<const float4*>(a.xp + j * DMAX));
+                const double lo = ((double)t - a0) / (1.0 + crel);
+                const double hi = fp32_upper_from_t((double)t, crel, a0);
+                if (!(lo > ls0) || __builtin_sqrt(hi) > a.dmax) continue;
+                const float hf = d2f_up(hi);
+                if (!(hf < hv[k - 1])) continue;
+                int p = k - 1;
+                while (p > 0 && hv[p - 1] > hf) { hv[p] = hv[p - 1]; --p; }
+                hv[p] = hf;
+            }
+            int head = 0;
+            for (int r = 0; r < k; ++r) {
+                float bv = head < k ? hv[head] : __builtin_huge_valf();
+                int bt = tid;
+                for (int off = 32; off > 0; off >>= 1) {
+                    const float ov = __shfl_xor(bv, off);
+                    const int ot = __shfl_xor(bt, off);
+                    if (ov < bv || (ov == bv && ot < bt)) { bv = ov; bt = ot; }
+                }
+                if (lane == 0) { uv[wave] = bv; ut[wave] = bt; }
+                __syncthreads();
+                float v0 = uv[0];
+                int t0 = ut[0];
+                for (int w = 1; w < 4; ++w)
+                    if (uv[w] < v0 || (uv[w] == v0 && ut[w] < t0)) { v0 = uv[w]; t0 = ut[w]; }
+                __syncthreads();
+                if (!(v0 < __builtin_huge_valf())) break;   // fewer than k sure columns
+                if (tid == t0) ++head;
+                if (r == k - 1) U = v0;
+            }
+        }
         if (lim >= 0) {
             for (int64_t j = c0 + tid; j < c1; j += 256) {
                 const int cj = a.comp[j];
                 if (cj == ci || a.csize[cj] > lim) continue;
                 const float4* yp = reinterpret_cast<const float4*>(a.xp + j * DMAX);
-                // FP32 first: its sum of squares t is within crel s + a0 of
-                // the key s, so a column whose s is surely below the known
-                // prefix or above this thread's k-th key is dropped unscored
+                // a column whose key is surely below the known prefix, above
+                // U or above this thread's k-th key is dropped unscored
                 {
-                    float t = 0.f;
-                    for (int f4 = 0; f4 < nq; ++f4) {
-                        const float4 y = yp[f4];
-                        const float d0 = xi[4 * f4] - y.x, d1 = xi[4 * f4 + 1] - y.y;
-                        const float d2 = xi[4 * f4 + 2] - y.z, d3 = xi[4 * f4 + 3] - y.w;
-                        t = __builtin_fmaf(d0, d0, t);
-                        t = __builtin_fmaf(d1, d1, t);
-                        t = __builtin_fmaf(d2, d2, t);
-                        t = __builtin_fmaf(d3, d3, t);
-                    }
+                    const float t = fp32_t(yp);
                     const double lo = ((double)t - a0) / (1.0 + crel);
                     const double hi = fp32_upper_from_t((double)t, crel, a0);
-                    if (hi < ls0 || lo > hs[k - 1]) continue;
+                    if (hi < ls0 || lo > (double)U || lo > hs[k - 1]) continue;
                 }
                 // the key of eq. (1): FP64 differences and squares, summed in
                 // feature order
@@ -276,11 +334,13 @@ struct Workspace {
     int32_t* part_j;          // [max(n, PART_MIN)][k]
     double* part_s;
     int32_t* part_len;        // [max(n, PART_MIN)]
+    int32_t* upd_i;           // [2n] cluster-id and size updates
+    int32_t* upd_v;           // [2n]
 };
 
 // per-range lists: a batch of nr points uses nr * splits <= max(nr, PART_MIN)
 constexpr int64_t PART_MIN = 8192;
-constexpr int64_t TARGET_GROUPS = 4096;
+constexpr int64_t TARGET_GROUPS = 1024;
 
 size_t carve_ap(int64_t n, int32_t k, size_t knn_bytes, char* base, Workspace* w)
 {
@@ -311,6 +371,8 @@ size_t carve_ap(int64_t n, int32_t k, size_t knn_bytes, char* base, Workspace* w
     w->part_j = (int32_t*)take(P * K * 4);
     w->part_s = (double*)take(P * K * 8);
     w->part_len = (int32_t*)take(P * 4);
+    w->upd_i = (int32_t*)take(2 * N * 4);
+    w->upd_v = (int32_t*)take(2 * N * 4);
     return off + 256;
 }
 
@@ -332,6 +394,10 @@ struct Process {
     // smaller side are relabelled at each union), sizes and versions by id
     std::vector<int32_t> size, ver;
     std::vector<int32_t> cid, mnext, mhead, mtail;
+    // changes since the device copy was last brought up to date
+    bool uploaded = false;
+    std::vector<int32_t> dirty_pts, dirty_roots;   // each listed once (dmark bits 1, 2)
+    std::vector<uint8_t> dmark;
     // per-cluster meldable heaps of points (randomised meld)
     std::vector<int32_t> hl, hr, hroot;
     std::vector<PairKey> hkey;
@@ -435,8 +501,36 @@ nnm_status refill(Process& p, const float* X, int32_t d, int64_t ld, Workspace& 
         lbj[(size_t)q] = p.lj[(size_t)r * p.K + p.K - 1];
         lim[(size_t)q] = p.limit_of(p.size[(size_t)p.cid[(size_t)r]]);
     }
-    HIP_OK(hipMemcpyAsync(w.comp, p.cid.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(w.csize, p.size.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, s));
+    // the clusters as they are now: everything the first time, then only
+    // the points relabelled and the sizes changed since the last scan
+    if (!p.uploaded) {
+        HIP_OK(hipMemcpyAsync(w.comp, p.cid.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, s));
+        HIP_OK(hipMemcpyAsync(w.csize, p.size.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, s));
+        p.uploaded = true;
+    } else {
+        const size_t np = p.dirty_pts.size(), nc = p.dirty_roots.size();
+        std::vector<int32_t> iv(np + nc), vv(np + nc);
+        for (size_t e = 0; e < np; ++e) {
+            iv[e] = p.dirty_pts[e];
+            vv[e] = p.cid[(size_t)p.dirty_pts[e]];
+        }
+        for (size_t e = 0; e < nc; ++e) {
+            iv[np + e] = p.dirty_roots[e];
+            vv[np + e] = p.size[(size_t)p.dirty_roots[e]];
+        }
+        if (np + nc > 0) {
+            HIP_OK(hipMemcpyAsync(w.upd_i, iv.data(), 4 * iv.size(), hipMemcpyHostToDevice, s));
+            HIP_OK(hipMemcpyAsync(w.upd_v, vv.data(), 4 * vv.size(), hipMemcpyHostToDevice, s));
+            k_scatter_i32<<<(unsigned)((np + 255) / 256 + 1), 256, 0, s>>>(w.upd_i, w.upd_v, (int64_t)np, w.comp);
+            k_scatter_i32<<<(unsigned)((nc + 255) / 256 + 1), 256, 0, s>>>(w.upd_i + np, w.upd_v + np,
+                                                                           (int64_t)nc, w.csize);
+            HIP_OK(hipGetLastError());
+        }
+    }
+    for (int32_t x : p.dirty_pts) p.dmark[(size_t)x] &= (uint8_t)~1u;
+    for (int32_t x : p.dirty_roots) p.dmark[(size_t)x] &= (uint8_t)~2u;
+    p.dirty_pts.clear();
+    p.dirty_roots.clear();
     HIP_OK(hipMemcpyAsync(w.rows, p.spent.data(), 4 * (size_t)nr, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(w.lb_s, lbs.data(), 8 * (size_t)nr, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(w.lb_j, lbj.data(), 4 * (size_t)nr, hipMemcpyHostToDevice, s));
@@ -713,6 +807,7 @@ extern "C" nnm_status cluster_cut_allpairs(const float* X_dev, int64_t n, int32_
     p.hroot.assign(N, -1);
     p.hkey.resize(N);
     p.cid.resize(N);
+    p.dmark.assign(N, 0);
     p.mnext.assign(N, -1);
     p.mhead.resize(N);
     p.mtail.resize(N);
@@ -763,7 +858,17 @@ extern "C" nnm_status cluster_cut_allpairs(const float* X_dev, int64_t n, int32_
         p.hroot[(size_t)o] = -1;
         p.troot[(size_t)Z] = p.tmeld(p.troot[(size_t)Z], p.troot[(size_t)o]);
         p.troot[(size_t)o] = -1;
-        for (int32_t x = p.mhead[(size_t)o]; x >= 0; x = p.mnext[(size_t)x]) p.cid[(size_t)x] = Z;
+        for (int32_t x = p.mhead[(size_t)o]; x >= 0; x = p.mnext[(size_t)x]) {
+            p.cid[(size_t)x] = Z;
+            if (p.uploaded && !(p.dmark[(size_t)x] & 1)) {
+                p.dmark[(size_t)x] |= 1;
+                p.dirty_pts.push_back(x);
+            }
+        }
+        if (p.uploaded && !(p.dmark[(size_t)Z] & 2)) {
+            p.dmark[(size_t)Z] |= 2;
+            p.dirty_roots.push_back(Z);
+        }
         p.mnext[(size_t)p.mtail[(size_t)Z]] = p.mhead[(size_t)o];
         p.mtail[(size_t)Z] = p.mtail[(size_t)o];
         p.ver[(size_t)Z] += 1;
