@@ -55,17 +55,25 @@ namespace {
 
 // ---- GPU: the next k admissible neighbours of a batch of points ---------
 
+// One point of a rescan batch: the point, the key (lb_s, lb_j) of the last
+// neighbour already known ((s, j) order), and the largest admissible size
+// of the other cluster (-1: none).
+struct NextReq {
+    int32_t row;
+    int32_t lb_j;
+    int32_t limit;
+    int32_t pad_;
+    double lb_s;
+};
+
 struct NextArgs {
     const float* xp;          // [n][DMAX] padded copy of the points
     int32_t d;
     int32_t k;
     int64_t n;
-    const int32_t* rows;      // [nr] points
+    const struct NextReq* req;// [nr] the points and what is known of them
     int32_t nr;
     int32_t splits;           // column ranges per point
-    const double* lb_s;       // [nr] key of the last neighbour already known
-    const int32_t* lb_j;      // [nr] and its index ((s, j) order)
-    const int32_t* limit;     // [nr] largest admissible size of the other cluster (-1: none)
     const int32_t* comp;      // [n] cluster of each point
     const int32_t* csize;     // [n] size of each cluster, by cluster id
     double dmax;
@@ -88,12 +96,11 @@ __global__ __launch_bounds__(256) void k_pad_points(const float* __restrict__ X,
 }
 
 // dst[idx[e]] = val[e] for e < m (every index listed once with its final value)
-__global__ __launch_bounds__(256) void k_scatter_i32(const int32_t* __restrict__ idx,
-                                                     const int32_t* __restrict__ val, int64_t m,
+__global__ __launch_bounds__(256) void k_scatter_i32(const int2* __restrict__ upd, int64_t m,
                                                      int32_t* __restrict__ dst)
 {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e < m) dst[idx[e]] = val[e];
+    if (e < m) dst[upd[e].x] = upd[e].y;
 }
 
 // One workgroup per (point, column range), grid-stride: every thread keeps
@@ -112,11 +119,12 @@ __global__ __launch_bounds__(256) void k_next_admissible(NextArgs a)
     for (int item = blockIdx.x; item < a.nr * a.splits; item += gridDim.x) {
         __syncthreads();
         const int q = item / a.splits, sp = item % a.splits;
-        const int i = a.rows[q];
+        const NextReq rq = a.req[q];
+        const int i = rq.row;
         const int ci = a.comp[i];
-        const int lim = a.limit[q];
-        const double ls0 = a.lb_s[q];
-        const int lj0 = a.lb_j[q];
+        const int lim = rq.limit;
+        const double ls0 = rq.lb_s;
+        const int lj0 = rq.lb_j;
         float xi[DMAX];
         {
             const float4* src = reinterpret_cast<const float4*>(a.xp + (int64_t)i * DMAX);
@@ -321,21 +329,28 @@ struct Workspace {
     int32_t* idx;             // [n][k]
     double* sd;               // [n][k]
     int32_t* len;             // [n]
-    int32_t* rows;            // [n]
-    double* lb_s;             // [n]
-    int32_t* lb_j;            // [n]
-    int32_t* limit;           // [n]
     int32_t* comp;            // [n]
     int32_t* csize;           // [n]
-    int32_t* out_j;           // [n][k]
-    double* out_s;            // [n][k]
-    int32_t* out_len;         // [n]
     float* xp;                // [n][DMAX]
     int32_t* part_j;          // [max(n, PART_MIN)][k]
     double* part_s;
     int32_t* part_len;        // [max(n, PART_MIN)]
-    int32_t* upd_i;           // [2n] cluster-id and size updates
-    int32_t* upd_v;           // [2n]
+    // one upload per rescan: [2n] (index, value) updates of the cluster ids
+    // and sizes, then [n] requests; one download: lengths, indices, keys
+    char* upload;
+    char* download;
+};
+
+// byte layout of a rescan's download for nr points of k neighbours
+struct DownLayout {
+    size_t len_off, j_off, s_off, bytes;
+    DownLayout(int64_t nr, int32_t k)
+    {
+        len_off = 0;
+        j_off = (size_t)nr * 4;
+        s_off = (j_off + (size_t)nr * k * 4 + 7) & ~(size_t)7;
+        bytes = s_off + (size_t)nr * k * 8;
+    }
 };
 
 // per-range lists: a batch of nr points uses nr * splits <= max(nr, PART_MIN)
@@ -357,22 +372,15 @@ size_t carve_ap(int64_t n, int32_t k, size_t knn_bytes, char* base, Workspace* w
     w->idx = (int32_t*)take(N * K * 4);
     w->sd = (double*)take(N * K * 8);
     w->len = (int32_t*)take(N * 4);
-    w->rows = (int32_t*)take(N * 4);
-    w->lb_s = (double*)take(N * 8);
-    w->lb_j = (int32_t*)take(N * 4);
-    w->limit = (int32_t*)take(N * 4);
     w->comp = (int32_t*)take(N * 4);
     w->csize = (int32_t*)take(N * 4);
-    w->out_j = (int32_t*)take(N * K * 4);
-    w->out_s = (double*)take(N * K * 8);
-    w->out_len = (int32_t*)take(N * 4);
     w->xp = (float*)take(N * DMAX * 4);
     const size_t P = (size_t)std::max<int64_t>(n, PART_MIN);
     w->part_j = (int32_t*)take(P * K * 4);
     w->part_s = (double*)take(P * K * 8);
     w->part_len = (int32_t*)take(P * 4);
-    w->upd_i = (int32_t*)take(2 * N * 4);
-    w->upd_v = (int32_t*)take(2 * N * 4);
+    w->upload = (char*)take(2 * N * sizeof(int2) + N * sizeof(NextReq) + 64);
+    w->download = (char*)take(DownLayout((int64_t)N, k).bytes + 64);
     return off + 256;
 }
 
@@ -408,6 +416,26 @@ struct Process {
     bool rows_ready = false;         // neighbour prefixes built
     std::vector<int32_t> tl, tr, troot;
     std::mt19937 coin{12345};
+    // page-locked staging of the rescans' transfers (grown on demand)
+    struct Pinned {
+        void* p = nullptr;
+        size_t cap = 0;
+        ~Pinned()
+        {
+            if (p) (void)hipHostFree(p);
+        }
+        void* get(size_t bytes)
+        {
+            if (bytes > cap) {
+                if (p) (void)hipHostFree(p);
+                p = nullptr;
+                cap = 0;
+                if (hipHostMalloc(&p, bytes, 0) != hipSuccess) return nullptr;
+                cap = bytes;
+            }
+            return p;
+        }
+    } up_pin, down_pin;
     int64_t refills = 0, refilled_rows = 0, merges = 0;
     double refill_ms = 0.0;
 
@@ -493,64 +521,58 @@ nnm_status refill(Process& p, const float* X, int32_t d, int64_t ld, Workspace& 
     const int32_t nr = (int32_t)p.spent.size();
     if (nr == 0) return NNM_OK;
     const auto t0 = std::chrono::steady_clock::now();
-    std::vector<int32_t> lim((size_t)nr), lbj((size_t)nr);
-    std::vector<double> lbs((size_t)nr);
-    for (int32_t q = 0; q < nr; ++q) {
-        const int32_t r = p.spent[(size_t)q];
-        lbs[(size_t)q] = p.ls[(size_t)r * p.K + p.K - 1];
-        lbj[(size_t)q] = p.lj[(size_t)r * p.K + p.K - 1];
-        lim[(size_t)q] = p.limit_of(p.size[(size_t)p.cid[(size_t)r]]);
-    }
     // the clusters as they are now: everything the first time, then only
     // the points relabelled and the sizes changed since the last scan
+    size_t nu = 0;
     if (!p.uploaded) {
         HIP_OK(hipMemcpyAsync(w.comp, p.cid.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, s));
         HIP_OK(hipMemcpyAsync(w.csize, p.size.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, s));
         p.uploaded = true;
     } else {
-        const size_t np = p.dirty_pts.size(), nc = p.dirty_roots.size();
-        std::vector<int32_t> iv(np + nc), vv(np + nc);
-        for (size_t e = 0; e < np; ++e) {
-            iv[e] = p.dirty_pts[e];
-            vv[e] = p.cid[(size_t)p.dirty_pts[e]];
-        }
-        for (size_t e = 0; e < nc; ++e) {
-            iv[np + e] = p.dirty_roots[e];
-            vv[np + e] = p.size[(size_t)p.dirty_roots[e]];
-        }
-        if (np + nc > 0) {
-            HIP_OK(hipMemcpyAsync(w.upd_i, iv.data(), 4 * iv.size(), hipMemcpyHostToDevice, s));
-            HIP_OK(hipMemcpyAsync(w.upd_v, vv.data(), 4 * vv.size(), hipMemcpyHostToDevice, s));
-            k_scatter_i32<<<(unsigned)((np + 255) / 256 + 1), 256, 0, s>>>(w.upd_i, w.upd_v, (int64_t)np, w.comp);
-            k_scatter_i32<<<(unsigned)((nc + 255) / 256 + 1), 256, 0, s>>>(w.upd_i + np, w.upd_v + np,
-                                                                           (int64_t)nc, w.csize);
-            HIP_OK(hipGetLastError());
-        }
+        nu = p.dirty_pts.size() + p.dirty_roots.size();
     }
+    const size_t np = p.uploaded ? p.dirty_pts.size() : 0, nc = nu - np;
+    const size_t req_off = (nu * sizeof(int2) + 15) & ~(size_t)15;
+    const size_t up_bytes = req_off + (size_t)nr * sizeof(NextReq);
+    char* up = (char*)p.up_pin.get(up_bytes);
+    if (!up) return NNM_EDEVICE;
+    int2* upd = reinterpret_cast<int2*>(up);
+    for (size_t e = 0; e < np; ++e) upd[e] = make_int2(p.dirty_pts[e], p.cid[(size_t)p.dirty_pts[e]]);
+    for (size_t e = 0; e < nc; ++e)
+        upd[np + e] = make_int2(p.dirty_roots[e], p.size[(size_t)p.dirty_roots[e]]);
+    NextReq* rq = reinterpret_cast<NextReq*>(up + req_off);
+    for (int32_t q = 0; q < nr; ++q) {
+        const int32_t r = p.spent[(size_t)q];
+        rq[q].row = r;
+        rq[q].lb_j = p.lj[(size_t)r * p.K + p.K - 1];
+        rq[q].limit = p.limit_of(p.size[(size_t)p.cid[(size_t)r]]);
+        rq[q].pad_ = 0;
+        rq[q].lb_s = p.ls[(size_t)r * p.K + p.K - 1];
+    }
+    HIP_OK(hipMemcpyAsync(w.upload, up, up_bytes, hipMemcpyHostToDevice, s));
+    if (np > 0)
+        k_scatter_i32<<<(unsigned)((np + 255) / 256), 256, 0, s>>>((const int2*)w.upload, (int64_t)np, w.comp);
+    if (nc > 0)
+        k_scatter_i32<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>((const int2*)w.upload + np, (int64_t)nc,
+                                                                   w.csize);
     for (int32_t x : p.dirty_pts) p.dmark[(size_t)x] &= (uint8_t)~1u;
     for (int32_t x : p.dirty_roots) p.dmark[(size_t)x] &= (uint8_t)~2u;
     p.dirty_pts.clear();
     p.dirty_roots.clear();
-    HIP_OK(hipMemcpyAsync(w.rows, p.spent.data(), 4 * (size_t)nr, hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(w.lb_s, lbs.data(), 8 * (size_t)nr, hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(w.lb_j, lbj.data(), 4 * (size_t)nr, hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(w.limit, lim.data(), 4 * (size_t)nr, hipMemcpyHostToDevice, s));
+    const DownLayout L(nr, p.K);
     NextArgs a;
     a.xp = w.xp;
     a.d = d;
     a.k = p.K;
     a.n = p.n;
-    a.rows = w.rows;
+    a.req = reinterpret_cast<const NextReq*>(w.upload + req_off);
     a.nr = nr;
-    a.lb_s = w.lb_s;
-    a.lb_j = w.lb_j;
-    a.limit = w.limit;
     a.comp = w.comp;
     a.csize = w.csize;
     a.dmax = p.dmax;
-    a.out_j = w.out_j;
-    a.out_s = w.out_s;
-    a.out_len = w.out_len;
+    a.out_len = reinterpret_cast<int32_t*>(w.download + L.len_off);
+    a.out_j = reinterpret_cast<int32_t*>(w.download + L.j_off);
+    a.out_s = reinterpret_cast<double*>(w.download + L.s_off);
     // enough workgroups for the chip: few points get more column ranges
     a.splits = nr >= TARGET_GROUPS / 2 ? 1 : (int32_t)std::min<int64_t>(64, (TARGET_GROUPS + nr - 1) / nr);
     a.part_j = w.part_j;
@@ -560,23 +582,24 @@ nnm_status refill(Process& p, const float* X, int32_t d, int64_t ld, Workspace& 
     k_next_admissible<<<(unsigned)std::min<int64_t>(items, 8192), 256, 0, s>>>(a);
     k_merge_ranges<<<(unsigned)((nr + 3) / 4), 256, 0, s>>>(a);
     HIP_OK(hipGetLastError());
-    std::vector<int32_t> oj((size_t)nr * p.K), ol((size_t)nr);
-    std::vector<double> os((size_t)nr * p.K);
-    HIP_OK(hipMemcpyAsync(oj.data(), w.out_j, 4 * oj.size(), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(os.data(), w.out_s, 8 * os.size(), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(ol.data(), w.out_len, 4 * ol.size(), hipMemcpyDeviceToHost, s));
+    char* down = (char*)p.down_pin.get(L.bytes);
+    if (!down) return NNM_EDEVICE;
+    HIP_OK(hipMemcpyAsync(down, w.download, L.bytes, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    const int32_t* ol = reinterpret_cast<const int32_t*>(down + L.len_off);
+    const int32_t* oj = reinterpret_cast<const int32_t*>(down + L.j_off);
+    const double* os = reinterpret_cast<const double*>(down + L.s_off);
     for (int32_t q = 0; q < nr; ++q) {
         const int32_t r = p.spent[(size_t)q];
         p.queued[(size_t)r] = 0;
-        const int32_t L = ol[(size_t)q];
-        for (int32_t e = 0; e < L; ++e) {
+        const int32_t ln = ol[q];
+        for (int32_t e = 0; e < ln; ++e) {
             p.lj[(size_t)r * p.K + e] = oj[(size_t)q * p.K + e];
             p.ls[(size_t)r * p.K + e] = os[(size_t)q * p.K + e];
         }
-        p.len[(size_t)r] = L;
+        p.len[(size_t)r] = ln;
         p.cur[(size_t)r] = 0;
-        p.state[(size_t)r] = L > 0 ? 0 : 2;
+        p.state[(size_t)r] = ln > 0 ? 0 : 2;
     }
     p.refills += 1;
     p.refilled_rows += nr;
