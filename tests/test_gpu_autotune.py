@@ -40,7 +40,8 @@ def test_tune_single_then_tuned_call(nnm, tmp_path):
     assert A.lookup(3000, 12, "fp16", cache=cache) == ent
     tree = nnm.mst_build(_dev(X), precision="fp16", tuned=cache)
     torch.cuda.synchronize()
-    assert tree.report["knn_k"] == ent["knn_k"]
+    # 0: the tuner kept the default depth (6 on the FP16 path)
+    assert tree.report["knn_k"] == (ent["knn_k"] or 6)
     u, v, s, w = tree.to_numpy()
     ou, ov, os_, ow = oracle.prim_mst(X)
     assert np.array_equal(u, ou) and np.array_equal(v, ov) and np.array_equal(s, os_)
