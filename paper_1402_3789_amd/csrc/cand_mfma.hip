@@ -14,11 +14,16 @@
 // K slots 0..D-1, the two squared norms ride in slots 26..31 as
 // (value, constant) pairs, so the FP32 accumulator is t itself.
 //
-// Frame.  For BF16 / FP16 on general data both operands are quantised in a
-// frame centred at the row tile's own centre (built in-kernel from an FP32
-// copy), so the quantisation error is relative to the distance from the
-// tile, not from the data's centre; exact integer data (FP8, or BF16/FP16 on
-// integer grids) use precomputed global operands.
+// Frame.  FP16 on general data, and exact integer data (FP8, or BF16/FP16 on
+// integer grids), use precomputed operands in one global frame.  BF16 on
+// general data (8 significant bits) uses the frame of each column
+// super-chunk, centred at that super-chunk's ball centre: the column
+// operands are built once per round in the frame of their own super-chunk
+// (k_split_columns), and a wave re-expresses its rows in a super-chunk's
+// frame when it starts on that super-chunk's chunks, as a sum of two BF16
+// values (q = qh + ql, both multiplied in by two chained MFMAs).  The
+// column error then scales with the super-chunk's radius and the row error
+// is ~2^-16 of the row's distance from the centre.
 //
 // Selection.  For every column that reaches the slow path the proven error
 // bound gives an upper bound on its exact key; each row keeps, in LDS, the k
@@ -67,6 +72,10 @@ template <> struct OpTraits<OP_BF16> {
                                                       __builtin_bit_cast(bf16x8_t, b),
                                                       f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
     }
+    __device__ static f32x4_t mma_acc(uint4 a, uint4 b, f32x4_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                      __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+    }
 };
 template <> struct OpTraits<OP_FP16> {
     typedef uint4 frag_t;             // 8 x f16 per lane
@@ -76,6 +85,7 @@ template <> struct OpTraits<OP_FP16> {
                                                      __builtin_bit_cast(f16x8_t, b),
                                                      f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
     }
+    __device__ static f32x4_t mma_acc(uint4, uint4, f32x4_t c) { return c; }   // not used
 };
 template <> struct OpTraits<OP_FP8> {
     typedef uint2 frag_t;             // 8 x e4m3 per lane
@@ -85,6 +95,7 @@ template <> struct OpTraits<OP_FP8> {
                                                          __builtin_bit_cast(long, b),
                                                          f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
     }
+    __device__ static f32x4_t mma_acc(uint2, uint2, f32x4_t c) { return c; }   // not used
 };
 
 // Upper bound, in FP32, on the exact key of a pair whose FP32 direct-difference
@@ -195,9 +206,12 @@ struct GroupGen {
         return g;
     }
 
-    // Wave w expands super-chunk sc (-1: none) into slots [SUPER w, SUPER w + SUPER).
+    // Wave w expands super-chunk sc (-1: none) into slots [SUPER w, SUPER w + SUPER);
+    // with gcm (super-chunk frames) also each chunk's column maxima of the
+    // bound inputs, and the super-chunk itself into gsc[w].
     __device__ void expand(const TileShared& sh, const CandArgs& a, int lo_r, int hi_r, float umax,
-                           int sc, int w, float (*gball)[BALL_STRIDE], int4* gpos, int32_t* gneed)
+                           int sc, int w, float (*gball)[BALL_STRIDE], int4* gpos, int32_t* gneed,
+                           float4* gcm, int32_t* gsc)
     {
         const int lane = threadIdx.x & 63, step = lane & 15, part = lane >> 4;
         const int slot = SUPER * w + step;
@@ -255,6 +269,10 @@ struct GroupGen {
             gball[slot][DMAX] = rad;
             gpos[slot] = make_int4((int)c0, (int)c1, clo, chi);
             gneed[slot] = pass ? 16 : 0;
+            if (gcm) {
+                gcm[slot] = a.cmaxT[ci];
+                if (step == 0) gsc[w] = sc;
+            }
         }
     }
 };
@@ -335,11 +353,73 @@ __device__ __forceinline__ void local_operands(const float* x, const float* c, f
     pc.eta = d2f_up((F::alpha * (double)__builtin_sqrtf(vn) * up + F::beta * __builtin_sqrt((double)d)) * up);
 }
 
-// LOCAL: BF16 operands are built in-kernel from the sorted FP32 copy of the
-// points, in a frame centred at the row tile's own centre, so their error
-// scales with the distance from the tile rather than from the data's centre.
-// Otherwise (FP16, exact integer data, FP8) the precomputed global operands
-// are used.
+// Column operands of the super-chunk frames (BF16 on general data), once
+// per round after the chunk tables and balls: workgroup ci writes the columns
+// of chunk ci in the frame of its super-chunk (centre: that super-chunk's
+// ball centre) to opC, and the maxima of their bound inputs (Q, P, rho, eta)
+// to cmax[ci].  TAB: component-aligned tables; workgroups past the chunk
+// count exit.
+template <bool TAB>
+__global__ __launch_bounds__(256) void k_split_columns(const float* __restrict__ xs, int64_t np, int d,
+                                                       float sigma, const int32_t* __restrict__ cstart,
+                                                       const int32_t* __restrict__ csup,
+                                                       const int32_t* __restrict__ tabn,
+                                                       const float* __restrict__ sballs,
+                                                       uint4* __restrict__ opC, float4* __restrict__ cmax)
+{
+    __shared__ float4 red[4];
+    const int ci = (int)blockIdx.x;
+    int64_t c0, c1;
+    int sc;
+    if constexpr (TAB) {
+        if (ci >= tabn[0]) return;
+        c0 = cstart[ci];
+        c1 = cstart[ci + 1];
+        sc = csup[ci];
+    } else {
+        c0 = (int64_t)ci * CHUNK;
+        c1 = c0 + CHUNK < np ? c0 + CHUNK : np;
+        sc = ci / SUPER;
+    }
+    const int64_t p = c0 + threadIdx.x;
+    float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (p < c1) {
+        float y[DMAX];
+        const float4* src = reinterpret_cast<const float4*>(xs + p * DMAX);
+#pragma unroll
+        for (int q = 0; q < DMAX / 4; ++q) {
+            const float4 v = src[q];
+            y[4 * q + 0] = v.x; y[4 * q + 1] = v.y; y[4 * q + 2] = v.z; y[4 * q + 3] = v.w;
+        }
+        uint4 row[4], col[4];
+        PointConst pc;
+        local_operands<OP_BF16>(y, sballs + (int64_t)sc * BALL_STRIDE, sigma, d, row, col, pc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) opC[p * 4 + q] = col[q];
+        m = make_float4(pc.Q, pc.P, pc.rho, pc.eta);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        m.x = fmaxf(m.x, __shfl_xor(m.x, off));
+        m.y = fmaxf(m.y, __shfl_xor(m.y, off));
+        m.z = fmaxf(m.z, __shfl_xor(m.z, off));
+        m.w = fmaxf(m.w, __shfl_xor(m.w, off));
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float4 r = red[0];
+        for (int w = 1; w < 4; ++w) {
+            r.x = fmaxf(r.x, red[w].x);
+            r.y = fmaxf(r.y, red[w].y);
+            r.z = fmaxf(r.z, red[w].z);
+            r.w = fmaxf(r.w, red[w].w);
+        }
+        cmax[ci] = r;
+    }
+}
+
+// LOCAL: BF16 on general data in the super-chunk frames (see the top of the
+// file); otherwise the precomputed global operands are used.
 //
 // Per-row state in LDS (thread t owns row t of the tile; the slow path of
 // the wave holding the row touches it one lane group at a time), packed so
@@ -361,7 +441,9 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
 
     __shared__ __align__(16) frag_t colbuf[2][BN / 16 * 4 * 16];  // two chunks: one in use, one filling
     __shared__ __align__(16) int32_t colcomp[2][BN];
-    __shared__ float cmax[2][4][4];                        // LOCAL: per-wave column maxima
+    __shared__ float4 gcm[LOCAL ? GW : 1];                 // LOCAL: column maxima per candidate chunk
+    __shared__ int32_t gsc[GS];                            // LOCAL: super-chunk of each wave's slots
+    __shared__ float4 rpc[LOCAL ? BM : 1];                 // LOCAL: rows' bound inputs, current frame
     __shared__ float4 rs[BM][2];                           // per-row state, see above
     __shared__ float wmx[4];                               // per-wave max of U
     __shared__ __align__(16) float wcen[4][DMAX];          // per-wave ball of the rows
@@ -404,9 +486,11 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
             x[4 * q + 0] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
         }
     }
-    float4 xq[NQR];                                        // kept for the per-row ball tests
+    // kept for the per-row ball tests (LOCAL: reloaded per group instead,
+    // which keeps them out of the registers of the chunk evaluation)
+    float4 xq[LOCAL ? 1 : NQR];
 #pragma unroll
-    for (int q = 0; q < NQR; ++q) xq[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+    for (int q = 0; q < (LOCAL ? 1 : NQR); ++q) xq[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
     float* my_tk = topk + tid * KP;
     for (int e = 0; e < KP; ++e) my_tk[e] = __builtin_huge_valf();
     float U = 0.f;
@@ -427,8 +511,8 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
 #pragma unroll
                 for (int f4 = 0; f4 < NQR; ++f4) {
                     const float4 y = src[f4];
-                    const float d0 = xq[f4].x - y.x, d1 = xq[f4].y - y.y;
-                    const float d2 = xq[f4].z - y.z, d3 = xq[f4].w - y.w;
+                    const float d0 = x[4 * f4] - y.x, d1 = x[4 * f4 + 1] - y.y;
+                    const float d2 = x[4 * f4 + 2] - y.z, d3 = x[4 * f4 + 3] - y.w;
                     sq = __builtin_fmaf(d0, d0, sq);
                     sq = __builtin_fmaf(d1, d1, sq);
                     sq = __builtin_fmaf(d2, d2, sq);
@@ -447,17 +531,11 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
     }
     rs[tid][0] = make_float4(-__builtin_huge_valf(), U, 0.f, 0.f);
     rs[tid][1] = make_float4(__int_as_float(0), __int_as_float(my_comp), 0.f, 0.f);
-    if (a.prune || LOCAL) tile_ball<DMAX>(sh, x, my_valid, a.d);
+    if (a.prune) tile_ball<DMAX>(sh, x, my_valid, a.d);
     if (a.prune) wave_ball<DMAX>(&wcen[wave][0], &wrad[wave], x, my_valid, a.d);
-    // row operand and its bound inputs
+    // row operand and its bound inputs (LOCAL: per super-chunk frame, below)
     PointConst mypc{0.f, 0.f, 0.f, 0.f};
-    if constexpr (LOCAL) {
-        uint4 rowop[4], colop[4];
-        local_operands<OP>(x, sh.cen, sigma, a.d, rowop, colop, mypc);
-        uint4* stage = reinterpret_cast<uint4*>(&colbuf[0][0]);   // free until the sweep
-#pragma unroll
-        for (int q = 0; q < 4; ++q) stage[tid * 4 + q] = rowop[q];
-    } else {
+    if constexpr (!LOCAL) {
         if (my_valid) mypc = a.pc[my_rp];
         // one frame for every pair: the row's slack is fixed
         rs[tid][0].z = global_eps(mypc, a.bc);
@@ -475,9 +553,11 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
         sh.col_lo = tile.z;
         sh.col_hi = tile.w;
     }
-    __syncthreads();                                       // the row stage in colbuf is written
-    // row fragments stay in registers for the whole sweep
-    frag_t bfrag[RB];
+    __syncthreads();                                       // the tile's shared fields are written
+    // row fragments stay in registers for the whole sweep (LOCAL: both
+    // halves, rebuilt per super-chunk frame from the rows' positions)
+    frag_t bfrag[RB], bfl[LOCAL ? RB : 1];
+    int32_t rprb[LOCAL ? RB : 1];
     int32_t rcomp[RB];
     uint32_t rvmask = 0;                                   // hit bits of valid rows
 #pragma unroll
@@ -487,7 +567,9 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
         const bool ok = slot < row_end;
         const int rp = ok ? (a.rows ? a.rows[slot] : a.row0 + (int)slot) : 0;
         if constexpr (LOCAL) {
-            bfrag[rb] = reinterpret_cast<const frag_t*>(&colbuf[0][0])[rl * 4 + grp];
+            bfrag[rb] = frag_t{};
+            bfl[rb] = frag_t{};
+            rprb[rb] = rp;
         } else {
             bfrag[rb] = reinterpret_cast<const frag_t*>(a.opR)[(int64_t)rp * 4 + grp];
         }
@@ -498,13 +580,12 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
     const int lo_r = sh.lo, hi_r = sh.hi;
     const bool one_comp = lo_r == hi_r;
     const int cl = sh.col_lo, ch = sh.col_hi;
-    __syncthreads();                                       // the row stage in colbuf is consumed
+    int frame = -1;                                        // LOCAL: the wave's current super-chunk frame
 
     // ---- column sweep: nearest chunks first, the next one in flight ---------
     unsigned long long pairs = 0;                          // per wave
     // Thread t carries column t of a chunk from global memory to LDS.
-    uint4 pf[LOCAL ? 1 : PF];
-    float4 pfx[LOCAL ? NQR : 1];
+    uint4 pf[PF];
     int pf_cc = -1;
     // the bound the other column splits have found for this row, read with
     // each chunk's loads and used behind the next barrier (any older value is
@@ -513,15 +594,9 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
     auto fetch = [&](int64_t c0, int64_t cend) {
         if (SHARE && my_valid) pf_gU = __uint_as_float(a.gU[my_slot]);
         const bool in = c0 + tid < cend;
-        if constexpr (LOCAL) {
-            const float4* src = reinterpret_cast<const float4*>(a.xs + (c0 + (in ? tid : 0)) * DMAX);
+        const uint4* src = reinterpret_cast<const uint4*>(a.opC) + (c0 + (in ? tid : 0)) * PF;
 #pragma unroll
-            for (int q = 0; q < NQR; ++q) pfx[q] = src[q];
-        } else {
-            const uint4* src = reinterpret_cast<const uint4*>(a.opC) + (c0 + (in ? tid : 0)) * PF;
-#pragma unroll
-            for (int q = 0; q < PF; ++q) pf[q] = src[q];
-        }
+        for (int q = 0; q < PF; ++q) pf[q] = src[q];
         pf_cc = in ? a.compS[c0 + tid] : -1;
     };
     // registers -> LDS buffer b, in fragment order; columns this tile never
@@ -532,37 +607,7 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
         const bool col_ok = pf_cc >= 0 && c0 + tid >= cl && c0 + tid < ch &&
                             !(one_comp && pf_cc == lo_r);
         colcomp[b][tid] = col_ok ? pf_cc : -1;
-        if constexpr (LOCAL) {
-            float y[DMAX];
-#pragma unroll
-            for (int q = 0; q < DMAX / 4; ++q) {
-                const float4 v = q < NQR ? pfx[q < NQR ? q : 0] : make_float4(0.f, 0.f, 0.f, 0.f);
-                y[4 * q + 0] = v.x; y[4 * q + 1] = v.y; y[4 * q + 2] = v.z; y[4 * q + 3] = v.w;
-            }
-            uint4 rowop[4], colop[4];
-            PointConst cp;
-            local_operands<OP>(y, sh.cen, sigma, a.d, rowop, colop, cp);
-            float cQ = 0.f, cP = 0.f, cR = 0.f, cE = 0.f;
-            if (col_ok) {
-                cQ = cp.Q; cP = cp.P; cR = cp.rho; cE = cp.eta;
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) colop[q] = make_uint4(0, 0, 0, 0);
-                colop[3].z = LpFmt<OP>::inf_bits << 16;   // K slot 29 (times the row's 1)
-            }
-            uint4* cb4 = reinterpret_cast<uint4*>(&colbuf[b][0]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) cb4[((tid >> 4) * 4 + q) * 16 + (tid & 15)] = colop[q];
-            for (int off = 32; off > 0; off >>= 1) {
-                cQ = fmaxf(cQ, __shfl_xor(cQ, off));
-                cP = fmaxf(cP, __shfl_xor(cP, off));
-                cR = fmaxf(cR, __shfl_xor(cR, off));
-                cE = fmaxf(cE, __shfl_xor(cE, off));
-            }
-            if (lane == 0) {
-                cmax[b][wave][0] = cQ; cmax[b][wave][1] = cP; cmax[b][wave][2] = cR; cmax[b][wave][3] = cE;
-            }
-        } else if constexpr (Tr::BYTES == 64) {
+        if constexpr (Tr::BYTES == 64) {
             uint4* cb4 = reinterpret_cast<uint4*>(&colbuf[b][0]);
             if (__ballot(!col_ok) == 0ull) {               // the usual case: copies only
 #pragma unroll
@@ -573,7 +618,10 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
                     uint4 v = pf[q];
                     if (!col_ok) {
                         v = make_uint4(0, 0, 0, 0);
-                        if (q == 3) v.z = LpFmt<OP>::inf_bits << 16;   // K slot 29: t = +inf
+                        // K slot 29: t = +inf; LOCAL: the largest finite BF16
+                        // (the rows' low halves hold 0 there, and 0 x inf would
+                        // be NaN); the slow path drops such a column anyway
+                        if (q == 3) v.z = (LOCAL ? 0x7F7Fu : LpFmt<OP>::inf_bits) << 16;
                     }
                     cb4[((tid >> 4) * 4 + q) * 16 + (tid & 15)] = v;
                 }
@@ -593,26 +641,124 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
 
     // chunk [c0, cend) in LDS buffer b, components lo_c..hi_c; wneed: some
     // row of this wave passed its test for the chunk (else nothing to do)
-    auto process = [&](int b, int lo_c, int hi_c, int64_t c0, int64_t cend, bool wneed) {
+    // LOCAL: the wave's rows in the frame of super-chunk sc, centred at its
+    // ball centre c.  Lane l builds, for every row block rb, K slots 8g..8g+7
+    // (g = l / 16) of row rb * 16 + l % 16 -- its own B fragments -- for both
+    // halves of q = qh + ql: u = sigma (x - c) in FP32, qh = bf16(u),
+    // ql = bf16(u - qh) (the difference is exact in FP32, and qh + ql too).
+    // The high half carries the norm slots [n1 n2 n3 1 1 1] of ||q||^2, the
+    // low half zeros there.  The row's bound inputs go to rpc: Q = ||qh|| +
+    // ||ql|| (the two MFMAs' products sum to at most 2 Q Q* + P + P* in
+    // magnitude), P and rho as for any operand, and eta from
+    // |ql - (u - qh)| <= 2^-8 |u - qh| <= 2^-16 |u| per feature, plus the
+    // FP32 offset's rounding and BF16's subnormal floor.
+    auto split_rows = [&](int sc) {
+      if constexpr (LOCAL && OP == OP_BF16) {
+        const float4* c4 = reinterpret_cast<const float4*>(a.sballs + (int64_t)sc * BALL_STRIDE) + 2 * grp;
+        const float4 ca = c4[0], cb = c4[1];
+        const float cv[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+        const uint32_t one = f32_to_bf16_rn(1.0f);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const float4* x4 = reinterpret_cast<const float4*>(a.xs + (int64_t)rprb[rb] * DMAX) + 2 * grp;
+            const float4 xa = x4[0], xb = x4[1];
+            const float xv[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+            uint32_t hw[4], lw[4];
+            float nrm = 0.f, vn = 0.f, nh = 0.f, nl = 0.f;
+#pragma unroll
+            for (int f2 = 0; f2 < 4; ++f2) {
+                uint32_t hp = 0, lp = 0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int f = 2 * f2 + h, kf = 8 * grp + f;
+                    if (kf < DMAX_MFMA && kf < a.d) {
+                        const float u = (xv[f] - cv[f]) * sigma;
+                        const uint32_t qh = f32_to_bf16_rn(u);
+                        const float qhv = bf16_to_f32((uint16_t)qh);
+                        const uint32_t ql = f32_to_bf16_rn(u - qhv);
+                        const float qlv = bf16_to_f32((uint16_t)ql);
+                        const float q = qhv + qlv;
+                        nrm = __builtin_fmaf(q, q, nrm);
+                        vn = __builtin_fmaf(u, u, vn);
+                        nh = __builtin_fmaf(qhv, qhv, nh);
+                        nl = __builtin_fmaf(qlv, qlv, nl);
+                        hp |= qh << (16 * h);
+                        lp |= ql << (16 * h);
+                    }
+                }
+                hw[f2] = hp;
+                lw[f2] = lp;
+            }
+            // the row's sums: the four lanes' quarter sums (the same value in each)
+            nrm += __shfl_xor(nrm, 16);
+            vn += __shfl_xor(vn, 16);
+            nh += __shfl_xor(nh, 16);
+            nl += __shfl_xor(nl, 16);
+            nrm += __shfl_xor(nrm, 32);
+            vn += __shfl_xor(vn, 32);
+            nh += __shfl_xor(nh, 32);
+            nl += __shfl_xor(nl, 32);
+            // three-part split of ||q||^2; every residual is exact in FP32
+            float r = nrm, psum = 0.f;
+            uint32_t part[NORM_PARTS];
+#pragma unroll
+            for (int k3 = 0; k3 < NORM_PARTS; ++k3) {
+                part[k3] = f32_to_bf16_rn(r);
+                const float pv = bf16_to_f32((uint16_t)part[k3]);
+                psum += __builtin_fabsf(pv);
+                r -= pv;
+            }
+            if (grp == 3) {                                // slots 24..31: features 24, 25, norm slots
+                hw[1] = part[0] | (part[1] << 16);
+                hw[2] = part[2] | (one << 16);
+                hw[3] = one | (one << 16);
+            }
+            bfrag[rb] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            bfl[rb] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+            if (grp == 0) {
+                const double up = 1.0 + 0x1p-18;
+                const double sq = (double)__builtin_sqrtf(nh) + (double)__builtin_sqrtf(nl);
+                rpc[wave * RB * 16 + rb * 16 + lane] = make_float4(
+                    d2f_up(sq * up), d2f_up((double)psum * up),
+                    // (the FP32 sums of ||q||^2 and the rounding of qh + ql
+                    // where ql is subnormal: within 30 2^-24 of it)
+                    d2f_up(((double)__builtin_fabsf(r) + (double)nrm * 30.0 * 0x1p-24) * up),
+                    d2f_up(((0x1p-16 + 0x1p-22) * (double)__builtin_sqrtf(vn) * up +
+                            LpFmt<OP_BF16>::beta * __builtin_sqrt((double)a.d)) * up));
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const float4 m = rpc[tid];
+        mypc = PointConst{m.x, m.y, m.z, m.w};
+      }
+    };
+
+    // chunk [c0, cend) in LDS buffer b, components lo_c..hi_c, candidate slot
+    // `slot`; wneed: some row of this wave passed its test for the chunk
+    // (else nothing to do)
+    auto process = [&](int b, int lo_c, int hi_c, int64_t c0, int64_t cend, bool wneed, int slot) {
         if (!wneed) return;
         const int ncols = (int)(cend - c0);
         const bool pure = lo_c == hi_c;                    // the chunk is one component
-        // per-tile frame: this chunk's slack and threshold for the row (the
-        // wave's rows are read back by other lanes of the same wave only).
-        // In the global frame the slack is fixed and T follows U wherever U
-        // moves, so nothing is recomputed per chunk.
+        // super-chunk frames: the rows in this chunk's frame, and this
+        // chunk's slack and threshold for the row (the wave's rows are read
+        // back by other lanes of the same wave only).  In the global frame
+        // the slack is fixed and T follows U wherever U moves, so nothing is
+        // recomputed per chunk.
         if constexpr (LOCAL) {
-            float eps, eta;
-            {
-                const float colQ = fmaxf(fmaxf(cmax[b][0][0], cmax[b][1][0]), fmaxf(cmax[b][2][0], cmax[b][3][0]));
-                const float colP = fmaxf(fmaxf(cmax[b][0][1], cmax[b][1][1]), fmaxf(cmax[b][2][1], cmax[b][3][1]));
-                const float colR = fmaxf(fmaxf(cmax[b][0][2], cmax[b][1][2]), fmaxf(cmax[b][2][2], cmax[b][3][2]));
-                const float colE = fmaxf(fmaxf(cmax[b][0][3], cmax[b][1][3]), fmaxf(cmax[b][2][3], cmax[b][3][3]));
-                eps = (a.bc.gamma * (2.f * mypc.Q * colQ + mypc.P + colP) + mypc.rho + colR) * (1.f + 0x1p-20f);
-                eta = (mypc.eta + colE) * (1.f + 0x1p-22f);
-                rs[tid][0].z = eps;
-                rs[tid][0].w = eta;
+            const int fsc = gsc[slot / SUPER];
+            if (fsc != frame) {                            // wave-uniform
+                split_rows(fsc);
+                frame = fsc;
             }
+            const float4 cm = gcm[slot];                   // column maxima of Q, P, rho, eta
+            const float eps = (a.bc.gamma * (2.f * mypc.Q * cm.x + mypc.P + cm.y) + mypc.rho + cm.z) *
+                              (1.f + 0x1p-20f);
+            const float eta = (mypc.eta + cm.w) * (1.f + 0x1p-22f);
+            rs[tid][0].z = eps;
+            rs[tid][0].w = eta;
             rs[tid][0].x = my_valid ? thresh_from_U(rs[tid][0].y * s2, eps, eta, exact) : -__builtin_huge_valf();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -746,6 +892,12 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
             for (int rb = 0; rb < RB; ++rb) acc0[rb] = Tr::mma(af0, bfrag[rb]);
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc1[rb] = Tr::mma(af1, bfrag[rb]);
+            if constexpr (LOCAL) {                         // the rows' low halves
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) acc0[rb] = Tr::mma_acc(af0, bfl[rb], acc0[rb]);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) acc1[rb] = Tr::mma_acc(af1, bfl[rb], acc1[rb]);
+            }
             // all eight MFMAs issue back to back; the epilogue then finds the
             // first results ready instead of stalling after each pair
             __builtin_amdgcn_sched_barrier(0);
@@ -788,6 +940,10 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
             f32x4_t acc[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc[rb] = Tr::mma(af, bfrag[rb]);
+            if constexpr (LOCAL) {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) acc[rb] = Tr::mma_acc(af, bfl[rb], acc[rb]);
+            }
             bool hit = false;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
@@ -819,8 +975,14 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
         int scl[GS];
         const int g = gen.take(sh, a, lo_r, hi_r, umax, scl);
         if (g == 0) break;                                 // the same decision in every wave
+        float4 xg[LOCAL ? NQR : 1];                        // LOCAL: the row's coordinates for the tests
+        if constexpr (LOCAL) {
+            const float4* src = reinterpret_cast<const float4*>(a.xs + (int64_t)my_rp * DMAX);
+#pragma unroll
+            for (int q = 0; q < NQR; ++q) xg[q] = src[q];
+        }
         gen.expand(sh, a, lo_r, hi_r, umax, wave < g ? scl[wave < GS ? wave : 0] : -1, wave, gball, gpos,
-                   gneed);
+                   gneed, LOCAL ? gcm : nullptr, gsc);
         __syncthreads();                                   // candidates in LDS
         // candidates within reach of this wave's ball (one per lane), then
         // the rows' own tests for those
@@ -840,7 +1002,10 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
             // a row skips a chunk made only of its own component, or whose
             // ball lies farther than its bound
             bool need = my_valid && !(gp.z == gp.w && gp.z == my_comp);
-            if (a.prune && need) need = point_ball_reach(xq, &gball[slot][0], reach);
+            if (a.prune && need) {
+                if constexpr (LOCAL) need = point_ball_reach(xg, &gball[slot][0], reach);
+                else need = point_ball_reach(xq, &gball[slot][0], reach);
+            }
             if (__ballot(need) != 0ull && lane == 0) atomicOr(&gneed[slot], 1 << wave);
         }
         __syncthreads();                                   // every wave's needs in LDS
@@ -871,7 +1036,7 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
                 nmask &= nmask - 1ull;
                 fetch(gpos[nxt].x, gpos[nxt].y);           // in flight while cur is processed
             }
-            process(buf, cp.z, cp.w, cp.x, cp.y, wn);
+            process(buf, cp.z, cp.w, cp.x, cp.y, wn, cur);
             cur = nxt;
             buf ^= 1;
         }
@@ -932,6 +1097,22 @@ void launch_one(const CandArgs& a, dim3 grid, size_t, hipStream_t s)
 
 }  // namespace
 
+hipError_t launch_split_columns(const float* xs, int64_t np, int d, float sigma, const int32_t* cstart,
+                                const int32_t* csup, const int32_t* tabn, int64_t nch_bound,
+                                const float* sballs, void* opC, float4* cmax, hipStream_t s)
+{
+    if (np <= 0) return hipSuccess;
+    if (cstart) {
+        k_split_columns<true><<<(unsigned)nch_bound, 256, 0, s>>>(xs, np, d, sigma, cstart, csup, tabn, sballs,
+                                                                  (uint4*)opC, cmax);
+    } else {
+        const unsigned nc = (unsigned)((np + CHUNK - 1) / CHUNK);
+        k_split_columns<false><<<nc, 256, 0, s>>>(xs, np, d, sigma, nullptr, nullptr, nullptr, sballs,
+                                                  (uint4*)opC, cmax);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s)
 {
     if (a.desc && a.cstart) return hipErrorInvalidValue;   // device-sized launches use fixed chunks
@@ -946,8 +1127,8 @@ hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s)
         else launch_one<OP_BF16, false>(a, grid, shm, s);
         break;
     case OP_FP16:
-        if (local) launch_one<OP_FP16, true>(a, grid, shm, s);
-        else launch_one<OP_FP16, false>(a, grid, shm, s);
+        if (local) return hipErrorInvalidValue;   // super-chunk frames are a BF16 format
+        launch_one<OP_FP16, false>(a, grid, shm, s);
         break;
     case OP_FP8:
         if (local) return hipErrorInvalidValue;   // FP8 is used on exact integer data only

@@ -70,7 +70,7 @@ struct Plan {
     int S_global = 256;             // survivor cap of the global frame
     int L1 = 1, L2 = 1;             // fine / coarse landmarks of the spatial order
     int ninst = 1;                  // instances in the point set (batched calls)
-    bool local = false;             // BF16 operands built per tile from FP32 (not exact data)
+    bool local = false;             // BF16 in the super-chunk frames (not exact data)
     bool keep_e = false;            // workspace holds t + E(t) per survivor (BF16 asked for)
     int metric = NNM_METRIC_EUCLIDEAN;  // nnm_metric asked for
     // the metric of the keys the kernels compute: the cosine metric runs as
@@ -97,6 +97,7 @@ struct WS {
     int32_t* perm0; int32_t* rank0; int32_t* ckey; int32_t* flag; int32_t* excl;
     float* balls;
     float* sballs;
+    float4* cmaxT;                  // BF16 super-chunk frames: per-chunk column maxima
     ChunkTabs tabs;
     uint32_t* gT; uint32_t* gU;
     uint32_t* tfin;
@@ -176,6 +177,7 @@ size_t carve(const Plan& p, void* base, WS* w)
     const size_t nsc_max = (n + CHUNK * SUPER - 1) / (CHUNK * SUPER) + nseg_max;
     w->balls = c.take<float>(nch_max * BALL_STRIDE);
     w->sballs = c.take<float>(nsc_max * BALL_STRIDE);
+    w->cmaxT = c.take<float4>(nch_max);
     w->tabs.segstart = c.take<int32_t>(nseg_max + 1);
     w->tabs.ccnt = c.take<int32_t>(nseg_max);
     w->tabs.scnt = c.take<int32_t>(nseg_max);
@@ -374,10 +376,11 @@ nnm_status stage(Run& R, const float* X)
     }
     p.exact = (p.opkind != OP_FP32 && intgrid) ? 1 : 0;
     // BF16 keeps 8 bits: relative to the data's centre its error would swamp
-    // nearest-neighbour distances, so its operands are built per tile
+    // nearest-neighbour distances, so it works in the frames of the column
+    // super-chunks, with the rows split into two BF16 halves
     p.local = p.opkind == OP_BF16 && !p.exact;
     // BF16 on an integer grid is exact in the global frame: the global cap
-    // (the buffers were sized for the larger per-tile one)
+    // (the buffers were sized for the larger BF16 one)
     if (!p.local) p.S = p.S_global;
     p.op_bytes = (p.opkind == OP_FP8) ? 32 : 64;
     R.bc = BoundConst{};
@@ -432,7 +435,9 @@ nnm_status stage(Run& R, const float* X)
         R.bc.colRho = cm[2];
         R.bc.colEta = cm[3];
     }
-    R.bc.gamma = p.exact ? 0.f : (float)(33.0 * 0x1p-23);
+    // FP32 accumulation of 32 exact products (one MFMA), or of 64 in two
+    // chained MFMAs (the split rows): any order, even truncating
+    R.bc.gamma = p.exact ? 0.f : (float)((p.local ? 67.0 : 33.0) * 0x1p-23);
     R.bc.sigma2 = sigma * sigma;
     R.bc.exact = p.exact;
     return NNM_OK;
@@ -489,6 +494,12 @@ nnm_status sort_points(Run& R, const float* X, int64_t ncomp)
     } else {
         HIP_TRY(launch_chunk_balls(w.xs, p.n, CHUNK, w.balls, R.s));
         HIP_TRY(launch_chunk_balls(w.xs, p.n, CHUNK * SUPER, w.sballs, R.s));
+    }
+    // BF16: the column operands in the frames of this order's super-chunks
+    if (p.local) {
+        const int64_t nch_bound = R.aligned ? (p.n + CHUNK - 1) / CHUNK + ncomp : 0;
+        HIP_TRY(launch_split_columns(w.xs, p.n, p.d, R.sigma, R.aligned ? w.tabs.cstart : nullptr,
+                                     w.tabs.csup, w.tabs.tabn, nch_bound, w.sballs, w.opCs, w.cmaxT, R.s));
     }
     return NNM_OK;
 }
@@ -574,6 +585,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     a.perm = w.perm;
     a.balls = w.balls;
     a.sballs = w.sballs;
+    a.cmaxT = w.cmaxT;
     if (R.aligned) {
         a.cstart = w.tabs.cstart;
         a.csup = w.tabs.csup;
@@ -794,6 +806,7 @@ nnm_status scan_batch_dev(Run& R, const float* X, const int32_t* rows, const int
     a.perm = w.perm;
     a.balls = w.balls;
     a.sballs = w.sballs;
+    a.cmaxT = w.cmaxT;
     a.prune = R.o.disable_prune ? 0 : 1;
     a.local = (p.local && !use32) ? 1 : 0;
     a.share = 1;

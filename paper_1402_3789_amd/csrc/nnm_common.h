@@ -277,7 +277,9 @@ struct CandArgs {
     const int32_t* ccomp;     // [chunks] the component of each chunk (each holds one)
     const int32_t* scomp;     // [super-chunks] and of each super-chunk
     int32_t prune;
-    int32_t local;            // BF16/FP16: operands built per tile from xs
+    int32_t local;            // BF16 on general data: super-chunk frames (opC from
+                              // launch_split_columns, rows split in-kernel from xs)
+    const float4* cmaxT;      // [chunks] LOCAL: maxima of the columns' (Q, P, rho, eta)
     // thresholds shared by the column splits of one row (float bits)
     int32_t share;
     uint32_t* gT;             // [n_rows] candidate-domain threshold
@@ -290,6 +292,13 @@ struct CandArgs {
 };
 
 hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s);
+// BF16 column operands in the frame of each column's super-chunk (centre:
+// the super-chunk's ball centre) and each chunk's maxima of their bound
+// inputs; cstart/csup/tabn: the component-aligned tables (NULL: fixed
+// chunks), nch_bound: at least their chunk count.
+hipError_t launch_split_columns(const float* xs, int64_t np, int d, float sigma, const int32_t* cstart,
+                                const int32_t* csup, const int32_t* tabn, int64_t nch_bound,
+                                const float* sballs, void* opC, float4* cmax, hipStream_t s);
 hipError_t launch_cand_fp32(const CandArgs& a, hipStream_t s);
 
 // FP64 rescoring of survivors into exact top-k lists.
