@@ -116,7 +116,7 @@ typedef struct {
 /* Run options.  Zero-initialised options mean "defaults". */
 typedef struct {
     int32_t precision;      /* nnm_precision (0 = FP32; use AUTO for auto)   */
-    int32_t knn_k;          /* cache depth, 1..32 (0: 6; FP32 and BF16: 8)    */
+    int32_t knn_k;          /* cache depth, 1..32 (0: 6; FP32: 8)             */
     int32_t survivor_cap;   /* candidates kept per row, 16..2048 (0 = auto)   */
     int32_t disable_prune;  /* 1: rescan every exhausted row (debug)          */
     int32_t force_fallback; /* 1: rescore every row by a full FP64 scan       */

@@ -77,7 +77,7 @@ __device__ __forceinline__ double fp32_upper_from_t(double t, double crel, doubl
 enum BoundMode : int {
     BOUND_FP32 = 0,     // FP32 direct differences: fp32_upper_from_t(t) - t
     BOUND_GLOBAL = 1,   // matrix cores, global frame: from the row's PointConst
-    BOUND_LOCAL = 2,    // matrix cores, per-tile frame: t + E(t) stored per survivor
+    BOUND_LOCAL = 2,    // matrix cores, super-chunk frames: t + E(t) stored per survivor
     BOUND_EXACT = 3     // exact integer data: E = 0
 };
 

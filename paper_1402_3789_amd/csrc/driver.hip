@@ -136,7 +136,7 @@ size_t carve(const Plan& p, void* base, WS* w)
     w->opRs = mfma ? c.take<char>(n * p.op_bytes) : nullptr;
     w->opCs = mfma ? c.take<char>(n * p.op_bytes) : nullptr;
     w->pcs = c.take<PointConst>(n);
-    w->xs = c.take<float>(n * DMAX);   // also the source of the per-tile BF16/FP16 operands
+    w->xs = c.take<float>(n * DMAX);   // also the source of the BF16 super-chunk operands
     w->compS = c.take<int32_t>(n);
     w->perm = c.take<int32_t>(n);
     w->comp = c.take<int32_t>(n);
@@ -239,17 +239,17 @@ nnm_status plan_common(int64_t n, int32_t d, int32_t k, const nnm_options* opt, 
     // settled after the data have been inspected
     p->opkind = (o.precision == NNM_PREC_FP32 || vec_only) ? OP_FP32 : OP_FP16;
     if (o.precision == NNM_PREC_AUTO && d > DMAX_MFMA) p->opkind = OP_FP32;
-    // cache depth: the global-frame matrix-core paths' survivor band grows
-    // with k, so they keep fewer neighbours than the FP32 and the per-tile
-    // BF16 paths (measured best on the 2M workload: 6, and 8)
-    const bool deep = p->opkind == OP_FP32 || o.precision == NNM_PREC_BF16;
+    // cache depth: the matrix-core paths' survivor band grows with k, so
+    // they keep fewer neighbours than the FP32 path (measured best on the 2M
+    // workload: 6, and 8)
+    const bool deep = p->opkind == OP_FP32;
     p->k = k > 0 ? k : (o.knn_k > 0 ? o.knn_k : (deep ? 8 : 6));
     if (p->k < 1 || p->k > KMAX) return NNM_EINVAL;
     if (o.precision != NNM_PREC_FP32 && o.precision != NNM_PREC_AUTO && d > DMAX_MFMA)
         return NNM_EUNSUPPORTED;
     p->op_bytes = 64;
-    // the per-tile frame (BF16 on data that is not an integer grid) keeps
-    // the bound it applied to each survivor for the error report
+    // the super-chunk frames (BF16 on data that is not an integer grid)
+    // keep the bound they applied to each survivor for the error report
     p->keep_e = o.precision == NNM_PREC_BF16;
     int S = o.survivor_cap;
     if (S <= 0) {
@@ -260,9 +260,10 @@ nnm_status plan_common(int64_t n, int32_t d, int32_t k, const nnm_options* opt, 
     if (S > SMAX) S = SMAX;
     S = pow2_at_least(S);
     p->S_global = S;
-    // BF16 on data that is not an integer grid builds its operands per tile
-    // (see stage); its margin is wider, so it keeps 4x the survivors per row
-    if (o.precision == NNM_PREC_BF16 && o.survivor_cap <= 0) S = S * 4 < SMAX ? S * 4 : SMAX;
+    // BF16 on data that is not an integer grid works in the super-chunk
+    // frames (see stage); its margin is wider, so it keeps 2x the survivors
+    // per row (measured best on the 2M workload)
+    if (o.precision == NNM_PREC_BF16 && o.survivor_cap <= 0) S = S * 2 < SMAX ? S * 2 : SMAX;
     p->S = S;
     // survivor buffers of at most 2^30 entries (8 GB; 12 GB with the BF16
     // bounds): 4M rows at S = 256 in one launch (a split launch pays two
@@ -480,7 +481,7 @@ nnm_status sort_points(Run& R, const float* X, int64_t ncomp)
     WS& w = R.w;
     HIP_TRY(launch_component_order(w.comp, w.perm0, w.rank0, p.n, w.ckey, w.srtA, w.srtB, w.perm,
                                    w.compS, w.flag, w.excl, w.radix_temp, w.scan_temp, R.s));
-    // the sorted FP32 copy (tile balls; the per-tile frame's operands) ...
+    // the sorted FP32 copy (tile balls; the BF16 super-chunk operands) ...
     HIP_TRY(launch_gather_points(p.n, OP_FP32, w.perm, w.opR, w.opC, w.pc, X, p.d, p.ld, w.comp,
                                  w.opRs, w.opCs, w.pcs, w.xs, w.compS, R.s));
     // ... and the precomputed operands where one global frame is used
@@ -600,7 +601,7 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     a.local = (p.local && !use32) ? 1 : 0;
     a.share = a.col_splits > 1 ? 1 : 0;
     a.gT = w.gT;
-    // final thresholds: one frame for every pair (not the per-tile frame)
+    // final thresholds: one frame for every pair (not the super-chunk frames)
     const bool use_tfin = !use32 && !p.local;
     a.tfin = use_tfin ? w.tfin : nullptr;
     if (use_tfin) HIP_TRY(launch_fill_i32((int32_t*)w.tfin, 0x7F800000, nb, R.s));

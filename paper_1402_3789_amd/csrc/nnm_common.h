@@ -255,7 +255,7 @@ struct CandArgs {
     int32_t* surv_cnt;        // [n_rows]
     int32_t* surv_j;          // [n_rows][S] sorted column positions
     float* surv_t;            // [n_rows][S] candidate values
-    float* surv_e;            // [n_rows][S] per-tile frame only: t + E(t) as applied
+    float* surv_e;            // [n_rows][S] super-chunk frames only: t + E(t) as applied
     unsigned long long* pairs;// [NSPREAD * SPREAD_STRIDE] count of evaluated pairs
     // chunk pruning and near-first order
     const float* X;           // original features (row-tile balls)
