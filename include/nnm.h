@@ -375,6 +375,33 @@ nnm_status cluster_cut(const nnm_edge *edges_host, int64_t n,
                        int64_t *n_clusters);
 
 /*
+ * The same cut on the device, for settings without size caps or priority
+ * (KL2 < 0, KL3 < 0, KL4 <= 1).  Only KL1 ("Problem settings") and the
+ * distance threshold ("Problem statement") can then stop a union, and since
+ * w never decreases along the key order the admissible tree edges (those
+ * with w <= dmax, i.e. not w > dmax) form a prefix: the clusters are the
+ * components of the forest of the first m = min(prefix, n - KL1) edges
+ * (KL1 <= 0: the whole prefix), found by a concurrent union-find on the GPU;
+ * labels and K are those cluster_cut returns for the same edges.  The
+ * tree's edges stay in device memory (as mst_build leaves them).
+ *   edges_dev   [n-1] nnm_edge, device, sorted by key;
+ *   ws_dev      at least cluster_cut_device_workspace_size(n) bytes
+ *               (about 12 n bytes);
+ *   labels_dev  [n] int32, device output: as cluster_cut's labels_host;
+ *   n_clusters  host output: K;
+ *   stream      as for mst_build; returns once the labels are complete.
+ * Errors: NNM_EUNSUPPORTED when KL2, KL3 or KL4 is on (cluster_cut applies
+ * those); NNM_EINVAL as for cluster_cut (n < 1 or above INT32_MAX, a null
+ * pointer, a short workspace, malformed or unsorted edges, or a cycle among
+ * the edges the cut takes); NNM_EDEVICE when a HIP call fails.
+ */
+nnm_status cluster_cut_device_workspace_size(int64_t n, size_t *bytes);
+nnm_status cluster_cut_device(const nnm_edge *edges_dev, int64_t n,
+                              const nnm_cut_params *params, void *ws_dev,
+                              size_t ws_bytes, int32_t *labels_dev,
+                              int64_t *n_clusters, void *stream);
+
+/*
  * The clustering process itself under the settings, over all pairs of
  * points: the section "General description of the algorithm for
  * constructing the set of minimum distances" unites, step by step, the two

@@ -20,7 +20,7 @@ from . import _native as N
 from ._native import NNMError, NativeMissing, PREC  # noqa: F401
 
 __all__ = ["mst_build", "mst_build_noalloc", "mst_build_pminimal", "knn_build", "cluster_cut",
-           "cluster_cut_allpairs",
+           "cluster_cut_device", "cluster_cut_allpairs",
            "mst_build_batched", "Tree",
            "options", "autotune", "NNMError", "NativeMissing"]
 
@@ -320,6 +320,31 @@ def cluster_cut(tree, n=None, kl1=0, kl2=-1, kl3=-1, kl4=0, dmax=math.inf):
                                ctypes.c_void_p(labels.ctypes.data), ctypes.byref(k))
     N.check("cluster_cut", code)
     return labels[:n], int(k.value)
+
+
+def cluster_cut_device(tree, kl1=0, dmax=math.inf, stream=None, workspace=None, host=True):
+    """The cut of mst_build's tree on the device, for settings without size
+    caps or priority (only kl1 and dmax): (labels int32 [n], K), the same as
+    cluster_cut.  The edges stay on the device; with host=True the labels
+    come back as a numpy array, else as a CUDA tensor."""
+    torch = _torch()
+    if not isinstance(tree, Tree) or not tree.raw.is_cuda:
+        raise TypeError("cluster_cut_device takes a Tree in device memory")
+    n = tree.n
+    L = N.lib()
+    nb = ctypes.c_size_t(0)
+    N.check("cluster_cut_device_workspace_size", L.cluster_cut_device_workspace_size(n, ctypes.byref(nb)))
+    dev = tree.raw.device
+    ws = (workspace or _WS).get(nb.value, dev)
+    labels = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    p = N.CutParams(int(kl1), -1, -1, 0, float(dmax))
+    k = ctypes.c_int64(0)
+    code = L.cluster_cut_device(ctypes.c_void_p(tree.raw.data_ptr() if n > 1 else None), n,
+                                ctypes.byref(p), ctypes.c_void_p(ws.data_ptr()), nb.value,
+                                ctypes.c_void_p(labels.data_ptr()), ctypes.byref(k), _stream(stream))
+    N.check("cluster_cut_device", code)
+    labels = labels[:n]
+    return (labels.cpu().numpy() if host else labels), int(k.value)
 
 
 def cluster_cut_allpairs(X, tree=None, kl1=0, kl2=-1, kl3=-1, kl4=0, dmax=math.inf, k=0,

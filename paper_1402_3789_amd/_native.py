@@ -135,6 +135,11 @@ _SIG = {
                                             ctypes.c_void_p]),
     "cluster_cut": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(CutParams),
                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "cluster_cut_device_workspace_size": (ctypes.c_int, [ctypes.c_int64,
+                                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "cluster_cut_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(CutParams),
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
 }
 
 _lib = None

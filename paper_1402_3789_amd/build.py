@@ -15,7 +15,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = [
     "stage.hip", "cand_mfma.hip", "cand_fp32.hip", "rescore.hip", "merge.hip",
-    "sort_scan.hip", "spatial.hip", "driver.hip", "allpairs.hip", "capi.cpp", "cut.cpp",
+    "sort_scan.hip", "spatial.hip", "driver.hip", "allpairs.hip", "cut_dev.hip", "capi.cpp", "cut.cpp",
     "autotune.cpp",
 ]
 

@@ -351,3 +351,27 @@ def test_pminimal_rejects_bad_arguments_before_device_work():
                                     ctypes.byref(o), ctypes.c_void_p(a["ws"]), a["wsb"],
                                     ctypes.c_void_p(a["e"]), None, ctypes.byref(rep))
         assert code == N.NNM_EINVAL, b
+
+
+def test_cut_device_argument_checks():
+    """Refusals that happen before any device work (no GPU needed)."""
+    L = N.lib()
+    nb = ctypes.c_size_t(0)
+    assert L.cluster_cut_device_workspace_size(0, ctypes.byref(nb)) == N.NNM_EINVAL
+    assert L.cluster_cut_device_workspace_size(1 << 31, ctypes.byref(nb)) == N.NNM_EINVAL
+    assert L.cluster_cut_device_workspace_size(1000, None) == N.NNM_EINVAL
+    assert L.cluster_cut_device_workspace_size(1000, ctypes.byref(nb)) == 0 and nb.value >= 12 * 1000
+    fake = ctypes.c_void_p(0x1000)                  # never dereferenced on these paths
+    k = ctypes.c_int64(0)
+    p = N.CutParams(3, -1, -1, 0, float("inf"))
+    call = lambda n, e, prm, ws, wsb, lab, kk: L.cluster_cut_device(e, n, prm, ws, wsb, lab, kk, None)
+    assert call(0, fake, ctypes.byref(p), fake, nb.value, fake, ctypes.byref(k)) == N.NNM_EINVAL
+    assert call(1000, None, ctypes.byref(p), fake, nb.value, fake, ctypes.byref(k)) == N.NNM_EINVAL
+    assert call(1000, fake, None, fake, nb.value, fake, ctypes.byref(k)) == N.NNM_EINVAL
+    assert call(1000, fake, ctypes.byref(p), None, nb.value, fake, ctypes.byref(k)) == N.NNM_EINVAL
+    assert call(1000, fake, ctypes.byref(p), fake, nb.value, None, ctypes.byref(k)) == N.NNM_EINVAL
+    assert call(1000, fake, ctypes.byref(p), fake, nb.value, fake, None) == N.NNM_EINVAL
+    assert call(1000, fake, ctypes.byref(p), fake, nb.value - 1, fake, ctypes.byref(k)) == N.NNM_EINVAL
+    for caps in [(3, 10, -1, 0), (3, -1, 50, 0), (3, -1, -1, 5)]:
+        q = N.CutParams(*caps, float("inf"))
+        assert call(1000, fake, ctypes.byref(q), fake, nb.value, fake, ctypes.byref(k)) == N.NNM_EUNSUPPORTED

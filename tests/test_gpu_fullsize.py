@@ -23,6 +23,7 @@ oracle cannot build the whole tree, so these tests check:
     smallest pair between A and the rest (oracle, |A| rows) is that edge.
 """
 import hashlib
+import math
 import json
 import os
 
@@ -152,10 +153,10 @@ def _bound_report_ok(rep):
         assert rep["max_abs_err"] == 0.0 and rep["max_bound"] == 0.0
 
 
-def _against_digest(nnm, X, want, precision):
+def _against_digest(nnm, X, want, precision, **kw):
     assert W.sha256(X) == want["x_sha256"]
     n = X.shape[0]
-    tree = nnm.mst_build(torch.from_numpy(X).to("cuda:0"), precision=precision)
+    tree = nnm.mst_build(torch.from_numpy(X).to("cuda:0"), precision=precision, **kw)
     torch.cuda.synchronize()
     rep = tree.report
     _say("tree built", precision, rep["rounds"], "rounds; max |t-s|", rep["max_abs_err"],
@@ -167,16 +168,25 @@ def _against_digest(nnm, X, want, precision):
         assert k == c["clusters"], (precision, kw, k)
         got = hashlib.sha256(np.ascontiguousarray(labels, "<i4").tobytes()).hexdigest()
         assert got == c["labels_sha256"], (precision, kw)
+        if kw.get("kl2", -1) < 0 and kw.get("kl3", -1) < 0 and kw.get("kl4", 0) <= 1:
+            dl, dk = nnm.cluster_cut_device(tree, kl1=kw.get("kl1", 0), dmax=kw.get("dmax", math.inf))
+            assert dk == c["clusters"], ("device cut", precision, kw, dk)
+            got = hashlib.sha256(np.ascontiguousarray(dl, "<i4").tobytes()).hexdigest()
+            assert got == c["labels_sha256"], ("device cut", precision, kw)
     _bound_report_ok(rep)
     _say(precision, "tree and", len(want["cuts"]), "cuts identical to the oracle")
     return tree
 
 
-@pytest.mark.parametrize("prec", ["fp16", "bf16", "fp32"])
+@pytest.mark.parametrize("prec", ["fp16", "bf16", "fp32", "bf16-cap2048"])
 def test_aniso500_full_size_oracle_digest(nnm, aniso, prec):
+    """bf16-cap2048: the largest survivor cap holds 2^30 / 2048 = 524,288
+    rows per candidate launch, so every full pass runs the row loop over
+    four launches."""
     want = _digest_file("aniso500")
     _say("aniso500 full vs oracle digest", prec)
-    _against_digest(nnm, aniso, want, prec)
+    kw = {"survivor_cap": 2048} if prec == "bf16-cap2048" else {}
+    _against_digest(nnm, aniso, want, prec.split("-")[0], **kw)
 
 
 @pytest.mark.parametrize("prec", ["fp8", "auto", "bf16"])

@@ -56,7 +56,7 @@ def test_boundary_and_oracle_pins_under_asan_ubsan(tmp_path):
     build = os.path.join(ROOT, "paper_1402_3789_amd", "_build")
     gpu_objs = [os.path.join(build, f + ".o") for f in
                 ("stage", "cand_mfma", "cand_fp32", "rescore", "merge", "sort_scan", "spatial",
-                 "driver", "allpairs", "autotune")]
+                 "driver", "allpairs", "cut_dev", "autotune")]
     if not all(os.path.exists(o) for o in gpu_objs):
         pytest.skip("GPU objects not built (paper_1402_3789_amd/build.py)")
     if shutil.which("g++") is None:
