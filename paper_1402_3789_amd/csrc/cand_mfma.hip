@@ -1043,9 +1043,13 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
     }
     if (!SHARE && my_valid) a.surv_cnt[my_slot] = __float_as_int(rs[tid][1].x);
     // the row's final threshold (one frame for every pair): a survivor above
-    // it has key > U >= the row's k-th key, so rescoring may drop it
-    if (!LOCAL && a.tfin && my_valid)
-        atomicMin(&a.tfin[my_slot], __float_as_uint(fmaxf(rs[tid][0].x, 0.f)));
+    // it has key > U >= the row's k-th key, so rescoring may drop it.  LOCAL
+    // (the frame changes per chunk): the final bound U itself, in data units;
+    // rescoring drops a survivor whose key is provably above it
+    if (a.tfin && my_valid) {
+        if constexpr (LOCAL) atomicMin(&a.tfin[my_slot], __float_as_uint(rs[tid][0].y));
+        else atomicMin(&a.tfin[my_slot], __float_as_uint(fmaxf(rs[tid][0].x, 0.f)));
+    }
     const int wrows = sh.rows - wave * 64;
     if (lane == 0 && a.pairs && wrows > 0)
         atomicAdd(&a.pairs[((blockIdx.x * 4 + wave) & (NSPREAD - 1)) * SPREAD_STRIDE],

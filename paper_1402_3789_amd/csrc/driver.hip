@@ -601,8 +601,8 @@ nnm_status scan_batch(Run& R, const float* X, const int32_t* rows, int32_t row0,
     a.local = (p.local && !use32) ? 1 : 0;
     a.share = a.col_splits > 1 ? 1 : 0;
     a.gT = w.gT;
-    // final thresholds: one frame for every pair (not the super-chunk frames)
-    const bool use_tfin = !use32 && !p.local;
+    // final thresholds (global frame) or final key bounds (super-chunk frames)
+    const bool use_tfin = !use32;
     a.tfin = use_tfin ? w.tfin : nullptr;
     if (use_tfin) HIP_TRY(launch_fill_i32((int32_t*)w.tfin, 0x7F800000, nb, R.s));
     a.gU = w.gU;
@@ -766,7 +766,7 @@ nnm_status scan_batch_dev(Run& R, const float* X, const int32_t* rows, const int
     const int32_t cap = (int32_t)p.rmax;
     const int32_t target = u0 ? (R.o.split_target > 0 ? R.o.split_target : 8192)
                               : (R.o.split_target0 > 0 ? R.o.split_target0 : 4096);
-    const bool use_tfin = !use32 && !p.local;
+    const bool use_tfin = !use32;
     HIP_TRY(launch_prep_launch(D, count, off, cap, p.n, target, R.o.col_splits, w.surv_cnt,
                                use_tfin ? w.tfin : nullptr, w.gT, w.gU, R.s));
     const int32_t* lrows = rows + off;

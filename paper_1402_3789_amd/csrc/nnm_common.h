@@ -284,7 +284,8 @@ struct CandArgs {
     int32_t share;
     uint32_t* gT;             // [n_rows] candidate-domain threshold
     uint32_t* tfin;           // [n_rows] or NULL: each row's final threshold (FP32
-                              // bits, clamped at 0; min over column splits)
+                              // bits, clamped at 0; min over column splits); LOCAL:
+                              // its final bound U on the k-th key (data units)
     uint32_t* gU;             // [n_rows] bound on the key of the k-th neighbour
     // device-sized launch (NULL: n_rows, n_tiles and col_splits above)
     LaunchDesc* desc;
@@ -315,6 +316,7 @@ struct RescoreArgs {
     int32_t row0;
     const int32_t* perm;      // sorted position -> point
     const uint32_t* tfin;     // NULL or the candidate pass's final threshold per row
+                              // (super-chunk frames: its final bound on the k-th key)
     const int32_t* comp;      // component of each point
     const int32_t* surv_cnt;
     const int32_t* surv_j;

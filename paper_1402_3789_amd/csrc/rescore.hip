@@ -48,8 +48,11 @@ __device__ __forceinline__ void rescore_row(const RescoreArgs& a, int64_t slot, 
     const float* xi = a.xs + (int64_t)rp * DMAX;
     // survivors above the row's final threshold cannot be among its k
     // nearest (their key exceeds the final bound U); an overflowed row keeps
-    // all of its first S for the bound it passes on
+    // all of its first S for the bound it passes on.  Super-chunk frames:
+    // tfin is U itself (data units) and a survivor goes when its key's lower
+    // bound t - E(t) >= 2t - (t + E(t) as stored), scaled, exceeds it
     const float tf = (a.tfin && !over) ? __uint_as_float(a.tfin[slot]) : __builtin_huge_valf();
+    const bool key_bound = a.bound_mode == BOUND_LOCAL;
     double sv[E];
     int jv[E];
     double emax = 0.0, rmax = 0.0, bmax = 0.0, qmax = 0.0;
@@ -68,7 +71,10 @@ __device__ __forceinline__ void rescore_row(const RescoreArgs& a, int64_t slot, 
         jv[e] = 0x7FFFFFFF;
         const int idx = e * 64 + lane;
         const float tv = idx < m ? a.surv_t[slot * a.S + idx] : 0.f;
-        if (idx < m && !(tv > tf)) {
+        const float te = (idx < m && key_bound) ? a.surv_e[slot * a.S + idx] : 0.f;
+        const bool drop = key_bound ? ((double)tv - ((double)te - (double)tv)) * a.inv_sigma2 > (double)tf
+                                    : tv > tf;
+        if (idx < m && !drop) {
             const int jp = a.surv_j[slot * a.S + idx];
             const int j = a.perm[jp];
             const double s = metric_key_rows(a.metric, xi, a.xs + (int64_t)jp * DMAX, a.d);
@@ -86,7 +92,7 @@ __device__ __forceinline__ void rescore_row(const RescoreArgs& a, int64_t slot, 
             else if (a.bound_mode == BOUND_GLOBAL)
                 eb = ((double)upper_from_t(tv, eps_r, eta_r, 0) - (double)tv) * a.inv_sigma2;
             else if (a.bound_mode == BOUND_LOCAL)
-                eb = ((double)a.surv_e[slot * a.S + idx] - (double)tv) * a.inv_sigma2;
+                eb = ((double)te - (double)tv) * a.inv_sigma2;
             bmax = eb > bmax ? eb : bmax;
             const double q = err > 0.0 ? (eb > 0.0 ? err / eb : __builtin_huge_val()) : 0.0;
             qmax = q > qmax ? q : qmax;
