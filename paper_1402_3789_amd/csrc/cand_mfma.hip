@@ -359,7 +359,7 @@ __device__ __forceinline__ void local_operands(const float* x, const float* c, f
 // ball centre) to opC, and the maxima of their bound inputs (Q, P, rho, eta)
 // to cmax[ci].  TAB: component-aligned tables; workgroups past the chunk
 // count exit.
-template <bool TAB>
+template <bool TAB, int OP>
 __global__ __launch_bounds__(256) void k_split_columns(const float* __restrict__ xs, int64_t np, int d,
                                                        float sigma, const int32_t* __restrict__ cstart,
                                                        const int32_t* __restrict__ csup,
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256) void k_split_columns(const float* __restrict__
         }
         uint4 row[4], col[4];
         PointConst pc;
-        local_operands<OP_BF16>(y, sballs + (int64_t)sc * BALL_STRIDE, sigma, d, row, col, pc);
+        local_operands<OP>(y, sballs + (int64_t)sc * BALL_STRIDE, sigma, d, row, col, pc);
 #pragma unroll
         for (int q = 0; q < 4; ++q) opC[p * 4 + q] = col[q];
         m = make_float4(pc.Q, pc.P, pc.rho, pc.eta);
@@ -556,7 +556,9 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
     __syncthreads();                                       // the tile's shared fields are written
     // row fragments stay in registers for the whole sweep (LOCAL: both
     // halves, rebuilt per super-chunk frame from the rows' positions)
-    frag_t bfrag[RB], bfl[LOCAL ? RB : 1];
+    // SPLIT: BF16 in the super-chunk frames keeps its rows as two halves
+    constexpr bool SPLIT = LOCAL && OP == OP_BF16;
+    frag_t bfrag[RB], bfl[SPLIT ? RB : 1];
     int32_t rprb[LOCAL ? RB : 1];
     int32_t rcomp[RB];
     uint32_t rvmask = 0;                                   // hit bits of valid rows
@@ -568,7 +570,7 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
         const int rp = ok ? (a.rows ? a.rows[slot] : a.row0 + (int)slot) : 0;
         if constexpr (LOCAL) {
             bfrag[rb] = frag_t{};
-            bfl[rb] = frag_t{};
+            if constexpr (SPLIT) bfl[rb] = frag_t{};
             rprb[rb] = rp;
         } else {
             bfrag[rb] = reinterpret_cast<const frag_t*>(a.opR)[(int64_t)rp * 4 + grp];
@@ -621,7 +623,7 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
                         // K slot 29: t = +inf; LOCAL: the largest finite BF16
                         // (the rows' low halves hold 0 there, and 0 x inf would
                         // be NaN); the slow path drops such a column anyway
-                        if (q == 3) v.z = (LOCAL ? 0x7F7Fu : LpFmt<OP>::inf_bits) << 16;
+                        if (q == 3) v.z = (SPLIT ? 0x7F7Fu : LpFmt<OP>::inf_bits) << 16;
                     }
                     cb4[((tid >> 4) * 4 + q) * 16 + (tid & 15)] = v;
                 }
@@ -653,11 +655,12 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
     // |ql - (u - qh)| <= 2^-8 |u - qh| <= 2^-16 |u| per feature, plus the
     // FP32 offset's rounding and BF16's subnormal floor.
     auto split_rows = [&](int sc) {
-      if constexpr (LOCAL && OP == OP_BF16) {
+      if constexpr (LOCAL && OP != OP_FP8) {
+        typedef LpFmt<OP> F;
         const float4* c4 = reinterpret_cast<const float4*>(a.sballs + (int64_t)sc * BALL_STRIDE) + 2 * grp;
         const float4 ca = c4[0], cb = c4[1];
         const float cv[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
-        const uint32_t one = f32_to_bf16_rn(1.0f);
+        const uint32_t one = F::to(1.0f);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             const float4* x4 = reinterpret_cast<const float4*>(a.xs + (int64_t)rprb[rb] * DMAX) + 2 * grp;
@@ -673,10 +676,14 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
                     const int f = 2 * f2 + h, kf = 8 * grp + f;
                     if (kf < DMAX_MFMA && kf < a.d) {
                         const float u = (xv[f] - cv[f]) * sigma;
-                        const uint32_t qh = f32_to_bf16_rn(u);
-                        const float qhv = bf16_to_f32((uint16_t)qh);
-                        const uint32_t ql = f32_to_bf16_rn(u - qhv);
-                        const float qlv = bf16_to_f32((uint16_t)ql);
+                        const uint32_t qh = F::to(u);
+                        const float qhv = F::from((uint16_t)qh);
+                        uint32_t ql = 0;
+                        float qlv = 0.f;
+                        if constexpr (SPLIT) {
+                            ql = F::to(u - qhv);
+                            qlv = F::from((uint16_t)ql);
+                        }
                         const float q = qhv + qlv;
                         nrm = __builtin_fmaf(q, q, nrm);
                         vn = __builtin_fmaf(u, u, vn);
@@ -703,8 +710,8 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
             uint32_t part[NORM_PARTS];
 #pragma unroll
             for (int k3 = 0; k3 < NORM_PARTS; ++k3) {
-                part[k3] = f32_to_bf16_rn(r);
-                const float pv = bf16_to_f32((uint16_t)part[k3]);
+                part[k3] = F::to(r);
+                const float pv = F::from((uint16_t)part[k3]);
                 psum += __builtin_fabsf(pv);
                 r -= pv;
             }
@@ -714,7 +721,7 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
                 hw[3] = one | (one << 16);
             }
             bfrag[rb] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-            bfl[rb] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+            if constexpr (SPLIT) bfl[rb] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
             if (grp == 0) {
                 const double up = 1.0 + 0x1p-18;
                 const double sq = (double)__builtin_sqrtf(nh) + (double)__builtin_sqrtf(nl);
@@ -722,9 +729,9 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
                     d2f_up(sq * up), d2f_up((double)psum * up),
                     // (the FP32 sums of ||q||^2 and the rounding of qh + ql
                     // where ql is subnormal: within 30 2^-24 of it)
-                    d2f_up(((double)__builtin_fabsf(r) + (double)nrm * 30.0 * 0x1p-24) * up),
-                    d2f_up(((0x1p-16 + 0x1p-22) * (double)__builtin_sqrtf(vn) * up +
-                            LpFmt<OP_BF16>::beta * __builtin_sqrt((double)a.d)) * up));
+                    d2f_up(((double)__builtin_fabsf(r) + (double)nrm * (SPLIT ? 30.0 : 27.0) * 0x1p-24) * up),
+                    d2f_up(((SPLIT ? 0x1p-16 + 0x1p-22 : F::alpha) * (double)__builtin_sqrtf(vn) * up +
+                            F::beta * __builtin_sqrt((double)a.d)) * up));
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -892,7 +899,7 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
             for (int rb = 0; rb < RB; ++rb) acc0[rb] = Tr::mma(af0, bfrag[rb]);
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc1[rb] = Tr::mma(af1, bfrag[rb]);
-            if constexpr (LOCAL) {                         // the rows' low halves
+            if constexpr (SPLIT) {                         // the rows' low halves
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) acc0[rb] = Tr::mma_acc(af0, bfl[rb], acc0[rb]);
 #pragma unroll
@@ -940,7 +947,7 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
             f32x4_t acc[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc[rb] = Tr::mma(af, bfrag[rb]);
-            if constexpr (LOCAL) {
+            if constexpr (SPLIT) {
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) acc[rb] = Tr::mma_acc(af, bfl[rb], acc[rb]);
             }
@@ -1101,19 +1108,29 @@ void launch_one(const CandArgs& a, dim3 grid, size_t, hipStream_t s)
 
 }  // namespace
 
-hipError_t launch_split_columns(const float* xs, int64_t np, int d, float sigma, const int32_t* cstart,
-                                const int32_t* csup, const int32_t* tabn, int64_t nch_bound,
-                                const float* sballs, void* opC, float4* cmax, hipStream_t s)
+template <int OP>
+void split_columns_op(const float* xs, int64_t np, int d, float sigma, const int32_t* cstart,
+                      const int32_t* csup, const int32_t* tabn, int64_t nch_bound, const float* sballs,
+                      void* opC, float4* cmax, hipStream_t s)
 {
-    if (np <= 0) return hipSuccess;
     if (cstart) {
-        k_split_columns<true><<<(unsigned)nch_bound, 256, 0, s>>>(xs, np, d, sigma, cstart, csup, tabn, sballs,
-                                                                  (uint4*)opC, cmax);
+        k_split_columns<true, OP><<<(unsigned)nch_bound, 256, 0, s>>>(xs, np, d, sigma, cstart, csup, tabn,
+                                                                      sballs, (uint4*)opC, cmax);
     } else {
         const unsigned nc = (unsigned)((np + CHUNK - 1) / CHUNK);
-        k_split_columns<false><<<nc, 256, 0, s>>>(xs, np, d, sigma, nullptr, nullptr, nullptr, sballs,
-                                                  (uint4*)opC, cmax);
+        k_split_columns<false, OP><<<nc, 256, 0, s>>>(xs, np, d, sigma, nullptr, nullptr, nullptr, sballs,
+                                                      (uint4*)opC, cmax);
     }
+}
+
+hipError_t launch_split_columns(int opkind, const float* xs, int64_t np, int d, float sigma,
+                                const int32_t* cstart, const int32_t* csup, const int32_t* tabn,
+                                int64_t nch_bound, const float* sballs, void* opC, float4* cmax,
+                                hipStream_t s)
+{
+    if (np <= 0) return hipSuccess;
+    if (opkind != OP_BF16) return hipErrorInvalidValue;   // the super-chunk frames are BF16's
+    split_columns_op<OP_BF16>(xs, np, d, sigma, cstart, csup, tabn, nch_bound, sballs, opC, cmax, s);
     return hipGetLastError();
 }
 
@@ -1131,7 +1148,10 @@ hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s)
         else launch_one<OP_BF16, false>(a, grid, shm, s);
         break;
     case OP_FP16:
-        if (local) return hipErrorInvalidValue;   // super-chunk frames are a BF16 format
+        // FP16 runs in the global frame: its super-chunk-frame variant (the
+        // same kernel, one MFMA per block) kept 2.4x fewer first-round
+        // survivors but rebuilt rows too often in the merge rounds
+        if (local) return hipErrorInvalidValue;
         launch_one<OP_FP16, false>(a, grid, shm, s);
         break;
     case OP_FP8:

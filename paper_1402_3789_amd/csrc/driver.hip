@@ -438,7 +438,7 @@ nnm_status stage(Run& R, const float* X)
     }
     // FP32 accumulation of 32 exact products (one MFMA), or of 64 in two
     // chained MFMAs (the split rows): any order, even truncating
-    R.bc.gamma = p.exact ? 0.f : (float)((p.local ? 67.0 : 33.0) * 0x1p-23);
+    R.bc.gamma = p.exact ? 0.f : (float)((p.local && p.opkind == OP_BF16 ? 67.0 : 33.0) * 0x1p-23);
     R.bc.sigma2 = sigma * sigma;
     R.bc.exact = p.exact;
     return NNM_OK;
@@ -499,7 +499,7 @@ nnm_status sort_points(Run& R, const float* X, int64_t ncomp)
     // BF16: the column operands in the frames of this order's super-chunks
     if (p.local) {
         const int64_t nch_bound = R.aligned ? (p.n + CHUNK - 1) / CHUNK + ncomp : 0;
-        HIP_TRY(launch_split_columns(w.xs, p.n, p.d, R.sigma, R.aligned ? w.tabs.cstart : nullptr,
+        HIP_TRY(launch_split_columns(p.opkind, w.xs, p.n, p.d, R.sigma, R.aligned ? w.tabs.cstart : nullptr,
                                      w.tabs.csup, w.tabs.tabn, nch_bound, w.sballs, w.opCs, w.cmaxT, R.s));
     }
     return NNM_OK;

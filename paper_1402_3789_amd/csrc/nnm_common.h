@@ -297,9 +297,10 @@ hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s);
 // the super-chunk's ball centre) and each chunk's maxima of their bound
 // inputs; cstart/csup/tabn: the component-aligned tables (NULL: fixed
 // chunks), nch_bound: at least their chunk count.
-hipError_t launch_split_columns(const float* xs, int64_t np, int d, float sigma, const int32_t* cstart,
-                                const int32_t* csup, const int32_t* tabn, int64_t nch_bound,
-                                const float* sballs, void* opC, float4* cmax, hipStream_t s);
+hipError_t launch_split_columns(int opkind, const float* xs, int64_t np, int d, float sigma,
+                                const int32_t* cstart, const int32_t* csup, const int32_t* tabn,
+                                int64_t nch_bound, const float* sballs, void* opC, float4* cmax,
+                                hipStream_t s);
 hipError_t launch_cand_fp32(const CandArgs& a, hipStream_t s);
 
 // FP64 rescoring of survivors into exact top-k lists.
