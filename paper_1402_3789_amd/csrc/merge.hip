@@ -248,20 +248,34 @@ __global__ __launch_bounds__(256) void k_break(MergeArgs a)
     if (p != c && a.parent[p] == c && c < p) a.parent[c] = (int32_t)c;
 }
 
-__global__ __launch_bounds__(256) void k_emit(MergeArgs a)
+// Workgroups of the kernels below that count into one global counter: one
+// atomic per workgroup (a per-wave atomic serialised some 30,000 waves on one
+// address in the first round).
+constexpr int AGG = 1024;
+
+// One counter atomic per workgroup; its waves take consecutive runs of slots.
+__global__ __launch_bounds__(AGG) void k_emit(MergeArgs a)
 {
+    __shared__ int wbase[AGG / 64];
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool emit = c < a.n && a.comp[c] == c && a.parent[c] != c;
-    // one counter atomic per wave; lanes take consecutive slots
     const unsigned long long m = __ballot(emit);
-    if (!m) return;
-    const int leader = (int)__builtin_ctzll(m);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&a.counters[0], (int)__popcll(m));
-    base = __shfl(base, leader);
+    if (lane == 0) wbase[wave] = (int)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < AGG / 64; ++w) {
+            const int cnt = wbase[w];
+            wbase[w] = tot;
+            tot += cnt;
+        }
+        const int base = tot > 0 ? atomicAdd(&a.counters[0], tot) : 0;
+        for (int w = 0; w < AGG / 64; ++w) wbase[w] += base;
+    }
+    __syncthreads();
     if (!emit) return;
-    const int e = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+    const int e = wbase[wave] + (int)__popcll(m & ((1ull << lane) - 1ull));
     if (e >= a.n) return;   // cannot happen: a tree has n - 1 edges
     const unsigned long long p = a.cbest_p[c];
     SortRec r;
@@ -281,15 +295,30 @@ __global__ __launch_bounds__(256) void k_jump(MergeArgs a)
     if (pp != p) a.parent[c] = pp;
 }
 
-// counters[1] = roots left, counters[2] = pointers not yet at a root.
-__global__ __launch_bounds__(256) void k_jump_check(MergeArgs a)
+// counters[1] = roots left, counters[2] = pointers not yet at a root
+// (counted per workgroup in LDS, then one atomic each).
+__global__ __launch_bounds__(AGG) void k_jump_check(MergeArgs a)
 {
-    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= a.n) return;
-    if (a.comp[c] != c) return;
-    const int p = a.parent[c];
-    if (a.parent[p] != p) atomicAdd(&a.counters[2], 1);
-    if (p == c) atomicAdd(&a.counters[1], 1);
+    __shared__ int cnt[2];
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool miss = false, root = false;
+    if (c < a.n && a.comp[c] == c) {
+        const int p = a.parent[c];
+        miss = a.parent[p] != p;
+        root = p == c;
+    }
+    const unsigned long long mm = __ballot(miss), mr = __ballot(root);
+    if ((threadIdx.x & 63) == 0) {
+        if (mm) atomicAdd(&cnt[0], (int)__popcll(mm));
+        if (mr) atomicAdd(&cnt[1], (int)__popcll(mr));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (cnt[0]) atomicAdd(&a.counters[2], cnt[0]);
+        if (cnt[1]) atomicAdd(&a.counters[1], cnt[1]);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_relabel(MergeArgs a)
@@ -329,6 +358,7 @@ __global__ __launch_bounds__(256) void k_export_knn(int64_t n, int k, const int3
 }
 
 inline unsigned g256(int64_t n) { return (unsigned)((n + 255) / 256); }
+inline unsigned gagg(int64_t n) { return (unsigned)((n + AGG - 1) / AGG); }
 
 }  // namespace
 
@@ -354,13 +384,17 @@ NNM_LAUNCH1(flag_rescan)
 NNM_LAUNCH1(compmin2)
 NNM_LAUNCH1(relabel)
 NNM_LAUNCH1(reset_comp)
-NNM_LAUNCH1(jump_check)
+hipError_t launch_jump_check(const MergeArgs& a, hipStream_t s)
+{
+    k_jump_check<<<gagg(a.n), AGG, 0, s>>>(a);
+    return hipGetLastError();
+}
 
 hipError_t launch_hook(const MergeArgs& a, hipStream_t s)
 {
     k_hook<<<g256(a.n), 256, 0, s>>>(a);
     k_break<<<g256(a.n), 256, 0, s>>>(a);
-    k_emit<<<g256(a.n), 256, 0, s>>>(a);
+    k_emit<<<gagg(a.n), AGG, 0, s>>>(a);
     return hipGetLastError();
 }
 

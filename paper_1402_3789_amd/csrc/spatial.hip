@@ -46,16 +46,19 @@ __global__ __launch_bounds__(256) void k_ckey_reset(int32_t* __restrict__ ckey, 
 
 // Visits the points in spatial order (rank q of point perm0[q] is q), so the
 // smallest rank of each run of equal components inside a wave is its first
-// lane's: one atomic per run instead of one per point.
+// lane's: one atomic per run instead of one per point.  Keys only decrease,
+// so a run whose rank is not below the key already read needs no atomic
+// (with few components left, most waves' runs fall on the same addresses).
 __global__ __launch_bounds__(256) void k_ckey_min(const int32_t* __restrict__ comp,
                                                   const int32_t* __restrict__ perm0, int64_t n,
-                                                  int32_t* __restrict__ ckey)
+                                                  int32_t* ckey)
 {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int c = q < n ? comp[perm0[q]] : -1;
     const int prev = __shfl_up(c, 1);
-    if (q < n && (lane == 0 || prev != c)) atomicMin(&ckey[c], (int32_t)q);
+    if (q < n && (lane == 0 || prev != c) && (int32_t)q < __atomic_load_n(&ckey[c], __ATOMIC_RELAXED))
+        atomicMin(&ckey[c], (int32_t)q);
 }
 
 // records in spatial order: k1 = key of the point's component, k2 = point
