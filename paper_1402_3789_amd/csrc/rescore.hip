@@ -28,10 +28,12 @@ __device__ __forceinline__ void atomic_max_pos_double(unsigned long long* p, dou
 // (kb <= k) bounds the row's kb-th key from above, so the row is
 // scanned again below that bound and gets an exact prefix of at least kb
 // neighbours (level 1).  A row that overflows again goes to the exact scan.
-template <int E>
+// W lanes serve the row (64: a wave; 32: half a wave, two rows a wave),
+// E slots each (E * W >= S).
+template <int E, int W>
 __device__ __forceinline__ void rescore_row(const RescoreArgs& a, int64_t slot, int32_t* overflow_list)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & (W - 1);
     const int rp = a.rows ? a.rows[slot] : a.row0 + (int)slot;
     const int i = a.perm[rp];
     const int cnt = a.surv_cnt[slot];
@@ -69,7 +71,7 @@ __device__ __forceinline__ void rescore_row(const RescoreArgs& a, int64_t slot, 
     for (int e = 0; e < E; ++e) {
         sv[e] = __builtin_huge_val();
         jv[e] = 0x7FFFFFFF;
-        const int idx = e * 64 + lane;
+        const int idx = e * W + lane;
         const float tv = idx < m ? a.surv_t[slot * a.S + idx] : 0.f;
         const float te = (idx < m && key_bound) ? a.surv_e[slot * a.S + idx] : 0.f;
         const bool drop = key_bound ? ((double)tv - ((double)te - (double)tv)) * a.inv_sigma2 > (double)tf
@@ -118,7 +120,7 @@ __device__ __forceinline__ void rescore_row(const RescoreArgs& a, int64_t slot, 
         double ws = bs;
         int wj = bj;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
+        for (int off = W / 2; off > 0; off >>= 1) {
             const double os = __shfl_xor(ws, off);
             const int oj = __shfl_xor(wj, off);
             if (sj_less(os, oj, ws, wj)) { ws = os; wj = oj; }
@@ -135,7 +137,7 @@ __device__ __forceinline__ void rescore_row(const RescoreArgs& a, int64_t slot, 
         ++kept;
         if (kept == kb) bound = ws;
     }
-    for (int off = 32; off > 0; off >>= 1) {
+    for (int off = W / 2; off > 0; off >>= 1) {
         const double o1 = __shfl_xor(emax, off);
         const double o2 = __shfl_xor(rmax, off);
         const double o3 = __shfl_xor(bmax, off);
@@ -175,21 +177,21 @@ __device__ __forceinline__ void rescore_row(const RescoreArgs& a, int64_t slot, 
 }
 
 // one wave per row
-template <int E>
+template <int E, int W>
 __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a, int32_t* overflow_list)
 {
-    const int64_t slot = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (slot < a.n_rows) rescore_row<E>(a, slot, overflow_list);
+    const int64_t slot = (int64_t)blockIdx.x * (256 / W) + (threadIdx.x / W);
+    if (slot < a.n_rows) rescore_row<E, W>(a, slot, overflow_list);
 }
 
 // device-sized: a fixed grid of waves strides over the launch's rows
-template <int E>
+template <int E, int W>
 __global__ __launch_bounds__(256) void k_rescore_dev(RescoreArgs a, int32_t* overflow_list)
 {
     const int64_t n = a.desc->n_rows;
-    for (int64_t slot = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); slot < n;
-         slot += (int64_t)gridDim.x * 4)
-        rescore_row<E>(a, slot, overflow_list);
+    for (int64_t slot = (int64_t)blockIdx.x * (256 / W) + (threadIdx.x / W); slot < n;
+         slot += (int64_t)gridDim.x * (256 / W))
+        rescore_row<E, W>(a, slot, overflow_list);
 }
 
 // Exact top-k of one row over every point of its instance outside its
@@ -297,11 +299,18 @@ __global__ __launch_bounds__(256) void k_fallback_dev(RescoreArgs a, const int32
 
 }  // namespace
 
+// Survivor lists of up to 256 (the global frame's cap at 2M points) are
+// served by half a wave each: most rows of the merge rounds hold a survivor
+// or two, and the row's dependent gathers, not its arithmetic, set the time,
+// so two rows a wave halve the waves that wait.
 template <int E>
 void rescore_e(const RescoreArgs& a, int32_t* overflow_list, hipStream_t s)
 {
-    if (a.desc) k_rescore_dev<E><<<2048, 256, 0, s>>>(a, overflow_list);
-    else k_rescore<E><<<(unsigned)((a.n_rows + 3) / 4), 256, 0, s>>>(a, overflow_list);
+    constexpr int W = E <= 4 ? 32 : 64;
+    constexpr int EW = E * 64 / W;
+    constexpr int RPB = 256 / W;
+    if (a.desc) k_rescore_dev<EW, W><<<2048, 256, 0, s>>>(a, overflow_list);
+    else k_rescore<EW, W><<<(unsigned)((a.n_rows + RPB - 1) / RPB), 256, 0, s>>>(a, overflow_list);
 }
 
 hipError_t launch_rescore(const RescoreArgs& a, int32_t* overflow_list, hipStream_t s)

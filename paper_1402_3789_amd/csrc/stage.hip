@@ -125,13 +125,13 @@ __global__ __launch_bounds__(256) void k_stage_operands_16(
     // the block's rows, read whole and together (row-major X: consecutive
     // threads read consecutive features), then each thread's own row from LDS
     __shared__ float tile[256 * DMAX_MFMA];
+    __shared__ float bmax[4][4];
     {
+        // 32 lanes a row (d <= 26 of them load), 8 rows a pass
         const int rows = (int)((n - b0) < 256 ? (n - b0) : 256);
-        for (int e = threadIdx.x; e < rows * d; e += 256) {
-            const int r = e / d;
-            const int f = e - r * d;
-            tile[e] = X[(b0 + r) * ld + f];
-        }
+        const int f = threadIdx.x & 31;
+        for (int r = threadIdx.x >> 5; r < rows; r += 8)
+            if (f < d) tile[r * d + f] = X[(b0 + r) * ld + f];
     }
     __syncthreads();
     const float* xrow = tile + (int)(i - b0) * d;
@@ -203,14 +203,22 @@ __global__ __launch_bounds__(256) void k_stage_operands_16(
                         LpBound<OP>::beta * __builtin_sqrt((double)d)) * (1.0 + 0x1p-40));
     }
     if (valid) pc[i] = p;
-    // column maxima: one atomic per wave and quantity (non-negative floats
-    // order as their bits)
+    // column maxima: one atomic per workgroup and quantity, skipped when the
+    // maximum already read is not smaller (non-negative floats order as
+    // their bits; maxima only grow)
     float m4[4] = {p.Q, p.P, p.rho, p.eta};
 #pragma unroll
     for (int q = 0; q < 4; ++q)
         for (int off = 32; off > 0; off >>= 1) m4[q] = fmaxf(m4[q], __shfl_xor(m4[q], off));
     if ((threadIdx.x & 63) == 0)
-        for (int q = 0; q < 4; ++q) atomicMax(&st->colmax[q], __float_as_uint(m4[q]));
+        for (int q = 0; q < 4; ++q) bmax[threadIdx.x >> 6][q] = m4[q];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        const float m = fmaxf(fmaxf(bmax[0][q], bmax[1][q]), fmaxf(bmax[2][q], bmax[3][q]));
+        const uint32_t bits = __float_as_uint(m);
+        if (bits > __atomic_load_n(&st->colmax[q], __ATOMIC_RELAXED)) atomicMax(&st->colmax[q], bits);
+    }
 }
 
 __device__ __forceinline__ uint8_t to_fp8(float f)
