@@ -443,7 +443,9 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
     __shared__ __align__(16) int32_t colcomp[2][BN];
     __shared__ float4 gcm[LOCAL ? GW : 1];                 // LOCAL: column maxima per candidate chunk
     __shared__ int32_t gsc[GS];                            // LOCAL: super-chunk of each wave's slots
-    __shared__ float4 rpc[LOCAL ? BM : 1];                 // LOCAL: rows' bound inputs, current frame
+    __shared__ float4 rpc[LOCAL ? BM : 1];                 // LOCAL: rows' (Q, ||a||^2, eta) in the tile frame
+    __shared__ float2 rpf[LOCAL ? BM : 1];                 // LOCAL: rows' (P, rho) in the current column frame
+    __shared__ __align__(16) float dlt[LOCAL ? GS : 1][DMAX + 4];   // LOCAL: each wave's offset delta, ||delta|| at [DMAX]
     __shared__ float4 rs[BM][2];                           // per-row state, see above
     __shared__ float wmx[4];                               // per-wave max of U
     __shared__ __align__(16) float wcen[4][DMAX];          // per-wave ball of the rows
@@ -531,7 +533,7 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
     }
     rs[tid][0] = make_float4(-__builtin_huge_valf(), U, 0.f, 0.f);
     rs[tid][1] = make_float4(__int_as_float(0), __int_as_float(my_comp), 0.f, 0.f);
-    if (a.prune) tile_ball<DMAX>(sh, x, my_valid, a.d);
+    if (a.prune || LOCAL) tile_ball<DMAX>(sh, x, my_valid, a.d);
     if (a.prune) wave_ball<DMAX>(&wcen[wave][0], &wrad[wave], x, my_valid, a.d);
     // row operand and its bound inputs (LOCAL: per super-chunk frame, below)
     PointConst mypc{0.f, 0.f, 0.f, 0.f};
@@ -555,9 +557,11 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
     }
     __syncthreads();                                       // the tile's shared fields are written
     // row fragments stay in registers for the whole sweep (LOCAL: both
-    // halves, rebuilt per super-chunk frame from the rows' positions)
+    // halves in the tile's frame; a column frame only rewrites their norm
+    // slots)
     // SPLIT: BF16 in the super-chunk frames keeps its rows as two halves
     constexpr bool SPLIT = LOCAL && OP == OP_BF16;
+    static_assert(!LOCAL || OP == OP_BF16, "the super-chunk frames are BF16's");
     frag_t bfrag[RB], bfl[SPLIT ? RB : 1];
     int32_t rprb[LOCAL ? RB : 1];
     int32_t rcomp[RB];
@@ -569,8 +573,6 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
         const bool ok = slot < row_end;
         const int rp = ok ? (a.rows ? a.rows[slot] : a.row0 + (int)slot) : 0;
         if constexpr (LOCAL) {
-            bfrag[rb] = frag_t{};
-            if constexpr (SPLIT) bfl[rb] = frag_t{};
             rprb[rb] = rp;
         } else {
             bfrag[rb] = reinterpret_cast<const frag_t*>(a.opR)[(int64_t)rp * 4 + grp];
@@ -604,11 +606,48 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
     // registers -> LDS buffer b, in fragment order; columns this tile never
     // pairs with (beyond the data, outside its column range, or in the
     // component of a one-component tile) get t = +inf where the format has one
-    auto stash = [&](int64_t c0, int b) {
+    //   LOCAL: a column's norm slots 29..31 are rewritten from ||p||^2 to
+    //   C = ||p||^2 - 2 delta.p for the chunk's frame offset (FP32, three
+    //   BF16 parts; see frame_rows)
+    auto stash = [&](int64_t c0, int b, int slot) {
         // (pf_cc < 0: past the chunk's end; component ids are >= 0)
         const bool col_ok = pf_cc >= 0 && c0 + tid >= cl && c0 + tid < ch &&
                             !(one_comp && pf_cc == lo_r);
         colcomp[b][tid] = col_ok ? pf_cc : -1;
+        if constexpr (LOCAL) {
+            if (col_ok) {
+                typedef LpFmt<OP> F;
+                const float4* dv4 = reinterpret_cast<const float4*>(&dlt[slot / SUPER][0]);
+                float dotp = 0.f;                          // (-2 p) . delta, eight features a quarter
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float4 da = dv4[2 * q], db = dv4[2 * q + 1];
+                    const float dq[8] = {da.x, da.y, da.z, da.w, db.x, db.y, db.z, db.w};
+                    const uint32_t wq[4] = {pf[q].x, pf[q].y, pf[q].z, pf[q].w};
+#pragma unroll
+                    for (int f = 0; f < 8; ++f) {
+                        const int kf = 8 * q + f;
+                        if (kf < DMAX_MFMA && kf < a.d) {
+                            const uint32_t wv = wq[f >> 1];
+                            const float m2p = __uint_as_float((f & 1) ? (wv & 0xFFFF0000u) : (wv << 16));
+                            dotp = __builtin_fmaf(m2p, dq[f], dotp);
+                        }
+                    }
+                }
+                // slots 29, 30, 31: the parts of ||p||^2
+                const float normp = (__uint_as_float(pf[3].z & 0xFFFF0000u) + __uint_as_float(pf[3].w << 16)) +
+                                    __uint_as_float(pf[3].w & 0xFFFF0000u);
+                float r = normp + dotp;
+                uint32_t part[NORM_PARTS];
+#pragma unroll
+                for (int k3 = 0; k3 < NORM_PARTS; ++k3) {
+                    part[k3] = F::to(r);
+                    r -= F::from((uint16_t)part[k3]);
+                }
+                pf[3].z = (pf[3].z & 0xFFFFu) | (part[0] << 16);
+                pf[3].w = part[1] | (part[2] << 16);
+            }
+        }
         if constexpr (Tr::BYTES == 64) {
             uint4* cb4 = reinterpret_cast<uint4*>(&colbuf[b][0]);
             if (__ballot(!col_ok) == 0ull) {               // the usual case: copies only
@@ -641,29 +680,26 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
         }
     };
 
-    // chunk [c0, cend) in LDS buffer b, components lo_c..hi_c; wneed: some
-    // row of this wave passed its test for the chunk (else nothing to do)
-    // LOCAL: the wave's rows in the frame of super-chunk sc, centred at its
-    // ball centre c.  Lane l builds, for every row block rb, K slots 8g..8g+7
-    // (g = l / 16) of row rb * 16 + l % 16 -- its own B fragments -- for both
-    // halves of q = qh + ql: u = sigma (x - c) in FP32, qh = bf16(u),
-    // ql = bf16(u - qh) (the difference is exact in FP32, and qh + ql too).
-    // The high half carries the norm slots [n1 n2 n3 1 1 1] of ||q||^2, the
-    // low half zeros there.  The row's bound inputs go to rpc: Q = ||qh|| +
-    // ||ql|| (the two MFMAs' products sum to at most 2 Q Q* + P + P* in
-    // magnitude), P and rho as for any operand, and eta from
-    // |ql - (u - qh)| <= 2^-8 |u - qh| <= 2^-16 |u| per feature, plus the
-    // FP32 offset's rounding and BF16's subnormal floor.
-    auto split_rows = [&](int sc) {
-      if constexpr (LOCAL && OP != OP_FP8) {
+    // LOCAL: the rows in their tile's frame (centre c_T = the tile ball's
+    // centre), split once.  Lane l builds, for every row block rb, K slots
+    // 8g..8g+7 (g = l / 16) of row rb * 16 + l % 16 -- its own B fragments --
+    // for both halves of a = ah + al: u = sigma (x - c_T) in FP32,
+    // ah = bf16(u), al = bf16(u - ah) (the difference is exact in FP32, and
+    // ah + al too).  The norm slots stay for the column frames (the high
+    // half's ones are set here, its parts per frame; the low half holds
+    // zeros there).  Per row, into rpc: Q = ||ah|| + ||al||, ||a||^2 (FP32),
+    // and eta from |al - (u - ah)| <= 2^-8 |u - ah| <= 2^-16 |u| per feature,
+    // plus the FP32 offset's rounding and BF16's subnormal floor.
+    auto tile_split = [&](const int (&rp)[RB]) {
+      if constexpr (LOCAL) {
         typedef LpFmt<OP> F;
-        const float4* c4 = reinterpret_cast<const float4*>(a.sballs + (int64_t)sc * BALL_STRIDE) + 2 * grp;
+        const float4* c4 = reinterpret_cast<const float4*>(sh.cen) + 2 * grp;
         const float4 ca = c4[0], cb = c4[1];
         const float cv[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
         const uint32_t one = F::to(1.0f);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            const float4* x4 = reinterpret_cast<const float4*>(a.xs + (int64_t)rprb[rb] * DMAX) + 2 * grp;
+            const float4* x4 = reinterpret_cast<const float4*>(a.xs + (int64_t)rp[rb] * DMAX) + 2 * grp;
             const float4 xa = x4[0], xb = x4[1];
             const float xv[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
             uint32_t hw[4], lw[4];
@@ -678,12 +714,8 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
                         const float u = (xv[f] - cv[f]) * sigma;
                         const uint32_t qh = F::to(u);
                         const float qhv = F::from((uint16_t)qh);
-                        uint32_t ql = 0;
-                        float qlv = 0.f;
-                        if constexpr (SPLIT) {
-                            ql = F::to(u - qhv);
-                            qlv = F::from((uint16_t)ql);
-                        }
+                        const uint32_t ql = F::to(u - qhv);
+                        const float qlv = F::from((uint16_t)ql);
                         const float q = qhv + qlv;
                         nrm = __builtin_fmaf(q, q, nrm);
                         vn = __builtin_fmaf(u, u, vn);
@@ -705,8 +737,70 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
             vn += __shfl_xor(vn, 32);
             nh += __shfl_xor(nh, 32);
             nl += __shfl_xor(nl, 32);
-            // three-part split of ||q||^2; every residual is exact in FP32
-            float r = nrm, psum = 0.f;
+            if (grp == 3) {                                // slots 24..31: features 24, 25, norm slots
+                hw[1] = 0;                                 // parts 1, 2: per frame
+                hw[2] = one << 16;                         // part 3: per frame; slot 29: 1
+                hw[3] = one | (one << 16);
+            }
+            bfrag[rb] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            bfl[rb] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+            if (grp == 0) {
+                const double up = 1.0 + 0x1p-18;
+                const double sq = (double)__builtin_sqrtf(nh) + (double)__builtin_sqrtf(nl);
+                rpc[wave * RB * 16 + rb * 16 + lane] = make_float4(
+                    d2f_up(sq * up), nrm,
+                    d2f_up(((0x1p-16 + 0x1p-22) * (double)__builtin_sqrtf(vn) * up +
+                            F::beta * __builtin_sqrt((double)a.d)) * up), 0.f);
+            }
+        }
+      }
+    };
+
+    // LOCAL: the rows' norm slots in the frame of the column super-chunk
+    // whose offset is dlt[w] (delta = sigma (c_T - c_S), FP32): with a the
+    // row in its tile's frame and p a column in its super-chunk's, the pair's
+    // t = ||a + delta||^2 + ||p||^2 - 2 a.p - 2 delta.p, so the row's slots
+    // carry R = ||a||^2 + 2 a.delta + ||delta||^2 (FP32: each dot product
+    // within 10 roundings, the sums within two more) as three BF16 parts and
+    // the columns' slots carry ||p||^2 - 2 delta.p (rewritten when staged).
+    // Per row into rpf: P = sum of |parts|, rho = residual + 30 2^-24 (||a||^2
+    // + 2 Q ||delta|| + ||delta||^2); eta grows by 2^-22 ||delta|| (the FP32
+    // rounding of delta moves the represented row).
+    auto frame_rows = [&](int w) {
+      if constexpr (LOCAL) {
+        typedef LpFmt<OP> F;
+        const float dn = dlt[w][DMAX];
+        float dv[8];
+#pragma unroll
+        for (int f = 0; f < 8; ++f) dv[f] = dlt[w][8 * grp + f];   // zero beyond the data's features
+        float dd = 0.f;
+#pragma unroll
+        for (int f = 0; f < 8; ++f) dd = __builtin_fmaf(dv[f], dv[f], dd);
+        dd += __shfl_xor(dd, 16);
+        dd += __shfl_xor(dd, 32);
+        const uint32_t one = F::to(1.0f);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            // a . delta over the lane's eight features, read in place
+            auto half = [](uint32_t w, int h) { return __uint_as_float(h ? (w & 0xFFFF0000u) : (w << 16)); };
+            float dot = 0.f;
+#pragma unroll
+            for (int f = 0; f < 8; ++f) {
+                const int kf = 8 * grp + f;
+                if (kf < DMAX_MFMA && kf < a.d) {
+                    const uint32_t wh = (f >> 1) == 0 ? bfrag[rb].x : (f >> 1) == 1 ? bfrag[rb].y
+                                      : (f >> 1) == 2 ? bfrag[rb].z : bfrag[rb].w;
+                    const uint32_t wl = (f >> 1) == 0 ? bfl[rb].x : (f >> 1) == 1 ? bfl[rb].y
+                                      : (f >> 1) == 2 ? bfl[rb].z : bfl[rb].w;
+                    dot = __builtin_fmaf(half(wh, f & 1) + half(wl, f & 1), dv[f], dot);
+                }
+            }
+            dot += __shfl_xor(dot, 16);
+            dot += __shfl_xor(dot, 32);
+            const int row = wave * RB * 16 + rb * 16 + (lane & 15);
+            const float4 rc = rpc[row];                    // Q, ||a||^2, eta
+            const float R = (rc.y + 2.f * dot) + dd;
+            float r = R, psum = 0.f;
             uint32_t part[NORM_PARTS];
 #pragma unroll
             for (int k3 = 0; k3 < NORM_PARTS; ++k3) {
@@ -715,32 +809,27 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
                 psum += __builtin_fabsf(pv);
                 r -= pv;
             }
-            if (grp == 3) {                                // slots 24..31: features 24, 25, norm slots
-                hw[1] = part[0] | (part[1] << 16);
-                hw[2] = part[2] | (one << 16);
-                hw[3] = one | (one << 16);
+            if (grp == 3) {                                // slots 26, 27 and 28
+                bfrag[rb].y = part[0] | (part[1] << 16);
+                bfrag[rb].z = part[2] | (one << 16);
             }
-            bfrag[rb] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-            if constexpr (SPLIT) bfl[rb] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
             if (grp == 0) {
                 const double up = 1.0 + 0x1p-18;
-                const double sq = (double)__builtin_sqrtf(nh) + (double)__builtin_sqrtf(nl);
-                rpc[wave * RB * 16 + rb * 16 + lane] = make_float4(
-                    d2f_up(sq * up), d2f_up((double)psum * up),
-                    // (the FP32 sums of ||q||^2 and the rounding of qh + ql
-                    // where ql is subnormal: within 30 2^-24 of it)
-                    d2f_up(((double)__builtin_fabsf(r) + (double)nrm * (SPLIT ? 30.0 : 27.0) * 0x1p-24) * up),
-                    d2f_up(((SPLIT ? 0x1p-16 + 0x1p-22 : F::alpha) * (double)__builtin_sqrtf(vn) * up +
-                            F::beta * __builtin_sqrt((double)a.d)) * up));
+                rpf[row] = make_float2(
+                    d2f_up((double)psum * up),
+                    d2f_up(((double)__builtin_fabsf(r) +
+                            30.0 * 0x1p-24 * ((double)rc.y + 2.0 * (double)rc.x * (double)dn + (double)dd)) * up));
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const float4 m = rpc[tid];
-        mypc = PointConst{m.x, m.y, m.z, m.w};
+        const float4 rc = rpc[tid];
+        const float2 rf = rpf[tid];
+        mypc = PointConst{rc.x, rf.x, rf.y, d2f_up(((double)rc.z + 0x1p-22 * (double)dn) * (1.0 + 0x1p-18))};
       }
     };
+    if constexpr (LOCAL) tile_split(rprb);
 
     // chunk [c0, cend) in LDS buffer b, components lo_c..hi_c, candidate slot
     // `slot`; wneed: some row of this wave passed its test for the chunk
@@ -755,13 +844,21 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
         // the slack is fixed and T follows U wherever U moves, so nothing is
         // recomputed per chunk.
         if constexpr (LOCAL) {
-            const int fsc = gsc[slot / SUPER];
+            const int fw = slot / SUPER;
+            const int fsc = gsc[fw];
             if (fsc != frame) {                            // wave-uniform
-                split_rows(fsc);
+                frame_rows(fw);
                 frame = fsc;
             }
-            const float4 cm = gcm[slot];                   // column maxima of Q, P, rho, eta
-            const float eps = (a.bc.gamma * (2.f * mypc.Q * cm.x + mypc.P + cm.y) + mypc.rho + cm.z) *
+            // the chunk's columns: maxima of Q, (P), rho, eta in their own
+            // frame; their rewritten norm slots carry |C| <= Q*^2 + rho* +
+            // 2 Q* ||delta|| (P: parts within 2^-6 of it) with FP32 error
+            // within 32 2^-24 of it beyond rho*
+            const float4 cm = gcm[slot];
+            const float mag = (cm.x * cm.x + cm.z + 2.f * cm.x * dlt[fw][DMAX]) * (1.f + 0x1p-18f);
+            const float Ps = mag * (1.f + 0x1p-6f);
+            const float rhoS = (cm.z + 32.f * 0x1p-24f * mag) * (1.f + 0x1p-18f);
+            const float eps = (a.bc.gamma * (2.f * mypc.Q * cm.x + mypc.P + Ps) + mypc.rho + rhoS) *
                               (1.f + 0x1p-20f);
             const float eta = (mypc.eta + cm.w) * (1.f + 0x1p-22f);
             rs[tid][0].z = eps;
@@ -990,6 +1087,20 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
         }
         gen.expand(sh, a, lo_r, hi_r, umax, wave < g ? scl[wave < GS ? wave : 0] : -1, wave, gball, gpos,
                    gneed, LOCAL ? gcm : nullptr, gsc);
+        if constexpr (LOCAL) {
+            // the offset delta = sigma (c_T - c_S) of this wave's super-chunk
+            // (FP32; zero beyond the data's features) and ||delta|| rounded up
+            const int scw = wave < g ? scl[wave < GS ? wave : 0] : -1;
+            if (scw >= 0) {
+                float dk = 0.f;
+                if (lane < a.d && lane < DMAX_MFMA)
+                    dk = (sh.cen[lane] - a.sballs[(int64_t)scw * BALL_STRIDE + lane]) * sigma;
+                if (lane < DMAX) dlt[wave][lane] = dk;
+                float sq = dk * dk;
+                for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+                if (lane == 0) dlt[wave][DMAX] = d2f_up((double)__builtin_sqrtf(sq) * (1.0 + 0x1p-18));
+            }
+        }
         __syncthreads();                                   // candidates in LDS
         // candidates within reach of this wave's ball (one per lane), then
         // the rows' own tests for those
@@ -1026,7 +1137,7 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
         while (cur >= 0) {
             const int4 cp = gpos[cur];
             const bool wn = ((__builtin_amdgcn_readlane(gn, cur) >> wave) & 1) != 0;
-            stash(cp.x, buf);
+            stash(cp.x, buf, cur);
             __syncthreads();    // chunk cur in LDS; every wave is done with buf ^ 1's last use
             // bounds found by the other column splits of the row (loaded with
             // the chunk now in LDS, so nothing waits here)

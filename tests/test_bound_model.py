@@ -206,3 +206,109 @@ def test_split_representation_error():
     # and the single BF16 rounding is within 2^-8 (the columns' alpha)
     e1 = np.abs(qh.astype(np.float64) - u.astype(np.float64))
     assert np.all(e1 <= 2.0 ** -8 * np.abs(u.astype(np.float64)) + 2.0 ** -134)
+
+
+# ---- rows in their tile's frame, columns in their super-chunk's frame ------
+#
+# The rows are split once in the frame of their tile's centre c_T
+# (a = ah + al of sigma (x - c_T)); a column super-chunk's frame (centre
+# c_S) enters through the offset delta = sigma (c_T - c_S) in FP32:
+#   t = ||a + delta||^2 + ||p||^2 - 2 a.p - 2 delta.p,
+# the row's norm slots carry R = ||a||^2 + 2 a.delta + ||delta||^2 and the
+# column's C = ||p||^2 - 2 delta.p, each evaluated in FP32 and split into
+# three BF16 parts.  Bound inputs: Q_i = ||ah|| + ||al||, Q_j = ||p||;
+# P and rho of the rewritten slots from the FP32 error of R and C:
+#   rho_R <= 30 u (||a||^2 + 2 Q_i ||delta|| + ||delta||^2) + |residual|,
+#   rho_C <= rho_p + 30 u (||p||^2 + 2 Q_j ||delta||) + |residual|,
+# and the represented row point moves by at most 2^-22 ||delta|| (the FP32
+# rounding of delta), added to eta_i.
+
+U32 = 2.0 ** -24
+
+
+def f32_dot_fma(x, y):
+    """sum_k x_k y_k with one FP32 rounding per step (fused multiply-add)."""
+    acc = np.float32(0.0)
+    for a, b in zip(np.asarray(x, np.float64), np.asarray(y, np.float64)):
+        acc = np.float32(np.float64(acc) + a * b)
+    return acc
+
+
+def tile_rows(u, d):
+    """Split rows of the tile frame: halves, ||a||^2 (FP32), Q, eta."""
+    ah = bf16(u)
+    al = bf16(np.float32(u - ah))
+    a = np.float32(ah + al)
+    nA = f32_dot_fma(a, a)
+    Q = (math.sqrt(float(np.sum(np.asarray(ah, np.float64) ** 2))) +
+         math.sqrt(float(np.sum(np.asarray(al, np.float64) ** 2)))) * UP
+    eta = ((2.0 ** -16 + 2.0 ** -22) * math.sqrt(float(np.sum(np.asarray(u, np.float64) ** 2))) * UP
+           + BETA * math.sqrt(d)) * UP
+    return ah, al, a, nA, Q, eta
+
+
+def frame_row(a, nA, Q, eta, delta, dn):
+    """The row's norm slots in a column frame: parts of R, P, rho, eta."""
+    dot = f32_dot_fma(a, delta)
+    dd = f32_dot_fma(delta, delta)
+    R = np.float32(np.float32(nA + np.float32(2.0 * dot)) + dd)
+    parts, res = norm_parts(R)
+    P = sum(abs(x) for x in parts) * UP
+    rho = (abs(res) + 30.0 * U32 * (float(nA) + 2.0 * Q * dn + float(dd))) * UP
+    return parts, (Q, P, rho, (eta + 2.0 ** -22 * dn) * UP)
+
+
+def frame_col(p, nrm_parts, rho_p, Qp, delta, dn):
+    """The column's norm slots in the row tile's frame: parts of C."""
+    normP = np.float32(np.float32(nrm_parts[0] + nrm_parts[1]) + nrm_parts[2])
+    dotP = f32_dot_fma(np.float32(-2.0) * p, delta)
+    C = np.float32(normP + dotP)
+    parts, res = norm_parts(C)
+    P = sum(abs(x) for x in parts) * UP
+    rho = (rho_p + abs(res) + 30.0 * U32 * (float(normP) + 2.0 * Qp * dn)) * UP
+    return parts, P, rho
+
+
+@pytest.mark.parametrize("d", [4, 25, 26])
+@pytest.mark.parametrize("order", list(ORDERS))
+def test_offset_frames_bound_holds(d, order):
+    rng = np.random.default_rng(7000 + 10 * d + len(order))
+    worst = 0.0
+    for trial in range(5):
+        spread = float(rng.choice([0.002, 0.02, 0.2]))
+        c_row = rng.uniform(0.0, 1.0, d).astype(np.float32)
+        c_col = (c_row + rng.normal(0.0, float(rng.choice([0.0, 0.05, 0.5])), d)).astype(np.float32)
+        rows = (c_row + rng.normal(0.0, spread, (16, d))).astype(np.float32)
+        cols = (c_col + rng.normal(0.0, spread, (24, d))).astype(np.float32)
+        c_T = rows.mean(axis=0).astype(np.float32)
+        c_S = cols.mean(axis=0).astype(np.float32)
+        span = float(np.max(np.abs(np.concatenate([rows, cols]) - 0.5)))
+        sigma = np.float32(2.0 ** -math.frexp(span)[1])
+        ur = ((rows - c_T).astype(np.float32) * sigma).astype(np.float32)
+        uc = ((cols - c_S).astype(np.float32) * sigma).astype(np.float32)
+        delta = ((c_T - c_S).astype(np.float32) * sigma).astype(np.float32)
+        dn = math.sqrt(float(np.sum(np.asarray(delta, np.float64) ** 2))) * UP
+        C = [col_operand(uc[j], d) for j in range(len(cols))]
+        # the chunk's maxima as the kernel keeps them, and the bounds it
+        # derives from them for the rewritten column slots
+        Qs = max(c[2][0] for c in C)
+        rhos = max(c[2][2] for c in C)
+        etas = max(c[2][3] for c in C)
+        mag = Qs * Qs + rhos + 2.0 * Qs * dn
+        Ps = mag * (1.0 + 2.0 ** -6)
+        rhoS = (rhos + 32.0 * U32 * mag) * UP
+        for i in range(len(rows)):
+            ah, al, a, nA, Qi, etai = tile_rows(ur[i], d)
+            rparts, ri = frame_row(a, nA, Qi, etai, delta, dn)
+            for j in range(len(cols)):
+                p, cparts0, (Qj, Pj0, rhoj0, etaj) = C[j]
+                cparts, Pj, rhoj = frame_col(p, cparts0, rhoj0, Qj, delta, dn)
+                assert Pj <= Ps and rhoj <= rhoS, (Pj, Ps, rhoj, rhoS)
+                t = candidate(ah, al, rparts, p, cparts, ORDERS[order])
+                diff = rows[i].astype(np.float64) - cols[j].astype(np.float64)
+                s = float(np.dot(diff, diff)) * float(sigma) ** 2
+                E = bound(t, ri, (Qs, Ps, rhoS, etas))
+                err = abs(t - s)
+                assert err <= E, (trial, i, j, t, s, err, E)
+                worst = max(worst, err / E)
+    assert worst > 1e-3, worst
