@@ -561,7 +561,7 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
     // slots)
     // SPLIT: BF16 in the super-chunk frames keeps its rows as two halves
     constexpr bool SPLIT = LOCAL && OP == OP_BF16;
-    static_assert(!LOCAL || OP == OP_BF16, "the super-chunk frames are BF16's");
+    static_assert(!LOCAL || OP != OP_FP8, "the super-chunk frames take BF16 or FP16 operands");
     frag_t bfrag[RB], bfl[SPLIT ? RB : 1];
     int32_t rprb[LOCAL ? RB : 1];
     int32_t rcomp[RB];
@@ -629,14 +629,14 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
                         const int kf = 8 * q + f;
                         if (kf < DMAX_MFMA && kf < a.d) {
                             const uint32_t wv = wq[f >> 1];
-                            const float m2p = __uint_as_float((f & 1) ? (wv & 0xFFFF0000u) : (wv << 16));
+                            const float m2p = F::from((uint16_t)((f & 1) ? (wv >> 16) : (wv & 0xFFFFu)));
                             dotp = __builtin_fmaf(m2p, dq[f], dotp);
                         }
                     }
                 }
                 // slots 29, 30, 31: the parts of ||p||^2
-                const float normp = (__uint_as_float(pf[3].z & 0xFFFF0000u) + __uint_as_float(pf[3].w << 16)) +
-                                    __uint_as_float(pf[3].w & 0xFFFF0000u);
+                const float normp = (F::from((uint16_t)(pf[3].z >> 16)) + F::from((uint16_t)(pf[3].w & 0xFFFFu))) +
+                                    F::from((uint16_t)(pf[3].w >> 16));
                 float r = normp + dotp;
                 uint32_t part[NORM_PARTS];
 #pragma unroll
@@ -714,8 +714,12 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
                         const float u = (xv[f] - cv[f]) * sigma;
                         const uint32_t qh = F::to(u);
                         const float qhv = F::from((uint16_t)qh);
-                        const uint32_t ql = F::to(u - qhv);
-                        const float qlv = F::from((uint16_t)ql);
+                        uint32_t ql = 0;
+                        float qlv = 0.f;
+                        if constexpr (SPLIT) {
+                            ql = F::to(u - qhv);
+                            qlv = F::from((uint16_t)ql);
+                        }
                         const float q = qhv + qlv;
                         nrm = __builtin_fmaf(q, q, nrm);
                         vn = __builtin_fmaf(u, u, vn);
@@ -743,13 +747,15 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
                 hw[3] = one | (one << 16);
             }
             bfrag[rb] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-            bfl[rb] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+            if constexpr (SPLIT) bfl[rb] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
             if (grp == 0) {
                 const double up = 1.0 + 0x1p-18;
                 const double sq = (double)__builtin_sqrtf(nh) + (double)__builtin_sqrtf(nl);
+                // split rows: |a - u| <= 2^-16 |u|; one half: the format's roundoff
+                const double alpha = SPLIT ? 0x1p-16 + 0x1p-22 : F::alpha;
                 rpc[wave * RB * 16 + rb * 16 + lane] = make_float4(
                     d2f_up(sq * up), nrm,
-                    d2f_up(((0x1p-16 + 0x1p-22) * (double)__builtin_sqrtf(vn) * up +
+                    d2f_up((alpha * (double)__builtin_sqrtf(vn) * up +
                             F::beta * __builtin_sqrt((double)a.d)) * up), 0.f);
             }
         }
@@ -782,7 +788,7 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             // a . delta over the lane's eight features, read in place
-            auto half = [](uint32_t w, int h) { return __uint_as_float(h ? (w & 0xFFFF0000u) : (w << 16)); };
+            auto half = [](uint32_t w, int h) { return F::from((uint16_t)(h ? (w >> 16) : (w & 0xFFFFu))); };
             float dot = 0.f;
 #pragma unroll
             for (int f = 0; f < 8; ++f) {
@@ -790,9 +796,13 @@ __device__ __forceinline__ void cand_mfma_item(const CandArgs& a, const Item& it
                 if (kf < DMAX_MFMA && kf < a.d) {
                     const uint32_t wh = (f >> 1) == 0 ? bfrag[rb].x : (f >> 1) == 1 ? bfrag[rb].y
                                       : (f >> 1) == 2 ? bfrag[rb].z : bfrag[rb].w;
-                    const uint32_t wl = (f >> 1) == 0 ? bfl[rb].x : (f >> 1) == 1 ? bfl[rb].y
-                                      : (f >> 1) == 2 ? bfl[rb].z : bfl[rb].w;
-                    dot = __builtin_fmaf(half(wh, f & 1) + half(wl, f & 1), dv[f], dot);
+                    float av = half(wh, f & 1);
+                    if constexpr (SPLIT) {
+                        const uint32_t wl = (f >> 1) == 0 ? bfl[rb].x : (f >> 1) == 1 ? bfl[rb].y
+                                          : (f >> 1) == 2 ? bfl[rb].z : bfl[rb].w;
+                        av += half(wl, f & 1);
+                    }
+                    dot = __builtin_fmaf(av, dv[f], dot);
                 }
             }
             dot += __shfl_xor(dot, 16);
@@ -1259,9 +1269,10 @@ hipError_t launch_cand_mfma(int opkind, const CandArgs& a, hipStream_t s)
         else launch_one<OP_BF16, false>(a, grid, shm, s);
         break;
     case OP_FP16:
-        // FP16 runs in the global frame: its super-chunk-frame variant (the
-        // same kernel, one MFMA per block) kept 2.4x fewer first-round
-        // survivors but rebuilt rows too often in the merge rounds
+        // FP16 runs in the global frame: in the super-chunk frames (one MFMA
+        // per block) it kept 2.7x fewer first-round survivors but the per-chunk
+        // thresholds and slot rewrites cost more in the merge rounds (2M
+        // workload: 114 against 96 ms)
         if (local) return hipErrorInvalidValue;
         launch_one<OP_FP16, false>(a, grid, shm, s);
         break;
