@@ -16,14 +16,16 @@
 //
 // Frame.  FP16 on general data, and exact integer data (FP8, or BF16/FP16 on
 // integer grids), use precomputed operands in one global frame.  BF16 on
-// general data (8 significant bits) uses the frame of each column
-// super-chunk, centred at that super-chunk's ball centre: the column
+// general data (8 significant bits) uses two frames per pair: the column
 // operands are built once per round in the frame of their own super-chunk
-// (k_split_columns), and a wave re-expresses its rows in a super-chunk's
-// frame when it starts on that super-chunk's chunks, as a sum of two BF16
-// values (q = qh + ql, both multiplied in by two chained MFMAs).  The
-// column error then scales with the super-chunk's radius and the row error
-// is ~2^-16 of the row's distance from the centre.
+// (k_split_columns, centre c_S = the super-chunk's ball centre), and the
+// rows once per tile in the frame of the tile's centre c_T, as a sum of two
+// BF16 values (a = ah + al, both multiplied in by two chained MFMAs).  The
+// frames meet through delta = sigma (c_T - c_S): the rows' norm slots carry
+// ||a + delta||^2 (rewritten when a wave moves to another super-chunk) and
+// the columns' ||p||^2 - 2 delta.p (rewritten when staged).  The column
+// error then scales with the super-chunk's radius and the row error is
+// ~2^-16 of the row's offset from its tile's centre.
 //
 // Selection.  For every column that reaches the slow path the proven error
 // bound gives an upper bound on its exact key; each row keeps, in LDS, the k
